@@ -1,0 +1,348 @@
+"""Pins of the FP64 CPU oracle against facts fixed outside it.
+
+Each test checks the oracle against something it does not compute itself:
+closed-form worked examples in exact rationals (verified here by exact
+identities), LAPACK's R and tau (same sign convention), exact rational normal
+equations on tiny inputs, and the Householder invariants with the tolerances
+50*n*u.  A plausible slip in the oracle (a dropped term, a wrong sign, an
+off-by-one row, a reversed reflector order) fails at least one of them, which
+``test_planted_mistakes`` demonstrates on mutated copies of the oracle source.
+"""
+import os
+import shutil
+import subprocess
+import ctypes
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2506_09463_amd import workloads
+
+U = 2.0 ** -53
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ----------------------------------------------------------------- fixtures
+def _parse_matrix(txt):
+    rows = [r.split() for r in txt.split(";")]
+    return [[Fraction(v) for v in r] for r in rows]
+
+
+def load_worked_examples():
+    cases = {}
+    cur = None
+    with open(os.path.join(HERE, "golden", "worked_examples.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("case "):
+                cur = {}
+                cases[line.split()[1]] = cur
+                continue
+            key, val = [t.strip() for t in line.split("=", 1)]
+            cur[key] = _parse_matrix(val)
+    return cases
+
+
+CASES = load_worked_examples()
+
+
+def _col(mat):
+    return [r[0] for r in mat]
+
+
+def _mm(A, B):
+    return [[sum(A[i][k] * B[k][j] for k in range(len(B))) for j in range(len(B[0]))]
+            for i in range(len(A))]
+
+
+def _t(A):
+    return [list(r) for r in zip(*A)]
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_worked_example_fixture_is_exact(name):
+    """The fixture itself satisfies the exact identities of a QR LSQ solve."""
+    c = CASES[name]
+    A, F = c["A"], c["F"]
+    m, n = len(A), len(A[0])
+    R = [[F[i][j] if j >= i else Fraction(0) for j in range(n)] for i in range(n)]
+    # R^T R = A^T A  (Q orthogonal)
+    assert _mm(_t(R), R) == _mm(_t(A), A)
+    b, qtb, x = _col(c["b"]), _col(c["qtb"]), _col(c["x"])
+    # ||Q^T b|| = ||b||
+    assert sum(v * v for v in qtb) == sum(v * v for v in b)
+    # R x = (Q^T b)[0:n]
+    assert [sum(R[i][j] * x[j] for j in range(n)) for i in range(n)] == qtb[:n]
+    # A^T A x = A^T b
+    AtA, Atb = _mm(_t(A), A), [sum(A[i][j] * b[i] for i in range(m)) for j in range(n)]
+    assert [sum(AtA[i][j] * x[j] for j in range(n)) for i in range(n)] == Atb
+    # ||b - A x||^2 = resnorm^2 = ||(Q^T b)[n:m]||^2
+    r = [b[i] - sum(A[i][j] * x[j] for j in range(n)) for i in range(m)]
+    rn = c["resnorm"][0][0]
+    assert sum(v * v for v in r) == rn * rn == sum(v * v for v in qtb[n:])
+    # reflector k: ||v_k||^2 = -2 b_k with v_k = (up_k, tail), b_k = up_k R_kk
+    up = c["up"][0]
+    for k in range(n):
+        if up[k] == 0:
+            continue
+        v2 = up[k] ** 2 + sum(F[i][k] ** 2 for i in range(k + 1, m))
+        assert v2 == -2 * up[k] * F[k][k]
+        # sign rule: R_kk has the opposite sign of the pivot x_0 = up + R_kk
+        assert F[k][k] * (up[k] + F[k][k]) <= 0
+
+
+def _close(a, b, scale, ulps=8):
+    return abs(float(a) - float(b)) <= ulps * U * max(1.0, float(scale))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_oracle_matches_worked_example(oracle_mod, name):
+    c = CASES[name]
+    A = np.array([[float(v) for v in r] for r in c["A"]])
+    m, n = A.shape
+    b = np.array([float(v) for v in _col(c["b"])])
+    F, up = oracle_mod.qr_factor(A)
+    for i in range(m):
+        for j in range(n):
+            assert _close(F[i, j], c["F"][i][j], 20), (i, j, F[i, j])
+    for k in range(n):
+        assert _close(up[k], c["up"][0][k], 20)
+    qtb = oracle_mod.apply_qt(F, up, b)[:, 0]
+    for i in range(m):
+        assert _close(qtb[i], _col(c["qtb"])[i], 4)
+    x, F2, up2, res, info = oracle_mod.lsq_solve(A, b)
+    assert info == 0
+    for j in range(n):
+        assert _close(x[j, 0], _col(c["x"])[j], 4)
+    assert _close(res[0], c["resnorm"][0][0], 4)
+
+
+# --------------------------------------------------------- library agreement
+SHAPES = [(1, 1), (2, 1), (5, 5), (7, 3), (40, 17), (64, 64), (130, 65)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_R_matches_lapack(oracle_mod, m, n):
+    """Same sign convention as LAPACK's reflector generator: R agrees with signs."""
+    A = workloads.gaussian(m, n, seed=100 + m + n)
+    F, up = oracle_mod.qr_factor(A)
+    R = np.linalg.qr(A, mode="r")
+    tol = 50 * n * U * np.linalg.norm(A, 2) * max(1.0, np.linalg.cond(A))
+    assert np.abs(np.triu(F[:n]) - R).max() <= tol
+
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_reflectors_match_lapack_geqrf(oracle_mod, m, n):
+    """LAPACK form: v = (1, tail/up), tau = -up/R_kk."""
+    torch = pytest.importorskip("torch")
+    A = workloads.gaussian(m, n, seed=200 + m + n)
+    F, up = oracle_mod.qr_factor(A)
+    a, tau = torch.geqrf(torch.from_numpy(np.array(A)))
+    a, tau = a.numpy(), tau.numpy()
+    for k in range(n):
+        if up[k] == 0.0:
+            assert tau[k] == 0.0
+            continue
+        assert abs(tau[k] - (-up[k] / F[k, k])) <= 1e3 * U * max(1.0, abs(tau[k]))
+        tail = F[k + 1:, k] / up[k]
+        assert np.allclose(tail, a[k + 1:, k], rtol=1e-11, atol=1e-12)
+
+
+# ------------------------------------------------------------ invariants
+@pytest.mark.parametrize("m,n", [(3, 3), (50, 20), (128, 64), (96, 96), (200, 1)])
+def test_householder_invariants(oracle_mod, m, n):
+    A = workloads.gaussian(m, n, seed=300 + m * 7 + n)
+    F, up = oracle_mod.qr_factor(A)
+    Q = oracle_mod.form_q(F, up)                    # m x m
+    R = np.zeros((m, n))
+    R[:n] = np.triu(F[:n])
+    bound = 50 * n * U
+    assert np.linalg.norm(A - Q @ R) / np.linalg.norm(A) <= bound
+    assert np.linalg.norm(Q.T @ Q - np.eye(m)) <= 50 * max(n, 1) * U * np.sqrt(m)
+    # Q^T applied with the transposed order gives the same as Q.T
+    QtI = oracle_mod.apply_qt(F, up, np.eye(m))
+    assert np.abs(QtI - Q.T).max() <= 50 * n * U
+    for k in range(n):
+        if up[k] == 0.0:
+            continue
+        x0 = up[k] + F[k, k]
+        assert F[k, k] * x0 <= 0.0                    # sign rule
+        v2 = up[k] ** 2 + np.sum(F[k + 1:, k] ** 2)
+        assert abs(v2 + 2 * up[k] * F[k, k]) <= 50 * U * v2   # ||v||^2 = -2 b
+    for j in range(n):                                # column norms preserved
+        assert abs(np.linalg.norm(A[:, j]) - np.linalg.norm(F[: j + 1, j])) \
+            <= 50 * n * U * np.linalg.norm(A[:, j])
+
+
+def test_residual_identity_and_det(oracle_mod):
+    A, b = workloads.small_problem(seed=11, m=40, n=25)
+    x, F, up, res, info = oracle_mod.lsq_solve(A, b)
+    r = b - A @ x[:, 0]
+    assert abs(np.linalg.norm(r) - res[0]) <= 50 * 40 * U * np.linalg.norm(b)
+    Asq = workloads.gaussian(6, 6, seed=12)
+    F, up = oracle_mod.qr_factor(Asq)
+    assert np.isclose(abs(np.prod(np.diag(F))), abs(np.linalg.det(Asq)), rtol=1e-12)
+
+
+def test_lsq_orthogonality(oracle_mod):
+    A, b, _ = workloads.conditioned(128, 64, 1e6, seed=4)
+    x, F, up, res, info = oracle_mod.lsq_solve(A, b)
+    r = b - A @ x[:, 0]
+    nA = np.linalg.norm(A, 2)
+    val = np.linalg.norm(A.T @ r) / (nA * (nA * np.linalg.norm(x) + np.linalg.norm(b)))
+    assert val <= 50 * 64 * U
+
+
+# ------------------------------------------- brute force: exact normal eqs
+def _exact_solve(M, v):
+    n = len(M)
+    a = [list(M[i]) + [v[i]] for i in range(n)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if a[r][c] != 0)
+        a[c], a[p] = a[p], a[c]
+        for r in range(n):
+            if r != c and a[r][c] != 0:
+                f = a[r][c] / a[c][c]
+                a[r] = [x - f * y for x, y in zip(a[r], a[c])]
+    return [a[i][n] / a[i][i] for i in range(n)]
+
+
+def _exact_lsq(A, b):
+    Af = [[Fraction(float(v)) for v in row] for row in A]
+    bf = [Fraction(float(v)) for v in b]
+    m, n = len(Af), len(Af[0])
+    AtA = [[sum(Af[k][i] * Af[k][j] for k in range(m)) for j in range(n)] for i in range(n)]
+    Atb = [sum(Af[k][i] * bf[k] for k in range(m)) for i in range(n)]
+    return np.array([float(v) for v in _exact_solve(AtA, Atb)])
+
+
+@pytest.mark.parametrize("m,n,seed", [(2, 2, 1), (4, 3, 2), (6, 2, 3), (8, 5, 4), (8, 8, 5), (7, 1, 6)])
+def test_bruteforce_normal_equations(oracle_mod, m, n, seed):
+    A, b = workloads.small_problem(seed=seed, m=m, n=n)
+    x, F, up, res, info = oracle_mod.lsq_solve(A, b)
+    xe = _exact_lsq(A, b)
+    kappa = np.linalg.cond(A)
+    r = b - A @ xe
+    nA = np.linalg.norm(A, 2)
+    bound = 50 * n * U * kappa * (1 + kappa * np.linalg.norm(r) / (nA * np.linalg.norm(xe)))
+    assert np.linalg.norm(x[:, 0] - xe) / np.linalg.norm(xe) <= bound
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e6])
+def test_extended_reference_hits_exact_solution(oracle_mod, kappa):
+    """x_ref (long-double residual refinement) reaches the exact LSQ solution."""
+    A, b, _ = workloads.conditioned(12, 8, kappa, seed=7)
+    xe = _exact_lsq(A, b)
+    xref, rref = oracle_mod.lsq_reference(A, b, steps=10)
+    assert np.linalg.norm(xref - xe) / np.linalg.norm(xe) <= 1e-14
+
+
+# --------------------------------------------------------------- edge cases
+def test_square_last_reflector_identity(oracle_mod):
+    A = workloads.gaussian(5, 5, seed=21)
+    F, up = oracle_mod.qr_factor(A)
+    assert up[4] == 0.0 and np.all(up[:4] != 0.0)
+
+
+def test_zero_column_is_skipped(oracle_mod):
+    A = workloads.gaussian(6, 3, seed=22)
+    A[:, 1] = 0.0
+    A[0, 1] = 0.0
+    F, up = oracle_mod.qr_factor(A)
+    # column 1 is zero before and after H_0 is applied to it, so its tail is zero
+    assert up[1] == 0.0
+    assert np.all(F[1:, 1] == 0.0) and F[1, 1] == 0.0
+
+
+def test_zero_tail_nonzero_pivot(oracle_mod):
+    A = np.array([[2.0, 1.0], [0.0, 3.0], [0.0, 4.0]])
+    F, up = oracle_mod.qr_factor(A)
+    assert up[0] == 0.0 and F[0, 0] == 2.0 and F[0, 1] == 1.0   # H_0 = I, R_00 keeps +2
+    assert F[1, 1] == -5.0 and up[1] == 8.0
+
+
+def test_n1_and_m_lt_n(oracle_mod):
+    A = np.array([[0.0], [0.0], [7.0]])
+    F, up = oracle_mod.qr_factor(A)
+    assert F[0, 0] == -7.0 and up[0] == 7.0
+    with pytest.raises(ValueError):
+        oracle_mod.qr_factor(np.ones((2, 3)))
+
+
+def test_singular_reports_info(oracle_mod):
+    A = np.array([[1.0, 2.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, 1.0], [0.0, 0.0, 0.0]])
+    b = np.ones(4)
+    x, F, up, res, info = oracle_mod.lsq_solve(A, b)
+    assert info == 2           # R_11 == 0 (second column in the span of the first)
+    qtb = oracle_mod.apply_qt(F, up, b)
+    assert np.array_equal(x[:, 0], qtb[:3, 0])   # B untouched by the backsolve
+
+
+def test_nan_propagates(oracle_mod):
+    A = workloads.gaussian(5, 3, seed=23)
+    A[2, 1] = np.nan
+    F, up = oracle_mod.qr_factor(A)
+    assert np.isnan(F[:, 1:]).any() and np.isfinite(F[:, 0]).all()
+
+
+def test_tiny_column_uses_scaled_norm(oracle_mod):
+    A = workloads.gaussian(8, 3, seed=24)
+    A[:, 0] *= 1e-165                    # squares underflow without scaling
+    F, up = oracle_mod.qr_factor(A)
+    assert abs(abs(F[0, 0]) - np.linalg.norm(A[:, 0] * 1e165) * 1e-165) <= 1e-13 * abs(F[0, 0])
+
+
+# ------------------------------------------------------ planted mistakes
+MUTATIONS = {
+    "sign": ("double s = (x0 >= 0.0) ? -nu : nu;", "double s = (x0 >= 0.0) ? nu : -nu;"),
+    "dropped_up_term": ("double w = up * y[k];", "double w = 0.0;"),
+    "row_off_by_one": ("for (int64_t i = k + 1; i < m; ++i) w += AT(A, i, k, lda) * y[i];",
+                       "for (int64_t i = k + 2; i < m; ++i) w += AT(A, i, k, lda) * y[i];"),
+    "reversed_qt_order": ("        for (int64_t k = 0; k < n; ++k)\n            if (up[k] != 0.0)",
+                          "        for (int64_t k = n - 1; k >= 0; --k)\n            if (up[k] != 0.0)"),
+    "transposed_backsolve": ("t -= AT(A, i, j, lda) * x[j];", "t -= AT(A, j, i, lda) * x[j];"),
+    "tie_sign": ("double s = (x0 >= 0.0) ? -nu : nu;", "double s = (x0 > 0.0) ? -nu : nu;"),
+}
+
+
+def _pins_pass(lib):
+    """Run the worked examples against a (possibly mutated) oracle build."""
+    i64, dp = ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_lsq_solve.argtypes = [i64, i64, i64, dp, i64, dp, dp, i64, dp, dp]
+    for c in CASES.values():
+        A = np.asfortranarray(np.array([[float(v) for v in r] for r in c["A"]]))
+        m, n = A.shape
+        B = np.asfortranarray(np.array([float(v) for v in _col(c["b"])]).reshape(m, 1))
+        up = np.zeros(n)
+        res = np.zeros(1)
+        info = ctypes.c_int(0)
+        lib.oracle_lsq_solve(m, n, 1, A.ctypes.data, m, up.ctypes.data, B.ctypes.data,
+                             m, res.ctypes.data, ctypes.addressof(info))
+        ok = all(_close(A[i, j], c["F"][i][j], 20) for i in range(m) for j in range(n))
+        ok = ok and all(_close(B[j, 0], _col(c["x"])[j], 8) for j in range(n))
+        if not ok:
+            return False
+    return True
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistakes(tmp_path, name):
+    src = os.path.join(HERE, "..", "oracle", "hqr_oracle.c")
+    text = open(src).read()
+    old, new = MUTATIONS[name]
+    assert old in text, name
+    d = tmp_path / name
+    d.mkdir()
+    shutil.copy(os.path.join(HERE, "..", "oracle", "hqr_oracle.h"), d)
+    (d / "m.c").write_text(text.replace(old, new, 1))
+    so = d / "libm.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC",
+                           "-shared", "-o", str(so), str(d / "m.c"), "-lm"])
+    assert not _pins_pass(ctypes.CDLL(str(so))), name
+
+
+def test_unmutated_oracle_passes_pins(oracle_mod):
+    assert _pins_pass(ctypes.CDLL(oracle_mod.build(force=False)))
