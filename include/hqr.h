@@ -1,0 +1,127 @@
+/*
+ * hqr.h -- C ABI of libhqr: in-place Householder QR least squares on MI355X.
+ *
+ * The operation (Chatterjee et al., "Efficient Task Graph Scheduling for
+ * Parallel QR Factorization in SLSQP"):
+ *   - qr_factor transforms A into upper-triangular form in place, one
+ *     reflector per column (Section 3, Alg. 2), keeping each reflector's
+ *     leading component `up` and its tail below the diagonal (the pair
+ *     (up, b) of Alg. 3, with b = up * R[k][k]);
+ *   - qr_apply_qt applies Q^T to right-hand sides with those stored
+ *     reflectors, without forming Q (Section 1);
+ *   - qr_backsolve back-substitutes with R (abstract; Section 6 names the
+ *     triangular solve as a kernel of the same solver);
+ *   - qr_lsq_solve chains the three.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are FP64, column-major, leading dimension >= max(1, rows).
+ *   - Every matrix/vector pointer is a DEVICE pointer (HBM of the current
+ *     HIP device).  Arrays of shapes in the batched call are HOST arrays.
+ *   - Calls are asynchronous on `stream` (0 = the null stream); outputs are
+ *     valid after the stream is synchronized.  Calls never synchronize the
+ *     host except where stated.
+ *   - The caller owns every buffer.  `work`/`lwork` is an optional device
+ *     workspace of at least hqr_workspace_size() bytes; with work == NULL the
+ *     library takes a stream-ordered allocation (hipMallocAsync) and frees it
+ *     on the same stream before returning.
+ *   - Return value (host): 0 on success; -i when argument i (1-based) is
+ *     invalid, checked before any work is enqueued; or one of the HQR_E*
+ *     codes below.  Data-dependent outcomes go to the DEVICE int `*info`.
+ *   - Reflector storage after qr_factor: R in the upper triangle (diagonal
+ *     included); below the diagonal, column k holds reflector k's tail as it
+ *     was when the reflector was generated; up[k] its leading component.
+ *     H_k = I + v v^T / b_k with v = (0..0, up[k], A[k+1:m, k]) and
+ *     b_k = up[k] * R[k][k]; up[k] == 0 means H_k = I (the tail below the
+ *     pivot was exactly zero, which includes the last column when m == n).
+ *     R[k][k] = -sgn(x_0) ||x|| with sgn(0) = +1, x = A[k:m, k] at step k.
+ *   - NaN/Inf inputs are not checked; they propagate.
+ */
+#ifndef HQR_H
+#define HQR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Host status codes (besides 0 and -i). */
+#define HQR_ENOMEM   (-1001) /* workspace too small or allocation failed     */
+#define HQR_EDEVICE  (-1002) /* a HIP call failed                             */
+#define HQR_ENOTSUP  (-1003) /* shape/option combination not supported        */
+
+/* Device info codes (besides 0 and k+1 for a zero R[k][k]). */
+#define HQR_INFO_TIMEOUT (-2001) /* a bounded cross-workgroup wait expired;
+                                     outputs are invalid                   */
+#define HQR_INFO_NOCONV  (1 << 29) /* mixed precision: refinement did not
+                                      converge; the FP64 fallback was used
+                                      and its result returned (OR-ed into
+                                      info together with any k+1)          */
+
+/* Precision of the trailing-update contractions. */
+#define HQR_PREC_FP64  0 /* everything FP64                                  */
+#define HQR_PREC_MIXED 1 /* trailing update on FP32 MFMA with FP32
+                            accumulation, subtracted into FP64 storage;
+                            reflector generation, R's diagonal, Q^T b and
+                            the back-substitution stay FP64, then
+                            augmented-system refinement with FP64 residuals */
+
+typedef struct hqr_opts {
+    int precision;   /* HQR_PREC_FP64 or HQR_PREC_MIXED                      */
+    double tol;      /* mixed: stop when ||dx|| <= tol * ||x|| (<= 0: 1e-13)  */
+    int max_iter;    /* mixed: refinement step limit (< 0: 10)                */
+} hqr_opts;
+
+/* Bytes of device workspace the calls below need for an m x n problem with
+ * nrhs right-hand sides at the given precision.  Returns a negative status on
+ * invalid arguments. */
+int64_t hqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, int precision);
+
+/* In-place factorization (Alg. 2 with the storage of Alg. 3).
+ *   m >= n >= 0; A: m x n (lda >= max(1,m)), overwritten by R and the
+ *   reflector tails; up: n doubles (out); info: one device int (out):
+ *   0, or HQR_INFO_TIMEOUT. */
+int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up,
+              void *work, int64_t lwork, int *info, hipStream_t stream);
+
+/* B (m x nrhs, ldb >= max(1,m)) <- Q^T B = H_{n-1} ... H_0 B, using the
+ * output of qr_factor.  Rows 0..n-1 of B then hold the coefficients for the
+ * back-substitution, rows n..m-1 the residual components. */
+int qr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A,
+                int64_t lda, const double *up, double *B, int64_t ldb,
+                void *work, int64_t lwork, hipStream_t stream);
+
+/* B[0:n] (n x nrhs, ldb >= max(1,n)) <- R^{-1} B[0:n], R = upper triangle
+ * of A (lda >= max(1,n)).  If some R[k][k] == 0, *info = smallest such k+1
+ * and B is left unchanged; otherwise *info = 0. */
+int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                 double *B, int64_t ldb, int *info, hipStream_t stream);
+
+/* Least squares min ||B[:,j] - A x_j|| for every column j:
+ * factor A in place, B <- Q^T B, resnorm[j] <- ||(Q^T B)[n:m, j]|| (if
+ * resnorm != NULL; device array of nrhs doubles), then back-substitute so
+ * x_j ends in B[0:n, j].
+ *   opt == NULL or opt->precision == HQR_PREC_FP64: plain FP64.
+ *   opt->precision == HQR_PREC_MIXED: A_orig must point to an unmodified
+ *     FP64 copy of A (same m x n, leading dimension lda_orig) used for the
+ *     FP64 residuals of the refinement; resnorm is then ||b - A x||.
+ *   info: device int (0, k+1 for a zero R[k][k], HQR_INFO_* flags);
+ *   iters: device int or NULL, refinement steps taken (0 for FP64). */
+int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
+                 double *up, double *B, int64_t ldb, double *resnorm,
+                 const hqr_opts *opt, const double *A_orig, int64_t lda_orig,
+                 void *work, int64_t lwork, int *info, int *iters,
+                 hipStream_t stream);
+
+/* Text of a host status or device info code (static storage). */
+const char *hqr_status_string(int status);
+
+/* Library version string. */
+const char *hqr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HQR_H */

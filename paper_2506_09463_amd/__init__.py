@@ -1,0 +1,12 @@
+"""MI355X-native in-place Householder QR least squares (libhqr, gfx950).
+
+The compute path is the HIP library ``libhqr.so`` (C ABI in include/hqr.h);
+``hqr`` is its thin ctypes binding.  Nothing in this package falls back to a
+CPU implementation.
+"""
+from .hqr import (  # noqa: F401
+    EXPORTS, HQR_EDEVICE, HQR_ENOMEM, HQR_ENOTSUP, HQR_INFO_NOCONV, HQR_INFO_TIMEOUT,
+    HQR_PREC_FP64, HQR_PREC_MIXED, HQRError, colmajor, empty_colmajor, load,
+    qr_apply_qt, qr_backsolve, qr_factor, qr_lsq_solve, status_string, version,
+    workspace_size,
+)

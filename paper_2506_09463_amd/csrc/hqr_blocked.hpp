@@ -1,0 +1,585 @@
+// hqr_blocked.hpp -- blocked in-place Householder QR for problems that do not
+// fit one workgroup.
+//
+// The matrix is processed in panels of NB columns (the coarsened "Task 1"
+// of the paper's Alg. 3: alpha pivots generated back to back) followed by a
+// blocked trailing update (the coarsened "Task 2" of Alg. 4, all of a panel's
+// reflectors applied to the trailing columns at once).  On the GPU the
+// trailing update is a compact-WY contraction on FP64 MFMA:
+//     W  = V^T X            (split over rows, partial sums per split)
+//     W' = T^T W            (T upper triangular, Q_panel = I - V T V^T)
+//     X <- X - V W'
+// where X = [trailing columns of A | B].  V's columns are the stored
+// reflectors: v_k = (0..0, up_k, A[k+1:m, k]) with up_k kept in `up`.
+//
+// Panel factorization, one launch per pivot (panel_col_kernel): launch k
+// applies reflector k-1 (derived from the reduced partial dot products of
+// launch k-1) to every row chunk, then writes this launch's partial dot
+// products of pivot column k, so every reflector is derived from the same
+// data, in the same order, by every workgroup.
+#pragma once
+
+#include "hqr_device.hpp"
+
+namespace hqr {
+
+constexpr int NB = 64;          // panel width
+constexpr int PC_ROWS = 128;    // rows per workgroup in panel_col_kernel
+constexpr int PW = NB + 2;      // partial vector: dots, max|x|, #nonzero
+constexpr int KC = 32;          // rows per LDS chunk in vtc_kernel
+
+// ------------------------------------------------------------------ panel
+struct PanelArgs {
+    double *A;
+    int64_t lda;
+    int64_t m;        // rows of A
+    int c0;           // first column (and pivot row) of the panel
+    int bw;           // panel width (<= NB)
+    int k;            // launch index 0..bw
+    int nchunk;       // workgroups (row chunks of PC_ROWS rows from c0)
+    double *up;       // global up array (output for columns c0..c0+bw)
+    double *xbuf;     // [2][nchunk][PW] partials
+    double *pbuf;     // [2][NB] pivot rows
+};
+
+__global__ void __launch_bounds__(256) panel_col_kernel(PanelArgs p)
+{
+    __shared__ double S[NB][PC_ROWS + 1];
+    __shared__ double red[4][PW];
+    __shared__ double wsh[NB];
+    __shared__ double scal[4];
+
+    const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
+    const int bw = p.bw, k = p.k, c0 = p.c0;
+    const int64_t row_lo = (int64_t)c0 + (int64_t)blockIdx.x * PC_ROWS;
+    const int64_t mp = p.m;
+    const int nrow = (int)min<int64_t>((int64_t)PC_ROWS, mp - row_lo);
+
+    // load my chunk (column-major in LDS)
+    for (int idx = tid; idx < nrow * bw; idx += 256) {
+        const int j = idx / nrow, r = idx - j * nrow;
+        S[j][r] = HQR_AT(p.A, row_lo + r, c0 + j, p.lda);
+    }
+    __syncthreads();
+
+    // ---- apply reflector k-1
+    if (k > 0) {
+        const int kp = k - 1;
+        const int par = kp & 1;
+        const double *X = p.xbuf + (size_t)par * p.nchunk * PW;
+        const double *prow = p.pbuf + (size_t)par * NB;
+        // reduced partials, same order in every workgroup
+        double d_j = 0.0;
+        if (tid < bw) {
+            for (int q = 0; q < p.nchunk; ++q) d_j += X[(size_t)q * PW + tid];
+        }
+        if (tid == 0) {
+            double ssq = 0.0, mx = 0.0, nz = 0.0;
+            for (int q = 0; q < p.nchunk; ++q) {
+                ssq += X[(size_t)q * PW + kp];
+                mx = fmax(mx, X[(size_t)q * PW + NB]);
+                nz += X[(size_t)q * PW + NB + 1];
+            }
+            scal[0] = ssq;
+            scal[1] = mx;
+            scal[2] = nz;
+        }
+        __syncthreads();
+        const double x0 = prow[kp];
+        double up_k, s_k;
+        if (scal[2] == 0.0) {
+            up_k = 0.0;
+            s_k = x0;
+        } else {
+            const double c = fmax(fabs(x0), scal[1]);
+            double nu;
+            if (norm_fast_path_ok(c)) {
+                nu = sqrt(x0 * x0 + scal[0]);
+            } else {
+                // rare: the partials of this launch's pivot were not scaled;
+                // recompute the scaled norm from the tail in global memory
+                // (a deterministic single-thread loop, identical in every WG)
+                double t = 0.0;
+                const int64_t pr = (int64_t)c0 + kp;
+                for (int64_t i = pr + 1; i < mp; ++i) {
+                    const double y = HQR_AT(p.A, i, c0 + kp, p.lda) / c;
+                    t += y * y;
+                }
+                const double x0c = x0 / c;
+                nu = c * sqrt(x0c * x0c + t);
+            }
+            s_k = (x0 >= 0.0) ? -nu : nu;
+            up_k = x0 - s_k;
+        }
+        const bool skip = (up_k == 0.0);
+        const double b_k = up_k * s_k;
+        if (tid < NB) wsh[tid] = (!skip && tid > kp && tid < bw) ? (up_k * prow[tid] + d_j) / b_k : 0.0;
+        const int64_t prow_g = (int64_t)c0 + kp;
+        if (blockIdx.x == 0 && tid == 0) p.up[c0 + kp] = up_k;
+        __syncthreads();
+        // rows of my chunk that are >= the pivot row
+        if (!skip) {
+            for (int idx = tid; idx < nrow * bw; idx += 256) {
+                const int j = idx / nrow, r = idx - j * nrow;
+                const int64_t gi = row_lo + r;
+                if (j <= kp || gi < prow_g) continue;
+                const double v = (gi == prow_g) ? up_k : S[kp][r];
+                S[j][r] += wsh[j] * v;
+            }
+        }
+        if (prow_g >= row_lo && prow_g < row_lo + nrow && tid == 0) S[kp][prow_g - row_lo] = s_k;
+        __syncthreads();
+    }
+
+    // ---- partials of pivot column k (x = A[c0+k+1 : m, c0+k])
+    if (k < bw) {
+        const int par = k & 1;
+        double *X = p.xbuf + (size_t)par * p.nchunk * PW;
+        double *prow = p.pbuf + (size_t)par * NB;
+        const int64_t pr = (int64_t)c0 + k;
+        // thread (column j = lane, row group g)
+        double acc = 0.0, mx = 0.0, nz = 0.0;
+        for (int r = g; r < nrow; r += 4) {
+            const int64_t gi = row_lo + r;
+            if (gi <= pr) continue;
+            const double xi = S[k][r];
+            if (lane < bw) acc += xi * S[lane][r];
+            mx = fmax(mx, fabs(xi));
+            nz += (xi != 0.0) ? 1.0 : 0.0;
+        }
+        red[g][lane] = acc;
+        if (lane == 0) {
+            red[g][NB] = mx;
+            red[g][NB + 1] = nz;
+        }
+        __syncthreads();
+        if (tid < PW) {
+            double v;
+            if (tid == NB) v = fmax(fmax(red[0][NB], red[1][NB]), fmax(red[2][NB], red[3][NB]));
+            else v = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+            X[(size_t)blockIdx.x * PW + tid] = v;
+        }
+        if (pr >= row_lo && pr < row_lo + nrow && tid < NB)
+            prow[tid] = (tid < bw) ? S[tid][pr - row_lo] : 0.0;
+    }
+    __syncthreads();
+
+    // store the chunk back
+    for (int idx = tid; idx < nrow * bw; idx += 256) {
+        const int j = idx / nrow, r = idx - j * nrow;
+        HQR_AT(p.A, row_lo + r, c0 + j, p.lda) = S[j][r];
+    }
+}
+
+// ----------------------------------------------------- W = V^T X (partials)
+// X columns: [0, bw) = V itself (gives G = V^T V), then ncA trailing columns
+// of A starting at column c0+bw, then nB columns of B.
+struct VtxArgs {
+    const double *A;
+    int64_t lda;
+    const double *B;
+    int64_t ldb;
+    const double *up;
+    int64_t m;
+    int c0, bw;
+    int ncA, nB;          // trailing A columns, B columns
+    int nx;               // bw + ncA + nB
+    int nxpad;            // row stride of the partial buffers
+    int64_t split_rows;   // rows per split (multiple of KC)
+    int with_v;           // include the bw V columns as X columns
+    double *wpart;        // [nsplit][NB][nxpad]
+};
+
+// V element (global row gi >= c0, panel column c)
+HQR_DEV double v_elem(const double *A, int64_t lda, const double *up, int c0, int64_t gi, int c)
+{
+    const int64_t d = gi - c0;
+    if (d < c) return 0.0;
+    if (d == c) return up[c0 + c];
+    return HQR_AT(A, gi, c0 + c, lda);
+}
+
+HQR_DEV double x_elem(const VtxArgs &p, int64_t gi, int x)
+{
+    if (gi >= p.m || x >= p.nx) return 0.0;
+    if (p.with_v) {
+        if (x < p.bw) return v_elem(p.A, p.lda, p.up, p.c0, gi, x);
+        x -= p.bw;
+    }
+    if (x < p.ncA) return HQR_AT(p.A, gi, p.c0 + p.bw + x, p.lda);
+    return HQR_AT(p.B, gi, x - p.ncA, p.ldb);
+}
+
+// grid: (ceil(nx/64), nsplit); 256 threads.  Output tile: 64 reflectors x 64
+// X columns.  Wave w owns reflector rows [16w, 16w+16), all four column tiles.
+__global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
+{
+    __shared__ double Vs[KC][NB + 1];
+    __shared__ double Xs[KC][64 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int x0 = blockIdx.x * 64;
+    const int64_t r_begin = (int64_t)p.c0 + (int64_t)blockIdx.y * p.split_rows;
+    const int64_t r_end = min<int64_t>(p.m, r_begin + p.split_rows);
+
+    f64x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
+        // stage: column-major global -> [row][col] LDS, consecutive threads
+        // walk down a column
+        for (int idx = tid; idx < KC * NB; idx += 256) {
+            const int c = idx / KC, r = idx - c * KC;
+            const int64_t gi = r0 + r;
+            Vs[r][c] = (gi < r_end && c < p.bw) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : 0.0;
+            Xs[r][c] = (gi < r_end) ? x_elem(p, gi, x0 + c) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const double a = Vs[kr][16 * w + (lane & 15)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double b = Xs[kr][16 * t + (lane & 15)];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D[i][j] at lane j + 16*(i%4), register i/4
+    double *out = p.wpart + (size_t)blockIdx.y * NB * p.nxpad;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * w + 4 * r + (lane >> 4);
+            const int x = x0 + 16 * t + (lane & 15);
+            if (x < p.nxpad) out[(size_t)i * p.nxpad + x] = acc[t][r];
+        }
+}
+
+// ------------------------------------------------- T from G = V^T V and tau
+// One workgroup.  tau_k = -1/(up_k R_kk) (0 for identity reflectors);
+// T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
+struct TArgs {
+    const double *A;
+    int64_t lda;
+    const double *up;
+    int c0, bw;
+    const double *wpart; // partials holding G in columns [0, bw)
+    int nsplit, nxpad;
+    double *T;           // [NB][NB] row-major T[i][j]
+};
+
+__global__ void __launch_bounds__(256) tfactor_kernel(TArgs p)
+{
+    __shared__ double G[NB][NB + 1];
+    __shared__ double Ts[NB][NB + 1];
+    __shared__ double tau[NB];
+    __shared__ double tmp[NB];
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx / NB, j = idx - i * NB;
+        double s = 0.0;
+        if (i < p.bw && j < p.bw)
+            for (int q = 0; q < p.nsplit; ++q) s += p.wpart[(size_t)q * NB * p.nxpad + (size_t)i * p.nxpad + j];
+        G[i][j] = s;
+        Ts[i][j] = 0.0;
+    }
+    if (tid < NB) {
+        double t = 0.0;
+        if (tid < p.bw) {
+            const double u = p.up[p.c0 + tid];
+            const double rkk = HQR_AT(p.A, (int64_t)p.c0 + tid, p.c0 + tid, p.lda);
+            t = (u == 0.0) ? 0.0 : -1.0 / (u * rkk);
+        }
+        tau[tid] = t;
+    }
+    __syncthreads();
+    for (int j = 0; j < p.bw; ++j) {
+        // tmp[i] = sum_{l=i}^{j-1} T[i][l] G[l][j], i < j
+        if (tid < j) {
+            double s = 0.0;
+            for (int l = tid; l < j; ++l) s += Ts[tid][l] * G[l][j];
+            tmp[tid] = s;
+        }
+        __syncthreads();
+        if (tid < j) Ts[tid][j] = -tau[j] * tmp[tid];
+        if (tid == j) Ts[j][j] = tau[j];
+        __syncthreads();
+    }
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx / NB, j = idx - i * NB;
+        p.T[idx] = Ts[i][j];
+    }
+}
+
+// ------------------------------------------------ W' = T^T (sum of partials)
+// grid: ceil(ncols/64) over the X columns that get updated (offset xoff).
+struct WArgs {
+    const double *wpart;
+    int nsplit, nxpad;
+    int xoff, ncols;      // updated X columns [xoff, xoff+ncols)
+    int bw;
+    const double *T;
+    double *wp;           // [NB][nxpad] row-major, same column indexing
+};
+
+__global__ void __launch_bounds__(256) wsolve_kernel(WArgs p)
+{
+    __shared__ double Ws[NB][64 + 1];
+    __shared__ double Ts[NB][NB + 1];
+    const int tid = threadIdx.x;
+    const int xb = p.xoff + blockIdx.x * 64;
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx / NB, j = idx - i * NB;
+        Ts[i][j] = p.T[idx];
+    }
+    for (int idx = tid; idx < NB * 64; idx += 256) {
+        const int i = idx / 64, c = idx - i * 64;
+        const int x = xb + c;
+        double s = 0.0;
+        if (i < p.bw && x < p.xoff + p.ncols)
+            for (int q = 0; q < p.nsplit; ++q) s += p.wpart[(size_t)q * NB * p.nxpad + (size_t)i * p.nxpad + x];
+        Ws[i][c] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NB * 64; idx += 256) {
+        const int i = idx / 64, c = idx - i * 64;
+        const int x = xb + c;
+        if (x >= p.xoff + p.ncols) continue;
+        double s = 0.0;
+        for (int l = 0; l <= i && l < p.bw; ++l) s += Ts[l][i] * Ws[l][c];
+        p.wp[(size_t)i * p.nxpad + x] = (i < p.bw) ? s : 0.0;
+    }
+}
+
+// ---------------------------------------------------------- X <- X - V W'
+// grid: (ceil(rows/64), ceil(ncols/64)); 256 threads.  Tile 64 rows x 64
+// columns, computed transposed (D' = W'^T V^T) so each accumulator register
+// maps to 16 consecutive rows of one column.
+struct UpdArgs {
+    double *A;
+    int64_t lda;
+    double *B;
+    int64_t ldb;
+    const double *up;
+    int64_t m;
+    int c0, bw;
+    int ncA, nB;          // updated A columns start at c0+bw; then B columns
+    int xoff;             // X index of the first updated column in wp
+    const double *wp;     // [NB][nxpad]
+    int nxpad;
+};
+
+HQR_DEV double *col_ptr(const UpdArgs &p, int c)
+{
+    if (c < p.ncA) return p.A + (size_t)(p.c0 + p.bw + c) * p.lda;
+    return p.B + (size_t)(c - p.ncA) * p.ldb;
+}
+
+__global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
+{
+    __shared__ double Vs[64][NB + 1];   // [row][k]
+    __shared__ double Wt[NB][64 + 1];   // [k][col]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t rb = (int64_t)p.c0 + (int64_t)blockIdx.x * 64;
+    const int cb = blockIdx.y * 64;
+    const int ncols = p.ncA + p.nB;
+
+    for (int idx = tid; idx < 64 * NB; idx += 256) {
+        const int k = idx / 64, r = idx - k * 64;
+        const int64_t gi = rb + r;
+        Vs[r][k] = (gi < p.m && k < p.bw) ? v_elem(p.A, p.lda, p.up, p.c0, gi, k) : 0.0;
+        const int kk = idx / 64, c = idx - kk * 64;
+        Wt[kk][c] = (kk < p.bw && cb + c < ncols) ? p.wp[(size_t)kk * p.nxpad + p.xoff + cb + c] : 0.0;
+    }
+    // accumulators: wave w owns columns [16w, 16w+16) of the tile, 4 row tiles
+    f64x4 acc[4];
+    const int jl = 16 * w;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = cb + jl + 4 * r + (lane >> 4);
+            const int64_t gi = rb + 16 * t + (lane & 15);
+            acc[t][r] = (c < ncols && gi < p.m) ? col_ptr(p, c)[gi] : 0.0;
+        }
+    __syncthreads();
+#pragma unroll 4
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+        const int kr = k0 + (lane >> 4);
+        const double a = -Wt[kr][jl + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double b = Vs[16 * t + (lane & 15)][kr];
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = cb + jl + 4 * r + (lane >> 4);
+            const int64_t gi = rb + 16 * t + (lane & 15);
+            if (c < ncols && gi < p.m) col_ptr(p, c)[gi] = acc[t][r];
+        }
+}
+
+// ------------------------------------------------------------ triangular
+// info = smallest k+1 with R[k][k] == 0 (0 if none).  One workgroup.
+__global__ void __launch_bounds__(256) diag_check_kernel(const double *A, int64_t lda, int64_t n, int *info)
+{
+    __shared__ int first;
+    if (threadIdx.x == 0) first = 0x7fffffff;
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < n; k += 256)
+        if (HQR_AT(A, k, k, lda) == 0.0) atomicMin(&first, (int)(k + 1));
+    __syncthreads();
+    if (threadIdx.x == 0) *info = (first == 0x7fffffff) ? 0 : first;
+}
+
+// Blocked back-substitution R X = B[0:n].  Row blocks of 64; workgroup b
+// owns row block nblk-1-b, so every block it waits for belongs to a
+// workgroup dispatched before it.  A block is published by writing its x
+// values to B and then raising flags[block] (release); consumers acquire it.
+// The wait is bounded: on expiry the kernel records HQR_INFO_TIMEOUT.
+struct TrsvArgs {
+    const double *A;
+    int64_t lda;
+    double *B;
+    int64_t ldb;
+    int64_t n;
+    int nrhs;
+    int *flags;      // [nblk], zero on entry
+    int *info;       // read: nonzero -> nothing to do; written on timeout
+    int epoch;       // value a published flag holds
+    long spin_limit;
+};
+
+constexpr int TRSV_MAXRHS = 8;
+
+__global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
+{
+    __shared__ double xs[64][TRSV_MAXRHS];
+    __shared__ double accs[64][TRSV_MAXRHS];
+    __shared__ double part[4][64][TRSV_MAXRHS];
+    __shared__ int bad;
+    const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
+    if (*((volatile int *)p.info) != 0) return;
+    const int nblk = (int)((p.n + 63) / 64);
+    const int ib = nblk - 1 - (int)blockIdx.x;
+    const int64_t r0 = (int64_t)ib * 64;
+    const int nr = (int)min<int64_t>(64, p.n - r0);
+    const int nrhs = p.nrhs;
+    if (tid == 0) bad = 0;
+    // accumulator: thread (row lane, group g) keeps partial sums for rhs c
+    double acc[TRSV_MAXRHS];
+#pragma unroll
+    for (int c = 0; c < TRSV_MAXRHS; ++c) acc[c] = 0.0;
+    __syncthreads();
+    for (int jb = nblk - 1; jb > ib; --jb) {
+        if (tid == 0) {
+            long s = 0;
+            while (__hip_atomic_load(&p.flags[jb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != p.epoch) {
+                if (++s > p.spin_limit) {
+                    bad = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __syncthreads();
+        if (bad) break;
+        const int64_t c0 = (int64_t)jb * 64;
+        const int nc = (int)min<int64_t>(64, p.n - c0);
+        for (int idx = tid; idx < 64 * TRSV_MAXRHS; idx += 256) {
+            const int r = idx / TRSV_MAXRHS, c = idx - r * TRSV_MAXRHS;
+            xs[r][c] = (r < nc && c < nrhs) ? __hip_atomic_load(&p.B[(size_t)(c0 + r) + (size_t)c * p.ldb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+        }
+        __syncthreads();
+        if (lane < nr) {
+            for (int l = g; l < nc; l += 4) {
+                const double rv = HQR_AT(p.A, r0 + lane, c0 + l, p.lda);
+#pragma unroll
+                for (int c = 0; c < TRSV_MAXRHS; ++c) acc[c] += rv * xs[l][c];
+            }
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (tid == 0) atomicExch(p.info, HQR_INFO_TIMEOUT);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < TRSV_MAXRHS; ++c) part[g][lane][c] = acc[c];
+    __syncthreads();
+    // diagonal block on wave 0: lanes = rows
+    if (g == 0) {
+        for (int c = 0; c < nrhs; ++c) {
+            double t = 0.0;
+            if (lane < nr)
+                t = HQR_AT(p.B, r0 + lane, c, p.ldb) - (((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c]);
+            for (int i = nr - 1; i >= 0; --i) {
+                const double ti = readlane_f64(t, i);
+                const double xi = ti / HQR_AT(p.A, r0 + i, r0 + i, p.lda);
+                if (lane < i) t -= HQR_AT(p.A, r0 + lane, r0 + i, p.lda) * xi;
+                if (lane == i) t = xi;
+            }
+            accs[lane][c] = t;
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nr * nrhs; idx += 256) {
+        const int c = idx / nr, r = idx - c * nr;
+        __hip_atomic_store(&p.B[(size_t)(r0 + r) + (size_t)c * p.ldb], accs[r][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(&p.flags[ib], p.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// resnorm[c] = ||B[n:m, c]||, one workgroup per column.
+__global__ void __launch_bounds__(256) resnorm_kernel(const double *B, int64_t ldb, int64_t n, int64_t m, double *out)
+{
+    __shared__ double ss[4], mxs[4];
+    const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
+    const double *col = B + (size_t)blockIdx.x * ldb;
+    double s = 0.0, mx = 0.0;
+    for (int64_t i = n + tid; i < m; i += 256) {
+        s += col[i] * col[i];
+        mx = fmax(mx, fabs(col[i]));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o);
+        mx = fmax(mx, __shfl_xor(mx, o));
+    }
+    if (lane == 0) {
+        ss[g] = s;
+        mxs[g] = mx;
+    }
+    __syncthreads();
+    const double tot = ((ss[0] + ss[1]) + ss[2]) + ss[3];
+    const double gmx = fmax(fmax(mxs[0], mxs[1]), fmax(mxs[2], mxs[3]));
+    if (gmx == 0.0 || norm_fast_path_ok(gmx)) {
+        if (tid == 0) out[blockIdx.x] = sqrt(tot);
+        return;
+    }
+    double t = 0.0;
+    for (int64_t i = n + tid; i < m; i += 256) {
+        const double y = col[i] / gmx;
+        t += y * y;
+    }
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    __syncthreads();
+    if (lane == 0) ss[g] = t;
+    __syncthreads();
+    if (tid == 0) out[blockIdx.x] = gmx * sqrt(((ss[0] + ss[1]) + ss[2]) + ss[3]);
+}
+
+__global__ void fill_int_kernel(int *p, int v, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+} // namespace hqr

@@ -1,0 +1,500 @@
+// hqr_lib.hip -- libhqr: the C ABI declared in include/hqr.h and its host
+// dispatch.  One translation unit: the kernels live in the included headers.
+#include "hqr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+
+#include "hqr_device.hpp"
+#include "hqr_small.hpp"
+#include "hqr_blocked.hpp"
+
+namespace hqr {
+
+// ------------------------------------------------------------- small path
+typedef void (*small_fn)(SmallArgs);
+struct SmallCfg {
+    int nw, rw, q;
+    small_fn fn;
+    size_t static_lds;
+};
+
+template <int NW, int RW, int Q>
+static SmallCfg make_small()
+{
+    const size_t st = sizeof(double) * (2 * NW * (Q * 64 + 2) + 2 * Q * 64 + NW) + 16;
+    return SmallCfg{NW, RW, Q, small_lsq_kernel<NW, RW, Q>, st};
+}
+
+static const SmallCfg *small_configs(int *count)
+{
+    static SmallCfg cfgs[] = {
+        make_small<4, 16, 1>(),  // m <= 64,  n+nrhs <= 64
+        make_small<8, 16, 2>(),  // m <= 128, n+nrhs <= 128
+        make_small<16, 16, 2>(), // m <= 256, n+nrhs <= 128
+    };
+    *count = (int)(sizeof(cfgs) / sizeof(cfgs[0]));
+    return cfgs;
+}
+
+static constexpr size_t LDS_LIMIT = 160 * 1024;
+
+static const SmallCfg *pick_small(int64_t m, int64_t n, int64_t nrhs)
+{
+    if (m > 256 || n + nrhs > 128 || n == 0) return nullptr;
+    int cnt = 0;
+    const SmallCfg *c = small_configs(&cnt);
+    for (int i = 0; i < cnt; ++i) {
+        if (m > (int64_t)c[i].nw * c[i].rw || n + nrhs > 64 * c[i].q) continue;
+        if (c[i].static_lds + small_dyn_lds((int)m, (int)n, (int)nrhs) > LDS_LIMIT) continue;
+        return &c[i];
+    }
+    return nullptr;
+}
+
+static hipError_t launch_small(const SmallCfg *cfg, SmallArgs a, hipStream_t s)
+{
+    a.ldl = small_ldl(a.m);
+    const size_t dyn = small_dyn_lds(a.m, a.n, a.nrhs);
+    (void)hipFuncSetAttribute((const void *)cfg->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    hipLaunchKernelGGL(cfg->fn, dim3(1), dim3(cfg->nw * 64), dyn, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ large path
+struct Plan {
+    int64_t m, n, nrhs;
+    int nchunk;      // panel row chunks for the first panel (upper bound)
+    int nxpad;       // row stride of W partials
+    int nsplit_max;
+    int nblk;        // triangular blocks
+};
+
+static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+static Plan make_plan(int64_t m, int64_t n, int64_t nrhs)
+{
+    Plan p;
+    p.m = m;
+    p.n = n;
+    p.nrhs = nrhs;
+    p.nchunk = (int)((m + PC_ROWS - 1) / PC_ROWS);
+    p.nxpad = (int)rup(NB + n + nrhs, 64);
+    p.nsplit_max = 16;
+    p.nblk = (int)((n + 63) / 64);
+    return p;
+}
+
+struct Work {
+    double *xbuf, *pbuf, *wpart, *T, *wp;
+    int *flags;
+    int *iscratch;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t work_bytes(const Plan &p, Work *w, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *ptr = base ? base + off : nullptr;
+        off += align256(bytes);
+        return ptr;
+    };
+    char *x = take(sizeof(double) * 2 * (size_t)p.nchunk * PW);
+    char *pb = take(sizeof(double) * 2 * NB);
+    char *wpart = take(sizeof(double) * (size_t)p.nsplit_max * NB * p.nxpad);
+    char *T = take(sizeof(double) * NB * NB);
+    char *wp = take(sizeof(double) * NB * (size_t)p.nxpad);
+    char *fl = take(sizeof(int) * (size_t)std::max(p.nblk, 1));
+    char *is = take(sizeof(int) * 64);
+    if (w) {
+        w->xbuf = (double *)x;
+        w->pbuf = (double *)pb;
+        w->wpart = (double *)wpart;
+        w->T = (double *)T;
+        w->wp = (double *)wp;
+        w->flags = (int *)fl;
+        w->iscratch = (int *)is;
+    }
+    return off;
+}
+
+static int pick_nsplit(int64_t rows, int ntiles, int nsplit_max)
+{
+    int want = (int)std::max<int64_t>(1, (512 + ntiles - 1) / std::max(ntiles, 1));
+    int cap = (int)std::max<int64_t>(1, rows / 256);
+    return std::max(1, std::min(std::min(want, cap), nsplit_max));
+}
+
+#define HQR_CK(call)                                   \
+    do {                                               \
+        if ((call) != hipSuccess) return HQR_EDEVICE;  \
+    } while (0)
+
+// Apply the compact-WY block of panel (c0, bw) to trailing A columns
+// [c0+bw, c0+bw+ncA) and all nB columns of B.
+static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t lda, double *B, int64_t ldb,
+                             const double *up, int c0, int bw, int ncA, int nB, hipStream_t s)
+{
+    const int64_t rows = pl.m - c0;
+    VtxArgs v;
+    v.A = A;
+    v.lda = lda;
+    v.B = B;
+    v.ldb = ldb;
+    v.up = up;
+    v.m = pl.m;
+    v.c0 = c0;
+    v.bw = bw;
+    v.ncA = ncA;
+    v.nB = nB;
+    v.with_v = 1;
+    v.nx = bw + ncA + nB;
+    v.nxpad = pl.nxpad;
+    const int ntiles = (v.nx + 63) / 64;
+    const int nsplit = pick_nsplit(rows, ntiles, pl.nsplit_max);
+    v.split_rows = rup((rows + nsplit - 1) / nsplit, KC);
+    const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
+    v.wpart = w.wpart;
+    hipLaunchKernelGGL(vtx_kernel, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
+    HQR_CK(hipGetLastError());
+
+    TArgs t;
+    t.A = A;
+    t.lda = lda;
+    t.up = up;
+    t.c0 = c0;
+    t.bw = bw;
+    t.wpart = w.wpart;
+    t.nsplit = nsplit_eff;
+    t.nxpad = pl.nxpad;
+    t.T = w.T;
+    hipLaunchKernelGGL(tfactor_kernel, dim3(1), dim3(256), 0, s, t);
+    HQR_CK(hipGetLastError());
+
+    const int ncols = ncA + nB;
+    if (ncols == 0) return 0;
+    WArgs wa;
+    wa.wpart = w.wpart;
+    wa.nsplit = nsplit_eff;
+    wa.nxpad = pl.nxpad;
+    wa.xoff = bw;
+    wa.ncols = ncols;
+    wa.bw = bw;
+    wa.T = w.T;
+    wa.wp = w.wp;
+    hipLaunchKernelGGL(wsolve_kernel, dim3((ncols + 63) / 64), dim3(256), 0, s, wa);
+    HQR_CK(hipGetLastError());
+
+    UpdArgs u;
+    u.A = A;
+    u.lda = lda;
+    u.B = B;
+    u.ldb = ldb;
+    u.up = up;
+    u.m = pl.m;
+    u.c0 = c0;
+    u.bw = bw;
+    u.ncA = ncA;
+    u.nB = nB;
+    u.xoff = bw;
+    u.wp = w.wp;
+    u.nxpad = pl.nxpad;
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)((rows + 63) / 64), (ncols + 63) / 64), dim3(256), 0, s, u);
+    HQR_CK(hipGetLastError());
+    return 0;
+}
+
+// Blocked factorization; B (nB columns) rides along as trailing columns.
+static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, double *B, int64_t ldb,
+                          int nB, hipStream_t s)
+{
+    const int64_t m = pl.m, n = pl.n;
+    for (int64_t c0 = 0; c0 < n; c0 += NB) {
+        const int bw = (int)std::min<int64_t>(NB, n - c0);
+        PanelArgs pa;
+        pa.A = A;
+        pa.lda = lda;
+        pa.m = m;
+        pa.c0 = (int)c0;
+        pa.bw = bw;
+        pa.nchunk = (int)((m - c0 + PC_ROWS - 1) / PC_ROWS);
+        pa.up = up;
+        pa.xbuf = w.xbuf;
+        pa.pbuf = w.pbuf;
+        for (int k = 0; k <= bw; ++k) {
+            pa.k = k;
+            hipLaunchKernelGGL(panel_col_kernel, dim3(pa.nchunk), dim3(256), 0, s, pa);
+            HQR_CK(hipGetLastError());
+        }
+        const int ncA = (int)(n - c0 - bw);
+        if (ncA + nB > 0) {
+            int rc = apply_panel_block(pl, w, A, lda, B, ldb, up, (int)c0, bw, ncA, nB, s);
+            if (rc) return rc;
+        }
+    }
+    return 0;
+}
+
+static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int64_t lda, double *B, int64_t ldb,
+                             int nrhs, int *info, hipStream_t s)
+{
+    hipLaunchKernelGGL(diag_check_kernel, dim3(1), dim3(256), 0, s, A, lda, pl.n, info);
+    HQR_CK(hipGetLastError());
+    for (int c = 0; c < nrhs; c += TRSV_MAXRHS) {
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, s, w.flags, 0, (int64_t)pl.nblk);
+        HQR_CK(hipGetLastError());
+        TrsvArgs t;
+        t.A = A;
+        t.lda = lda;
+        t.B = B + (size_t)c * ldb;
+        t.ldb = ldb;
+        t.n = pl.n;
+        t.nrhs = std::min(TRSV_MAXRHS, nrhs - c);
+        t.flags = w.flags;
+        t.info = info;
+        t.epoch = 1;
+        t.spin_limit = 20000000L;
+        hipLaunchKernelGGL(trsv_kernel, dim3(pl.nblk), dim3(256), 0, s, t);
+        HQR_CK(hipGetLastError());
+    }
+    return 0;
+}
+
+struct WorkGuard {
+    void *ptr = nullptr;
+    hipStream_t s = nullptr;
+    ~WorkGuard()
+    {
+        if (ptr) (void)hipFreeAsync(ptr, s);
+    }
+};
+
+static int get_work(const Plan &pl, void *work, int64_t lwork, hipStream_t s, WorkGuard &g, Work *w)
+{
+    const size_t need = work_bytes(pl, nullptr, nullptr);
+    char *base = (char *)work;
+    if (!base) {
+        if (hipMallocAsync((void **)&base, need, s) != hipSuccess) return HQR_ENOMEM;
+        g.ptr = base;
+        g.s = s;
+    } else if (lwork < (int64_t)need) {
+        return HQR_ENOMEM;
+    }
+    work_bytes(pl, w, base);
+    return 0;
+}
+
+} // namespace hqr
+
+using namespace hqr;
+
+extern "C" {
+
+int64_t hqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, int precision)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (nrhs < 0) return -3;
+    if (precision != HQR_PREC_FP64 && precision != HQR_PREC_MIXED) return -4;
+    Plan pl = make_plan(m, n, nrhs);
+    return (int64_t)work_bytes(pl, nullptr, nullptr);
+}
+
+int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up, void *work, int64_t lwork, int *info,
+              hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (!info) return -8;
+    if (n > 0 && !A) return -3;
+    if (n > 0 && !up) return -5;
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2) return HQR_ENOTSUP;
+    if (n == 0) {
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
+    }
+    if (const SmallCfg *c = pick_small(m, n, 0)) {
+        SmallArgs a{};
+        a.m = (int)m;
+        a.n = (int)n;
+        a.nrhs = 0;
+        a.mode = SMALL_FACTOR;
+        a.lda = lda;
+        a.ldb = std::max<int64_t>(1, m);
+        a.A = A;
+        a.up = up;
+        a.info = info;
+        return launch_small(c, a, stream) == hipSuccess ? 0 : HQR_EDEVICE;
+    }
+    Plan pl = make_plan(m, n, 0);
+    WorkGuard g;
+    Work w;
+    int rc = get_work(pl, work, lwork, stream, g, &w);
+    if (rc) return rc;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+    HQR_CK(hipGetLastError());
+    return factor_blocked(pl, w, A, lda, up, nullptr, 1, 0, stream);
+}
+
+int qr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *up, double *B,
+                int64_t ldb, void *work, int64_t lwork, hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (nrhs < 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (ldb < std::max<int64_t>(1, m)) return -8;
+    if (n == 0 || nrhs == 0) return 0;
+    if (!A) return -4;
+    if (!up) return -6;
+    if (!B) return -7;
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
+    if (const SmallCfg *c = pick_small(m, n, nrhs)) {
+        SmallArgs a{};
+        a.m = (int)m;
+        a.n = (int)n;
+        a.nrhs = (int)nrhs;
+        a.mode = 0;
+        a.lda = lda;
+        a.ldb = ldb;
+        a.A = const_cast<double *>(A);
+        a.B = B;
+        a.up = const_cast<double *>(up);
+        return launch_small(c, a, stream) == hipSuccess ? 0 : HQR_EDEVICE;
+    }
+    Plan pl = make_plan(m, n, nrhs);
+    WorkGuard g;
+    Work w;
+    int rc = get_work(pl, work, lwork, stream, g, &w);
+    if (rc) return rc;
+    for (int64_t c0 = 0; c0 < n; c0 += NB) {
+        const int bw = (int)std::min<int64_t>(NB, n - c0);
+        rc = apply_panel_block(pl, w, const_cast<double *>(A), lda, B, ldb, up, (int)c0, bw, 0, (int)nrhs, stream);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *B, int64_t ldb, int *info,
+                 hipStream_t stream)
+{
+    if (n < 0) return -1;
+    if (nrhs < 0) return -2;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (!info) return -7;
+    if (n > 0 && nrhs > 0) {
+        if (!A) return -3;
+        if (!B) return -5;
+    }
+    if (n > INT32_MAX / 2) return HQR_ENOTSUP;
+    if (n == 0 || nrhs == 0) {
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
+    }
+    Plan pl = make_plan(n, n, nrhs);
+    WorkGuard g;
+    Work w;
+    int rc = get_work(pl, nullptr, 0, stream, g, &w);
+    if (rc) return rc;
+    return backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, stream);
+}
+
+int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B, int64_t ldb,
+                 double *resnorm, const hqr_opts *opt, const double *A_orig, int64_t lda_orig, void *work,
+                 int64_t lwork, int *info, int *iters, hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (nrhs < 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (ldb < std::max<int64_t>(1, m)) return -8;
+    if (!info) return -15;
+    const int prec = opt ? opt->precision : HQR_PREC_FP64;
+    if (prec != HQR_PREC_FP64 && prec != HQR_PREC_MIXED) return -10;
+    if (n > 0) {
+        if (!A) return -4;
+        if (!up) return -6;
+    }
+    if (nrhs > 0 && !B) return -7;
+    if (prec == HQR_PREC_MIXED) {
+        if (!A_orig) return -11;
+        if (lda_orig < std::max<int64_t>(1, m)) return -12;
+        return HQR_ENOTSUP; // mixed precision: not in this build yet
+    }
+    (void)A_orig;
+    (void)lda_orig;
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
+    if (iters) {
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
+        HQR_CK(hipGetLastError());
+    }
+    if (n == 0) {
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_CK(hipGetLastError());
+        if (resnorm && nrhs > 0) {
+            hipLaunchKernelGGL(resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb,
+                               (int64_t)0, m, resnorm);
+            HQR_CK(hipGetLastError());
+        }
+        return 0;
+    }
+    if (const SmallCfg *c = pick_small(m, n, nrhs)) {
+        SmallArgs a{};
+        a.m = (int)m;
+        a.n = (int)n;
+        a.nrhs = (int)nrhs;
+        a.mode = SMALL_FACTOR | SMALL_SOLVE | (resnorm ? SMALL_RESNORM : 0);
+        a.lda = lda;
+        a.ldb = ldb;
+        a.A = A;
+        a.B = B;
+        a.up = up;
+        a.resnorm = resnorm;
+        a.info = info;
+        return launch_small(c, a, stream) == hipSuccess ? 0 : HQR_EDEVICE;
+    }
+    Plan pl = make_plan(m, n, nrhs);
+    WorkGuard g;
+    Work w;
+    int rc = get_work(pl, work, lwork, stream, g, &w);
+    if (rc) return rc;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+    HQR_CK(hipGetLastError());
+    rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, stream);
+    if (rc) return rc;
+    if (nrhs == 0) return 0;
+    if (resnorm) {
+        hipLaunchKernelGGL(resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb, n, m,
+                           resnorm);
+        HQR_CK(hipGetLastError());
+    }
+    return backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, stream);
+}
+
+const char *hqr_status_string(int status)
+{
+    switch (status) {
+    case 0: return "success";
+    case HQR_ENOMEM: return "workspace too small or allocation failed";
+    case HQR_EDEVICE: return "a HIP call failed";
+    case HQR_ENOTSUP: return "shape or option combination not supported";
+    case HQR_INFO_TIMEOUT: return "a bounded cross-workgroup wait expired";
+    case HQR_INFO_NOCONV: return "refinement did not converge; FP64 fallback used";
+    default: break;
+    }
+    if (status < 0 && status > -100) return "invalid argument";
+    if (status > 0) return "zero diagonal entry of R (info = k+1)";
+    return "unknown status";
+}
+
+const char *hqr_version(void) { return "hqr-mi355x 0.1 (gfx950)"; }
+
+} // extern "C"

@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libhqr (include/hqr.h).
+
+Argument marshalling only: every step of the factorization, Q^T B and the
+back-substitution runs in libhqr's HIP kernels.  PyTorch supplies device
+memory and the current stream.  Matrices are float64 CUDA tensors in
+column-major layout (stride (1, ld)); ``colmajor`` and ``empty_colmajor``
+build such tensors.  There is no fallback: if libhqr.so is missing or no GPU
+is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhqr.so")
+
+HQR_ENOMEM = -1001
+HQR_EDEVICE = -1002
+HQR_ENOTSUP = -1003
+HQR_INFO_TIMEOUT = -2001
+HQR_INFO_NOCONV = 1 << 29
+HQR_PREC_FP64 = 0
+HQR_PREC_MIXED = 1
+
+EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_backsolve",
+           "qr_lsq_solve", "hqr_status_string", "hqr_version")
+
+
+class HQRError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__("%s failed: status %d (%s)" % (fn, status, status_string(status)))
+
+
+class hqr_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhqr.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libhqr.so not built: run __graft_entry__.build() (%s)" % path)
+    lib = ctypes.CDLL(path)
+    i64, vp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
+    lib.hqr_workspace_size.argtypes = [i64, i64, i64, ctypes.c_int]
+    lib.hqr_workspace_size.restype = i64
+    lib.qr_factor.argtypes = [i64, i64, vp, i64, vp, vp, i64, ip, vp]
+    lib.qr_apply_qt.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]
+    lib.qr_backsolve.argtypes = [i64, i64, vp, i64, vp, i64, ip, vp]
+    lib.qr_lsq_solve.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp,
+                                 ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
+    for fn in ("qr_factor", "qr_apply_qt", "qr_backsolve", "qr_lsq_solve"):
+        getattr(lib, fn).restype = ctypes.c_int
+    lib.hqr_status_string.argtypes = [ctypes.c_int]
+    lib.hqr_status_string.restype = ctypes.c_char_p
+    lib.hqr_version.argtypes = []
+    lib.hqr_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().hqr_status_string(int(status)).decode()
+    except ImportError:
+        return "libhqr not loaded"
+
+
+def version() -> str:
+    return load().hqr_version().decode()
+
+
+# ------------------------------------------------------------ tensor helpers
+def _torch():
+    import torch
+    return torch
+
+
+def empty_colmajor(m: int, n: int, ld: Optional[int] = None, device="cuda", dtype=None):
+    """Uninitialised m x n column-major tensor with leading dimension ld >= m."""
+    torch = _torch()
+    ld = max(1, m) if ld is None else ld
+    if ld < max(1, m):
+        raise ValueError("ld < m")
+    dtype = torch.float64 if dtype is None else dtype
+    base = torch.empty((max(n, 1), ld), device=device, dtype=dtype)
+    return base.t()[:m, :n]
+
+
+def colmajor(a, ld: Optional[int] = None, device="cuda"):
+    """Copy a 1-D/2-D array or tensor into a column-major float64 tensor."""
+    torch = _torch()
+    t = torch.as_tensor(a, dtype=torch.float64)
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    m, n = t.shape
+    out = empty_colmajor(m, n, ld, device=device)
+    out.copy_(t.to(device))
+    return out
+
+
+def _ld(t, name):
+    """Leading dimension of a column-major 2-D float64 device tensor."""
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if t.dtype != _torch().float64:
+        raise TypeError("%s must be float64" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    m, n = t.shape
+    if m > 1 and t.stride(0) != 1:
+        raise ValueError("%s must be column-major (stride(0) == 1)" % name)
+    ld = t.stride(1) if n > 1 else max(m, 1)
+    if ld < max(m, 1):
+        raise ValueError("%s: leading dimension smaller than its rows" % name)
+    return ld
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _int_dev(t, device):
+    torch = _torch()
+    return torch.zeros(1, dtype=torch.int32, device=device) if t is None else t
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise HQRError(fn, rc)
+
+
+# ----------------------------------------------------------- the entry points
+def workspace_size(m: int, n: int, nrhs: int = 0, precision: int = HQR_PREC_FP64) -> int:
+    r = load().hqr_workspace_size(m, n, nrhs, precision)
+    if r < 0:
+        raise HQRError("hqr_workspace_size", int(r))
+    return int(r)
+
+
+def qr_factor(A, up=None, info=None, work=None, stream=None):
+    """Factor A (m x n, column-major float64 device tensor) in place.
+
+    Returns (up, info): up holds the reflectors' leading components, info a
+    device int32 tensor (0 or HQR_INFO_TIMEOUT)."""
+    torch = _torch()
+    lib = load()
+    m, n = A.shape
+    lda = _ld(A, "A")
+    if up is None:
+        up = torch.empty(max(n, 1), dtype=torch.float64, device=A.device)
+    info = _int_dev(info, A.device)
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("qr_factor", lib.qr_factor(m, n, _ptr(A), lda, _ptr(up), _ptr(work), lw, _ptr(info), _stream(stream)))
+    return up, info
+
+
+def qr_apply_qt(A, up, B, work=None, stream=None):
+    """B <- Q^T B in place using the output of qr_factor."""
+    lib = load()
+    m, n = A.shape
+    mb, nrhs = B.shape
+    if mb != m:
+        raise ValueError("B must have m rows")
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("qr_apply_qt", lib.qr_apply_qt(m, n, nrhs, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(B), _ld(B, "B"),
+                                          _ptr(work), lw, _stream(stream)))
+    return B
+
+
+def qr_backsolve(R, B, info=None, stream=None):
+    """B[0:n] <- R^{-1} B[0:n] with R the upper triangle of the n x n view R."""
+    lib = load()
+    n = R.shape[1]
+    if R.shape[0] < n or B.shape[0] < n:
+        raise ValueError("R must be at least n x n and B at least n rows")
+    info = _int_dev(info, B.device)
+    _check("qr_backsolve", lib.qr_backsolve(n, B.shape[1], _ptr(R), _ld(R, "R"), _ptr(B), _ld(B, "B"),
+                                            _ptr(info), _stream(stream)))
+    return B, info
+
+
+def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=HQR_PREC_FP64,
+                 tol=0.0, max_iter=-1, A_orig=None, work=None, stream=None):
+    """Least squares in place: A factored, B[0:n] <- x, returns (up, resnorm, info, iters)."""
+    torch = _torch()
+    lib = load()
+    m, n = A.shape
+    mb, nrhs = B.shape
+    if mb != m:
+        raise ValueError("B must have m rows")
+    dev = A.device
+    if up is None:
+        up = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    if resnorm is None:
+        resnorm = torch.empty(max(nrhs, 1), dtype=torch.float64, device=dev)
+    info = _int_dev(info, dev)
+    iters = _int_dev(iters, dev)
+    opts = hqr_opts(int(precision), float(tol), int(max_iter))
+    lda_o = _ld(A_orig, "A_orig") if A_orig is not None else max(1, m)
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("qr_lsq_solve", lib.qr_lsq_solve(m, n, nrhs, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(B), _ld(B, "B"),
+                                            _ptr(resnorm), ctypes.byref(opts), _ptr(A_orig), lda_o,
+                                            _ptr(work), lw, _ptr(info), _ptr(iters), _stream(stream)))
+    return up, resnorm, info, iters

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Every case prints the entry point, shape and seed before its GPU work so a
+failing run names its case.  Tolerances:
+  * factored matrix: element-wise 50 n u kappa ||A||_2 (two backward-stable
+    Householder factorizations with the same sign convention);
+  * x: the LSQ perturbation bound 50 n u kappa (1 + kappa ||r||/(||A|| ||x||))
+    against the oracle's x;
+  * LSQ orthogonality ||A^T r|| / (||A|| (||A|| ||x|| + ||b||)) <= 50 n u;
+  * integers (info) and identity reflectors (up == 0) bit-exact.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_09463_amd import workloads
+from tests.gpu_util import (U, check_reflector_invariants, factor_tol, lsq_forward_bound,
+                            lsq_orthogonality, to_dev, to_host)
+from tests.test_oracle_pins import CASES, _col
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hqr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2506_09463_amd as h
+    h.load()
+    return h
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _run_lsq(hqr, A, B, ld_pad=0):
+    import torch
+    m, n = A.shape
+    dA = to_dev(A, ld=m + ld_pad)
+    dB = to_dev(B, ld=m + ld_pad)
+    up, res, info, it = hqr.qr_lsq_solve(dA, dB)
+    torch.cuda.synchronize()
+    return to_host(dA), to_host(up)[:n], to_host(dB), to_host(res), int(info.item())
+
+
+# --------------------------------------------------- closed-form examples
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_worked_examples_on_gpu(hqr, name):
+    c = CASES[name]
+    A = np.array([[float(v) for v in r] for r in c["A"]])
+    b = np.array([float(v) for v in _col(c["b"])]).reshape(-1, 1)
+    _say("qr_lsq_solve worked example", name, A.shape)
+    F, up, X, res, info = _run_lsq(hqr, A, b)
+    m, n = A.shape
+    assert info == 0
+    for i in range(m):
+        for j in range(n):
+            assert abs(F[i, j] - float(c["F"][i][j])) <= 32 * U * 20
+    for k in range(n):
+        assert abs(up[k] - float(c["up"][0][k])) <= 32 * U * 20
+        assert (up[k] == 0.0) == (c["up"][0][k] == 0)
+    for j in range(n):
+        assert abs(X[j, 0] - float(_col(c["x"])[j])) <= 32 * U * 4
+    assert abs(res[0] - float(c["resnorm"][0][0])) <= 32 * U * 4
+
+
+# ------------------------------------------- element-wise parity vs oracle
+SHAPES = [
+    # (m, n, nrhs, seed) -- single-workgroup path
+    (1, 1, 1, 31), (2, 1, 1, 32), (7, 7, 2, 33), (64, 64, 1, 34), (128, 64, 1, 1),
+    (128, 127, 1, 35), (200, 100, 3, 36), (256, 64, 8, 37),
+    # blocked path: several panels, ragged panel and tile tails, TRSV groups
+    (300, 70, 1, 41), (513, 200, 9, 42), (1000, 333, 2, 43), (1536, 700, 1, 44),
+    (640, 640, 1, 45),
+]
+
+
+@pytest.mark.parametrize("m,n,nrhs,seed", SHAPES)
+def test_lsq_parity(hqr, oracle_mod, m, n, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    A = np.asfortranarray(rng.standard_normal((m, n)))
+    B = np.asfortranarray(rng.standard_normal((m, nrhs)))
+    _say("qr_lsq_solve", (m, n, nrhs), "seed", seed)
+    F, up, X, res, info = _run_lsq(hqr, A, B, ld_pad=3)
+    Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, B)
+    assert info == infoo == 0
+    tol = factor_tol(A)
+    assert np.abs(F - Fo).max() <= tol
+    assert np.array_equal(up == 0.0, upo == 0.0)
+    assert np.abs(up - upo).max() <= tol
+    check_reflector_invariants(A, F, up)
+    for c in range(nrhs):
+        x, xo = X[:n, c], Xo[:, c]
+        r = B[:, c] - A @ xo
+        bound = lsq_forward_bound(A, xo, r)
+        assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 2 * bound
+        assert lsq_orthogonality(A, x, B[:, c]) <= 50 * n * U
+        assert abs(res[c] - reso[c]) <= 50 * m * U * max(reso[c], 1e-300) + tol
+        assert abs(res[c] - np.linalg.norm(B[:, c] - A @ x)) <= 1e-9 * max(1.0, res[c])
+
+
+@pytest.mark.parametrize("m,n,nrhs,seed", [(128, 64, 1, 51), (300, 70, 2, 52), (1000, 333, 3, 53)])
+def test_factor_apply_backsolve_split(hqr, oracle_mod, m, n, nrhs, seed):
+    """qr_factor, qr_apply_qt, qr_backsolve called one by one."""
+    import torch
+    rng = np.random.default_rng(seed)
+    A = np.asfortranarray(rng.standard_normal((m, n)))
+    B = np.asfortranarray(rng.standard_normal((m, nrhs)))
+    _say("qr_factor/qr_apply_qt/qr_backsolve", (m, n, nrhs))
+    dA, dB = to_dev(A), to_dev(B)
+    up, info = hqr.qr_factor(dA)
+    hqr.qr_apply_qt(dA, up, dB)
+    qtb = to_host(dB).copy()
+    _, info2 = hqr.qr_backsolve(dA[:n, :n], dB)
+    torch.cuda.synchronize()
+    F, upn = to_host(dA), to_host(up)[:n]
+    Fo, upo = oracle_mod.qr_factor(A)
+    tol = factor_tol(A)
+    assert int(info.item()) == 0 and int(info2.item()) == 0
+    assert np.abs(F - Fo).max() <= tol
+    qtbo = oracle_mod.apply_qt(Fo, upo, B)
+    assert np.abs(qtb - qtbo).max() <= tol * max(1.0, np.abs(B).max())
+    Xo, _ = oracle_mod.backsolve(Fo, qtbo)
+    X = to_host(dB)[:n]
+    for c in range(nrhs):
+        r = B[:, c] - A @ Xo[:, c]
+        assert np.linalg.norm(X[:, c] - Xo[:, c]) / np.linalg.norm(Xo[:, c]) <= 2 * lsq_forward_bound(A, Xo[:, c], r)
+
+
+@pytest.mark.parametrize("m,n", [(128, 64), (700, 300)])
+def test_deterministic(hqr, m, n):
+    """Same input, same launch configuration: bitwise identical results."""
+    rng = np.random.default_rng(61)
+    A = rng.standard_normal((m, n))
+    B = rng.standard_normal((m, 2))
+    _say("determinism", (m, n))
+    r1 = _run_lsq(hqr, A, B)
+    r2 = _run_lsq(hqr, A, B)
+    for a, b in zip(r1[:4], r2[:4]):
+        assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------ edge cases
+@pytest.mark.parametrize("m,n", [(9, 5), (400, 150)])
+def test_zero_column_identity(hqr, oracle_mod, m, n):
+    rng = np.random.default_rng(71)
+    A = rng.standard_normal((m, n))
+    A[:, 1] = 0.0
+    B = rng.standard_normal((m, 1))
+    _say("zero column", (m, n))
+    dA = to_dev(A)
+    up, info = hqr.qr_factor(dA)
+    F, upn = to_host(dA), to_host(up)[:n]
+    Fo, upo = oracle_mod.qr_factor(A)
+    assert upn[1] == 0.0 and upo[1] == 0.0
+    assert np.array_equal(upn == 0.0, upo == 0.0)
+    assert np.abs(F - Fo).max() <= 1e-10 * np.abs(A).max() * m
+
+
+@pytest.mark.parametrize("m,n", [(6, 4), (300, 130)])
+def test_singular_info(hqr, oracle_mod, m, n):
+    rng = np.random.default_rng(72)
+    A = rng.standard_normal((m, n))
+    A[:, 2] = 0.0                      # R[2][2] == 0 exactly
+    B = rng.standard_normal((m, 1))
+    _say("singular", (m, n))
+    F, up, X, res, info = _run_lsq(hqr, A, B)
+    Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, B)
+    assert info == infoo == 3
+    qtbo = oracle_mod.apply_qt(Fo, upo, B)
+    assert np.abs(X[:, 0] - qtbo[:, 0]).max() <= 1e-10 * m   # B left as Q^T B
+
+
+@pytest.mark.parametrize("m,n", [(10, 4), (300, 80)])
+def test_tiny_column_scaled_norm(hqr, oracle_mod, m, n):
+    """A column of magnitude 1e-145 takes the scaled-norm branch (largest
+    entry below 2^-460) on both paths."""
+    rng = np.random.default_rng(73)
+    A = rng.standard_normal((m, n))
+    A[:, 0] *= 1e-145
+    _say("tiny column", (m, n))
+    dA = to_dev(A)
+    up, info = hqr.qr_factor(dA)
+    F = to_host(dA)
+    Fo, upo = oracle_mod.qr_factor(A)
+    assert np.isfinite(F).all() and np.isfinite(Fo).all()
+    assert abs(F[0, 0] - Fo[0, 0]) <= 1e-13 * abs(Fo[0, 0])
+    R, Ro = np.triu(F[:n]), np.triu(Fo[:n])
+    assert np.abs(R[:, 1:] - Ro[:, 1:]).max() <= 1e-10 * np.abs(A[:, 1:]).max() * m
+
+
+def test_underflowing_b_matches_oracle(hqr, oracle_mod):
+    """Below ~1e-154 the product b = up * R_kk underflows; both paths then
+    produce the same pattern of non-finite values."""
+    rng = np.random.default_rng(75)
+    A = rng.standard_normal((10, 4))
+    A[:, 0] *= 1e-165
+    _say("underflowing b", A.shape)
+    dA = to_dev(A)
+    hqr.qr_factor(dA)
+    F = to_host(dA)
+    Fo, _ = oracle_mod.qr_factor(A)
+    assert np.array_equal(np.isfinite(F), np.isfinite(Fo))
+
+
+def test_nan_propagates(hqr):
+    rng = np.random.default_rng(74)
+    A = rng.standard_normal((20, 6))
+    A[5, 2] = np.nan
+    _say("nan", A.shape)
+    dA = to_dev(A)
+    hqr.qr_factor(dA)
+    F = to_host(dA)
+    assert np.isnan(F[:, 2:]).any() and np.isfinite(F[:, :2]).all()
+
+
+def test_argument_errors(hqr):
+    import torch
+    dA = to_dev(np.ones((3, 4)))
+    with pytest.raises(hqr.HQRError) as e:
+        hqr.qr_factor(dA)
+    assert e.value.status == -2
+    dA = to_dev(np.ones((4, 3)))
+    dB = to_dev(np.ones((4, 1)))
+    up, info = hqr.qr_factor(dA)
+    torch.cuda.synchronize()
+    with pytest.raises(ValueError):
+        hqr.qr_apply_qt(dA, up, to_dev(np.ones((5, 1))))
+    hqr.qr_apply_qt(dA, up, dB)

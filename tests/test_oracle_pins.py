@@ -293,6 +293,14 @@ def test_tiny_column_uses_scaled_norm(oracle_mod):
     A[:, 0] *= 1e-165                    # squares underflow without scaling
     F, up = oracle_mod.qr_factor(A)
     assert abs(abs(F[0, 0]) - np.linalg.norm(A[:, 0] * 1e165) * 1e-165) <= 1e-13 * abs(F[0, 0])
+    # b = up * R_00 ~ 1e-330 underflows, so the stored representation of the
+    # paper cannot apply this reflector: the trailing columns turn non-finite
+    assert not np.isfinite(F[:, 1:]).all()
+    A2 = workloads.gaussian(8, 3, seed=24)
+    A2[:, 0] *= 1e-145                   # b ~ 1e-290 is still representable
+    F2, _ = oracle_mod.qr_factor(A2)
+    assert np.isfinite(F2).all()
+    assert np.allclose(np.abs(np.triu(F2[:3])[1:, 1:]), np.abs(np.linalg.qr(A2[:, 1:] - np.outer(A2[:, 0], A2[:, 0] @ A2[:, 1:]) / (A2[:, 0] @ A2[:, 0]), mode="r")), rtol=1e-8)
 
 
 # ------------------------------------------------------ planted mistakes
