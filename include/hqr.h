@@ -114,6 +114,19 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
                  void *work, int64_t lwork, int *info, int *iters,
                  hipStream_t stream);
 
+/* Kernel timing for measurement.  hqr_profile_begin() starts recording: every
+ * kernel the library launches afterwards (on any stream) is bracketed by a
+ * pair of HIP events on that stream, grouped by kernel class.
+ * hqr_profile_end() stops recording, synchronizes on the recorded events and
+ * adds each class's summed elapsed milliseconds and launch count into
+ * ms[0..nclass) and count[0..nclass) (either may be NULL).  It returns the
+ * number of classes the library knows (or a negative status); class names
+ * come from hqr_profile_class().  Process-global and not thread-safe; the
+ * events add launch overhead, so time throughput with profiling off. */
+int hqr_profile_begin(void);
+int hqr_profile_end(int nclass, double *ms, int64_t *count);
+const char *hqr_profile_class(int cls);
+
 /* Text of a host status or device info code (static storage). */
 const char *hqr_status_string(int status);
 

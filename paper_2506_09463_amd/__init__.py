@@ -7,6 +7,7 @@ CPU implementation.
 from .hqr import (  # noqa: F401
     EXPORTS, HQR_EDEVICE, HQR_ENOMEM, HQR_ENOTSUP, HQR_INFO_NOCONV, HQR_INFO_TIMEOUT,
     HQR_PREC_FP64, HQR_PREC_MIXED, HQRError, colmajor, empty_colmajor, load,
-    qr_apply_qt, qr_backsolve, qr_factor, qr_lsq_solve, status_string, version,
+    profile_begin, profile_end, qr_apply_qt, qr_backsolve, qr_factor, qr_lsq_solve,
+    status_string, version,
     workspace_size,
 )

@@ -68,21 +68,26 @@ __global__ void __launch_bounds__(256) panel_col_kernel(PanelArgs p)
         const int par = kp & 1;
         const double *X = p.xbuf + (size_t)par * p.nchunk * PW;
         const double *prow = p.pbuf + (size_t)par * NB;
-        // reduced partials, same order in every workgroup
-        double d_j = 0.0;
-        if (tid < bw) {
-            for (int q = 0; q < p.nchunk; ++q) d_j += X[(size_t)q * PW + tid];
-        }
-        if (tid == 0) {
-            double ssq = 0.0, mx = 0.0, nz = 0.0;
-            for (int q = 0; q < p.nchunk; ++q) {
-                ssq += X[(size_t)q * PW + kp];
-                mx = fmax(mx, X[(size_t)q * PW + NB]);
-                nz += X[(size_t)q * PW + NB + 1];
+        // reduced partials, same order in every workgroup: thread (value v,
+        // quarter g4) sums chunks q = g4, g4+4, ...; quarters then summed 0..3
+        for (int t = tid; t < 4 * PW; t += 256) {
+            const int v = t % PW, g4 = t / PW;
+            double acc4 = 0.0;
+            if (v == NB) {
+                for (int q = g4; q < p.nchunk; q += 4) acc4 = fmax(acc4, X[(size_t)q * PW + v]);
+            } else {
+#pragma unroll 4
+                for (int q = g4; q < p.nchunk; q += 4) acc4 += X[(size_t)q * PW + v];
             }
-            scal[0] = ssq;
-            scal[1] = mx;
-            scal[2] = nz;
+            red[g4][v] = acc4;
+        }
+        __syncthreads();
+        double d_j = 0.0;
+        if (tid < bw) d_j = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+        if (tid == 0) {
+            scal[0] = ((red[0][kp] + red[1][kp]) + red[2][kp]) + red[3][kp];
+            scal[1] = fmax(fmax(red[0][NB], red[1][NB]), fmax(red[2][NB], red[3][NB]));
+            scal[2] = ((red[0][NB + 1] + red[1][NB + 1]) + red[2][NB + 1]) + red[3][NB + 1];
         }
         __syncthreads();
         const double x0 = prow[kp];
@@ -210,37 +215,94 @@ HQR_DEV double x_elem(const VtxArgs &p, int64_t gi, int x)
     return HQR_AT(p.B, gi, x - p.ncA, p.ldb);
 }
 
-// grid: (ceil(nx/64), nsplit); 256 threads.  Output tile: 64 reflectors x 64
-// X columns.  Wave w owns reflector rows [16w, 16w+16), all four column tiles.
+// grid: (ceil(nx/128), nsplit); 256 threads.  Output tile: 64 reflectors x
+// 128 X columns over the rows of one split.  Wave w owns reflector rows
+// [16w, 16w+16) and all eight 16-column tiles.  Row chunks of KC rows are
+// staged in LDS ([row][col]); the next chunk is prefetched into registers
+// while the current one is multiplied.
+constexpr int VTX_COLS = 128;
+
 __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
 {
     __shared__ double Vs[KC][NB + 1];
-    __shared__ double Xs[KC][64 + 1];
+    __shared__ double Xs[KC][VTX_COLS + 1];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int x0 = blockIdx.x * 64;
+    const int x0 = blockIdx.x * VTX_COLS;
     const int64_t r_begin = (int64_t)p.c0 + (int64_t)blockIdx.y * p.split_rows;
     const int64_t r_end = min<int64_t>(p.m, r_begin + p.split_rows);
 
-    f64x4 acc[4];
+    f64x4 acc[8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 8; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
-        // stage: column-major global -> [row][col] LDS, consecutive threads
-        // walk down a column
-        for (int idx = tid; idx < KC * NB; idx += 256) {
-            const int c = idx / KC, r = idx - c * KC;
-            const int64_t gi = r0 + r;
-            Vs[r][c] = (gi < r_end && c < p.bw) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : 0.0;
-            Xs[r][c] = (gi < r_end) ? x_elem(p, gi, x0 + c) : 0.0;
-        }
-        __syncthreads();
+    // staging layout: thread t loads rows (t % KC) of columns t / KC + 8 q
+    constexpr int VPT = KC * NB / 256;       // V elements per thread
+    constexpr int XPT = KC * VTX_COLS / 256; // X elements per thread
+    const int sr = tid % KC, sc = tid / KC;  // sc in [0, 8)
+    double vreg[VPT], xreg[XPT];
+    // column pointers (nullptr: zero column); a column flagged in vmask is a
+    // V column and is read through the triangle mask near the pivot rows
+    const double *vcol[VPT];
+    const double *xcol[XPT];
+    unsigned xvmask = 0u;
 #pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+        const int c = sc + 8 * q;
+        vcol[q] = (c < p.bw) ? p.A + (size_t)(p.c0 + c) * p.lda : nullptr;
+    }
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+        int x = x0 + sc + 8 * q;
+        const double *ptr = nullptr;
+        if (x < p.nx) {
+            if (p.with_v && x < p.bw) {
+                ptr = p.A + (size_t)(p.c0 + x) * p.lda;
+                xvmask |= 1u << q;
+            } else {
+                if (p.with_v) x -= p.bw;
+                ptr = (x < p.ncA) ? p.A + (size_t)(p.c0 + p.bw + x) * p.lda : p.B + (size_t)(x - p.ncA) * p.ldb;
+            }
+        }
+        xcol[q] = ptr;
+    }
+    const int64_t tri_end = (int64_t)p.c0 + p.bw; // rows below need no mask
+    auto fetch = [&](int64_t r0) {
+        const int64_t gi = r0 + sr;
+        const bool ok = gi < r_end;
+        if (r0 < tri_end) {
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) {
+                const int c = sc + 8 * q;
+                vreg[q] = (ok && vcol[q]) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < XPT; ++q) {
+                const int c = x0 + sc + 8 * q;
+                double v = 0.0;
+                if (ok && xcol[q]) v = ((xvmask >> q) & 1u) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : xcol[q][gi];
+                xreg[q] = v;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < VPT; ++q) vreg[q] = (ok && vcol[q]) ? vcol[q][gi] : 0.0;
+#pragma unroll
+            for (int q = 0; q < XPT; ++q) xreg[q] = (ok && xcol[q]) ? xcol[q][gi] : 0.0;
+        }
+    };
+    if (r_begin < r_end) fetch(r_begin);
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) Vs[sr][sc + 8 * q] = vreg[q];
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) Xs[sr][sc + 8 * q] = xreg[q];
+        __syncthreads();
+        if (r0 + KC < r_end) fetch(r0 + KC);
+#pragma unroll 2
         for (int kk = 0; kk < KC; kk += 4) {
             const int kr = kk + (lane >> 4);
             const double a = Vs[kr][16 * w + (lane & 15)];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+            for (int t = 0; t < 8; ++t) {
                 const double b = Xs[kr][16 * t + (lane & 15)];
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
             }
@@ -250,7 +312,7 @@ __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
     // D[i][j] at lane j + 16*(i%4), register i/4
     double *out = p.wpart + (size_t)blockIdx.y * NB * p.nxpad;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 8; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = 16 * w + 4 * r + (lane >> 4);
@@ -282,8 +344,10 @@ __global__ void __launch_bounds__(256) tfactor_kernel(TArgs p)
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, j = idx - i * NB;
         double s = 0.0;
-        if (i < p.bw && j < p.bw)
+        if (i < p.bw && j < p.bw) {
+#pragma unroll 8
             for (int q = 0; q < p.nsplit; ++q) s += p.wpart[(size_t)q * NB * p.nxpad + (size_t)i * p.nxpad + j];
+        }
         G[i][j] = s;
         Ts[i][j] = 0.0;
     }
@@ -326,29 +390,39 @@ struct WArgs {
     double *wp;           // [NB][nxpad] row-major, same column indexing
 };
 
+// grid: ceil(ncols/WS_COLS); 256 threads, WS_COLS columns per workgroup.
+constexpr int WS_COLS = 16;
+
 __global__ void __launch_bounds__(256) wsolve_kernel(WArgs p)
 {
-    __shared__ double Ws[NB][64 + 1];
+    __shared__ double Ws[NB][WS_COLS + 1];
     __shared__ double Ts[NB][NB + 1];
     const int tid = threadIdx.x;
-    const int xb = p.xoff + blockIdx.x * 64;
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx / NB, j = idx - i * NB;
-        Ts[i][j] = p.T[idx];
-    }
-    for (int idx = tid; idx < NB * 64; idx += 256) {
-        const int i = idx / 64, c = idx - i * 64;
+    const int xb = p.xoff + blockIdx.x * WS_COLS;
+    const int xe = p.xoff + p.ncols;
+    for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx / NB][idx % NB] = p.T[idx];
+    // 1024 partial sums: thread t reduces elements (i = t / 4 + 64 q?) -- four per thread
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {
+        const int e = tid + 256 * e4;          // e in [0, 1024)
+        const int i = e / WS_COLS, c = e % WS_COLS;
         const int x = xb + c;
         double s = 0.0;
-        if (i < p.bw && x < p.xoff + p.ncols)
-            for (int q = 0; q < p.nsplit; ++q) s += p.wpart[(size_t)q * NB * p.nxpad + (size_t)i * p.nxpad + x];
+        if (i < p.bw && x < xe) {
+            const double *src = p.wpart + (size_t)i * p.nxpad + x;
+            const size_t stride = (size_t)NB * p.nxpad;
+#pragma unroll 8
+            for (int q = 0; q < p.nsplit; ++q) s += src[q * stride];
+        }
         Ws[i][c] = s;
     }
     __syncthreads();
-    for (int idx = tid; idx < NB * 64; idx += 256) {
-        const int i = idx / 64, c = idx - i * 64;
+#pragma unroll
+    for (int e4 = 0; e4 < 4; ++e4) {
+        const int e = tid + 256 * e4;
+        const int i = e / WS_COLS, c = e % WS_COLS;
         const int x = xb + c;
-        if (x >= p.xoff + p.ncols) continue;
+        if (x >= xe) continue;
         double s = 0.0;
         for (int l = 0; l <= i && l < p.bw; ++l) s += Ts[l][i] * Ws[l][c];
         p.wp[(size_t)i * p.nxpad + x] = (i < p.bw) ? s : 0.0;
@@ -379,52 +453,74 @@ HQR_DEV double *col_ptr(const UpdArgs &p, int c)
     return p.B + (size_t)(c - p.ncA) * p.ldb;
 }
 
+// grid: (ceil(rows/128), ceil(ncols/128)); 256 threads.  Wave (wr, wc)
+// owns rows [128 bx + 64 wr, +64) x columns [128 by + 64 wc, +64) and keeps
+// that 64 x 64 block of X^T in 16 MFMA accumulators.  The fragments of W'
+// and V are read straight from global memory (L2): each fragment load is
+// four 128-byte segments.
+constexpr int UPD_TILE = 128;
+
 __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
 {
-    __shared__ double Vs[64][NB + 1];   // [row][k]
-    __shared__ double Wt[NB][64 + 1];   // [k][col]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t rb = (int64_t)p.c0 + (int64_t)blockIdx.x * 64;
-    const int cb = blockIdx.y * 64;
+    const int wr = w & 1, wc = w >> 1;
+    const int64_t rb = (int64_t)p.c0 + (int64_t)blockIdx.x * UPD_TILE + 64 * wr;
+    const int cb = blockIdx.y * UPD_TILE + 64 * wc;
     const int ncols = p.ncA + p.nB;
+    if (rb >= p.m || cb >= ncols) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const bool masked = rb < (int64_t)p.c0 + p.bw; // rows that meet the triangle of V
 
-    for (int idx = tid; idx < 64 * NB; idx += 256) {
-        const int k = idx / 64, r = idx - k * 64;
-        const int64_t gi = rb + r;
-        Vs[r][k] = (gi < p.m && k < p.bw) ? v_elem(p.A, p.lda, p.up, p.c0, gi, k) : 0.0;
-        const int kk = idx / 64, c = idx - kk * 64;
-        Wt[kk][c] = (kk < p.bw && cb + c < ncols) ? p.wp[(size_t)kk * p.nxpad + p.xoff + cb + c] : 0.0;
-    }
-    // accumulators: wave w owns columns [16w, 16w+16) of the tile, 4 row tiles
-    f64x4 acc[4];
-    const int jl = 16 * w;
+    f64x4 acc[4][4]; // [column tile][row tile]
+    double *cptr[4][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int c = cb + jl + 4 * r + (lane >> 4);
-            const int64_t gi = rb + 16 * t + (lane & 15);
-            acc[t][r] = (c < ncols && gi < p.m) ? col_ptr(p, c)[gi] : 0.0;
+            const int c = cb + 16 * tj + 4 * r + lk;
+            cptr[tj][r] = (c < ncols) ? col_ptr(p, c) : nullptr;
         }
-    __syncthreads();
-#pragma unroll 4
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb + 16 * ti + li;
+                acc[tj][ti][r] = (cptr[tj][r] && gi < p.m) ? cptr[tj][r][gi] : 0.0;
+            }
+
+    const double *wrow = p.wp + p.xoff + cb + li;
+#pragma unroll 2
     for (int k0 = 0; k0 < NB; k0 += 4) {
-        const int kr = k0 + (lane >> 4);
-        const double a = -Wt[kr][jl + (lane & 15)];
+        const int k = k0 + lk;
+        double a[4], b[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const double b = Vs[16 * t + (lane & 15)][kr];
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        for (int tj = 0; tj < 4; ++tj) {
+            const int c = cb + 16 * tj + li;
+            a[tj] = (k < p.bw && c < ncols) ? -wrow[(size_t)k * p.nxpad + 16 * tj] : 0.0;
         }
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) {
+            const int64_t gi = rb + 16 * ti + li;
+            double v = 0.0;
+            if (k < p.bw && gi < p.m) v = masked ? v_elem(p.A, p.lda, p.up, p.c0, gi, k) : HQR_AT(p.A, gi, p.c0 + k, p.lda);
+            b[ti] = v;
+        }
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti) acc[tj][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tj], b[ti], acc[tj][ti], 0, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int c = cb + jl + 4 * r + (lane >> 4);
-            const int64_t gi = rb + 16 * t + (lane & 15);
-            if (c < ncols && gi < p.m) col_ptr(p, c)[gi] = acc[t][r];
-        }
+        for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = rb + 16 * ti + li;
+                if (cptr[tj][r] && gi < p.m) cptr[tj][r][gi] = acc[tj][ti][r];
+            }
 }
 
 // ------------------------------------------------------------ triangular
@@ -465,6 +561,7 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
     __shared__ double xs[64][TRSV_MAXRHS];
     __shared__ double accs[64][TRSV_MAXRHS];
     __shared__ double part[4][64][TRSV_MAXRHS];
+    __shared__ double Rd[64][65];
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
     if (*((volatile int *)p.info) != 0) return;
@@ -500,6 +597,7 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
         }
         __syncthreads();
         if (lane < nr) {
+#pragma unroll 4
             for (int l = g; l < nc; l += 4) {
                 const double rv = HQR_AT(p.A, r0 + lane, c0 + l, p.lda);
 #pragma unroll
@@ -515,16 +613,25 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
 #pragma unroll
     for (int c = 0; c < TRSV_MAXRHS; ++c) part[g][lane][c] = acc[c];
     __syncthreads();
-    // diagonal block on wave 0: lanes = rows
+    // diagonal block (staged in LDS) on wave 0: lanes = rows
+    for (int idx = tid; idx < nr * nr; idx += 256) {
+        const int cc = idx / nr, r = idx - cc * nr;
+        Rd[r][cc] = HQR_AT(p.A, r0 + r, r0 + cc, p.lda);
+    }
+    for (int idx = tid; idx < nr * nrhs; idx += 256) {
+        const int c = idx / nr, r = idx - c * nr;
+        accs[r][c] = HQR_AT(p.B, r0 + r, c, p.ldb);
+    }
+    __syncthreads();
     if (g == 0) {
         for (int c = 0; c < nrhs; ++c) {
             double t = 0.0;
             if (lane < nr)
-                t = HQR_AT(p.B, r0 + lane, c, p.ldb) - (((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c]);
+                t = accs[lane][c] - (((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c]);
             for (int i = nr - 1; i >= 0; --i) {
                 const double ti = readlane_f64(t, i);
-                const double xi = ti / HQR_AT(p.A, r0 + i, r0 + i, p.lda);
-                if (lane < i) t -= HQR_AT(p.A, r0 + lane, r0 + i, p.lda) * xi;
+                const double xi = ti / Rd[i][i];
+                if (lane < i) t -= Rd[lane][i] * xi;
                 if (lane == i) t = xi;
             }
             accs[lane][c] = t;

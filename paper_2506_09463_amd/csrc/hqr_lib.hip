@@ -12,8 +12,78 @@
 #include "hqr_device.hpp"
 #include "hqr_small.hpp"
 #include "hqr_blocked.hpp"
+#include "hqr_cqr.hpp"
 
 namespace hqr {
+
+// ------------------------------------------------------------- profiling
+// Optional per-kernel-class timing: while active, every launch is bracketed
+// by a pair of HIP events recorded on the launch's own stream.
+enum KClass {
+    K_SMALL, K_PANEL, K_VTX, K_TFACTOR, K_WSOLVE, K_UPDATE, K_DIAG, K_TRSV, K_RESNORM, K_FILL,
+    K_CQR_GRAM, K_CQR_CHOL, K_CQR_FINISH, K_PANEL_EXACT, K_GRED, K_NCLASS
+};
+static const char *kclass_name[K_NCLASS] = {"small_lsq", "panel_col", "vtx", "tfactor", "wsolve",
+                                            "update", "diag_check", "trsv", "resnorm", "fill",
+                                            "cqr_gram", "cqr_chol", "cqr_finish", "panel_exact",
+                                            "gram_reduce"};
+struct ProfRec {
+    int cls;
+    hipEvent_t e0, e1;
+};
+struct ProfState {
+    bool on = false;
+    ProfRec *recs = nullptr;
+    size_t n = 0, cap = 0;
+    hipEvent_t *pool = nullptr;
+    size_t pool_n = 0, pool_used = 0;
+};
+static ProfState g_prof;
+
+static hipEvent_t prof_event()
+{
+    if (g_prof.pool_used == g_prof.pool_n) {
+        size_t nn = g_prof.pool_n ? 2 * g_prof.pool_n : 1024;
+        hipEvent_t *np = (hipEvent_t *)realloc(g_prof.pool, nn * sizeof(hipEvent_t));
+        if (!np) return nullptr;
+        g_prof.pool = np;
+        for (size_t i = g_prof.pool_n; i < nn; ++i)
+            if (hipEventCreate(&g_prof.pool[i]) != hipSuccess) g_prof.pool[i] = nullptr;
+        g_prof.pool_n = nn;
+    }
+    return g_prof.pool[g_prof.pool_used++];
+}
+
+static hipEvent_t prof_begin(hipStream_t s)
+{
+    if (!g_prof.on) return nullptr;
+    hipEvent_t e = prof_event();
+    if (e) (void)hipEventRecord(e, s);
+    return e;
+}
+
+static void prof_end(int cls, hipEvent_t e0, hipStream_t s)
+{
+    if (!g_prof.on || !e0) return;
+    hipEvent_t e1 = prof_event();
+    if (!e1) return;
+    (void)hipEventRecord(e1, s);
+    if (g_prof.n == g_prof.cap) {
+        size_t nc = g_prof.cap ? 2 * g_prof.cap : 1024;
+        ProfRec *nr = (ProfRec *)realloc(g_prof.recs, nc * sizeof(ProfRec));
+        if (!nr) return;
+        g_prof.recs = nr;
+        g_prof.cap = nc;
+    }
+    g_prof.recs[g_prof.n++] = ProfRec{cls, e0, e1};
+}
+
+#define HQR_LAUNCH(cls, kern, grid, block, shmem, stream, ...)                     \
+    do {                                                                           \
+        hipEvent_t e0_ = prof_begin(stream);                                       \
+        hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);         \
+        prof_end(cls, e0_, stream);                                                \
+    } while (0)
 
 // ------------------------------------------------------------- small path
 typedef void (*small_fn)(SmallArgs);
@@ -61,7 +131,7 @@ static hipError_t launch_small(const SmallCfg *cfg, SmallArgs a, hipStream_t s)
     a.ldl = small_ldl(a.m);
     const size_t dyn = small_dyn_lds(a.m, a.n, a.nrhs);
     (void)hipFuncSetAttribute((const void *)cfg->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-    hipLaunchKernelGGL(cfg->fn, dim3(1), dim3(cfg->nw * 64), dyn, s, a);
+    HQR_LAUNCH(K_SMALL, cfg->fn, dim3(1), dim3(cfg->nw * 64), dyn, s, a);
     return hipGetLastError();
 }
 
@@ -72,6 +142,8 @@ struct Plan {
     int nxpad;       // row stride of W partials
     int nsplit_max;
     int nblk;        // triangular blocks
+    int ngroups;     // CholeskyQR row groups of the first panel (upper bound)
+    int npanels;
 };
 
 static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -83,9 +155,11 @@ static Plan make_plan(int64_t m, int64_t n, int64_t nrhs)
     p.n = n;
     p.nrhs = nrhs;
     p.nchunk = (int)((m + PC_ROWS - 1) / PC_ROWS);
-    p.nxpad = (int)rup(NB + n + nrhs, 64);
+    p.nxpad = (int)rup(NB + n + nrhs, 128);
     p.nsplit_max = 16;
     p.nblk = (int)((n + 63) / 64);
+    p.ngroups = (int)((m + CQR_ROWS - 1) / CQR_ROWS);
+    p.npanels = (int)((n + NB - 1) / NB);
     return p;
 }
 
@@ -93,6 +167,9 @@ struct Work {
     double *xbuf, *pbuf, *wpart, *T, *wp;
     int *flags;
     int *iscratch;
+    double *gpart, *r1, *r1inv, *winv, *G;
+    unsigned long long *mask, *mask_all;
+    int *pflag;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -112,7 +189,23 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *wp = take(sizeof(double) * NB * (size_t)p.nxpad);
     char *fl = take(sizeof(int) * (size_t)std::max(p.nblk, 1));
     char *is = take(sizeof(int) * 64);
+    char *gp = take(sizeof(double) * (size_t)p.ngroups * NB * NB);
+    char *r1 = take(sizeof(double) * NB * NB);
+    char *r1i = take(sizeof(double) * NB * NB);
+    char *wi = take(sizeof(double) * NB * NB);
+    char *mk = take(sizeof(unsigned long long) * (size_t)p.ngroups);
+    char *pf = take(sizeof(int) * (size_t)std::max(p.npanels, 1));
+    char *gg = take(sizeof(double) * NB * NB);
+    char *ma = take(sizeof(unsigned long long));
     if (w) {
+        w->G = (double *)gg;
+        w->mask_all = (unsigned long long *)ma;
+        w->gpart = (double *)gp;
+        w->r1 = (double *)r1;
+        w->r1inv = (double *)r1i;
+        w->winv = (double *)wi;
+        w->mask = (unsigned long long *)mk;
+        w->pflag = (int *)pf;
         w->xbuf = (double *)x;
         w->pbuf = (double *)pb;
         w->wpart = (double *)wpart;
@@ -139,7 +232,7 @@ static int pick_nsplit(int64_t rows, int ntiles, int nsplit_max)
 // Apply the compact-WY block of panel (c0, bw) to trailing A columns
 // [c0+bw, c0+bw+ncA) and all nB columns of B.
 static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t lda, double *B, int64_t ldb,
-                             const double *up, int c0, int bw, int ncA, int nB, hipStream_t s)
+                             const double *up, int c0, int bw, int ncA, int nB, bool have_t, hipStream_t s)
 {
     const int64_t rows = pl.m - c0;
     VtxArgs v;
@@ -153,29 +246,32 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
     v.bw = bw;
     v.ncA = ncA;
     v.nB = nB;
-    v.with_v = 1;
-    v.nx = bw + ncA + nB;
+    v.with_v = have_t ? 0 : 1;
+    const int vcols = have_t ? 0 : bw;
+    v.nx = vcols + ncA + nB;
     v.nxpad = pl.nxpad;
-    const int ntiles = (v.nx + 63) / 64;
+    const int ntiles = (v.nx + VTX_COLS - 1) / VTX_COLS;
     const int nsplit = pick_nsplit(rows, ntiles, pl.nsplit_max);
     v.split_rows = rup((rows + nsplit - 1) / nsplit, KC);
     const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
     v.wpart = w.wpart;
-    hipLaunchKernelGGL(vtx_kernel, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
+    HQR_LAUNCH(K_VTX, vtx_kernel, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
     HQR_CK(hipGetLastError());
 
-    TArgs t;
-    t.A = A;
-    t.lda = lda;
-    t.up = up;
-    t.c0 = c0;
-    t.bw = bw;
-    t.wpart = w.wpart;
-    t.nsplit = nsplit_eff;
-    t.nxpad = pl.nxpad;
-    t.T = w.T;
-    hipLaunchKernelGGL(tfactor_kernel, dim3(1), dim3(256), 0, s, t);
-    HQR_CK(hipGetLastError());
+    if (!have_t) {
+        TArgs t;
+        t.A = A;
+        t.lda = lda;
+        t.up = up;
+        t.c0 = c0;
+        t.bw = bw;
+        t.wpart = w.wpart;
+        t.nsplit = nsplit_eff;
+        t.nxpad = pl.nxpad;
+        t.T = w.T;
+        HQR_LAUNCH(K_TFACTOR, tfactor_kernel, dim3(1), dim3(256), 0, s, t);
+        HQR_CK(hipGetLastError());
+    }
 
     const int ncols = ncA + nB;
     if (ncols == 0) return 0;
@@ -183,12 +279,12 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
     wa.wpart = w.wpart;
     wa.nsplit = nsplit_eff;
     wa.nxpad = pl.nxpad;
-    wa.xoff = bw;
+    wa.xoff = vcols;
     wa.ncols = ncols;
     wa.bw = bw;
     wa.T = w.T;
     wa.wp = w.wp;
-    hipLaunchKernelGGL(wsolve_kernel, dim3((ncols + 63) / 64), dim3(256), 0, s, wa);
+    HQR_LAUNCH(K_WSOLVE, wsolve_kernel, dim3((ncols + WS_COLS - 1) / WS_COLS), dim3(256), 0, s, wa);
     HQR_CK(hipGetLastError());
 
     UpdArgs u;
@@ -202,39 +298,145 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
     u.bw = bw;
     u.ncA = ncA;
     u.nB = nB;
-    u.xoff = bw;
+    u.xoff = vcols;
     u.wp = w.wp;
     u.nxpad = pl.nxpad;
-    hipLaunchKernelGGL(update_kernel, dim3((unsigned)((rows + 63) / 64), (ncols + 63) / 64), dim3(256), 0, s, u);
+    HQR_LAUNCH(K_UPDATE, update_kernel, dim3((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols + UPD_TILE - 1) / UPD_TILE), dim3(256), 0, s, u);
     HQR_CK(hipGetLastError());
     return 0;
+}
+
+// Panel factorization by one launch per pivot (exact loop order).
+static int panel_percol(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw,
+                        hipStream_t s)
+{
+    PanelArgs pa;
+    pa.A = A;
+    pa.lda = lda;
+    pa.m = pl.m;
+    pa.c0 = c0;
+    pa.bw = bw;
+    pa.nchunk = (int)((pl.m - c0 + PC_ROWS - 1) / PC_ROWS);
+    pa.up = up;
+    pa.xbuf = w.xbuf;
+    pa.pbuf = w.pbuf;
+    for (int k = 0; k <= bw; ++k) {
+        pa.k = k;
+        HQR_LAUNCH(K_PANEL, panel_col_kernel, dim3(pa.nchunk), dim3(256), 0, s, pa);
+        HQR_CK(hipGetLastError());
+    }
+    return 0;
+}
+
+// Panel factorization by CholeskyQR2 + Householder reconstruction, with the
+// exact one-workgroup panel when the device flags the panel.  Leaves T (for
+// the stored vectors) in w.T.
+static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
+                     hipStream_t s)
+{
+    const int64_t mp = pl.m - c0;
+    int *flag = w.pflag + pidx;
+    CqrArgs g;
+    g.A = A;
+    g.lda = lda;
+    g.m = pl.m;
+    g.c0 = c0;
+    g.bw = bw;
+    g.ngroups = (int)((mp + CQR_ROWS - 1) / CQR_ROWS);
+    g.gpart = w.gpart;
+    g.mask = w.mask;
+    g.r1inv = w.r1inv;
+    g.flag = flag;
+    GredArgs gr;
+    gr.gpart = w.gpart;
+    gr.ngroups = g.ngroups;
+    gr.G = w.G;
+    gr.mask = w.mask;
+    gr.mask_all = w.mask_all;
+    gr.flag = flag;
+    CholArgs c;
+    c.A = A;
+    c.lda = lda;
+    c.m = pl.m;
+    c.c0 = c0;
+    c.bw = bw;
+    c.G = w.G;
+    c.mask_all = w.mask_all;
+    c.r1 = w.r1;
+    c.r1inv = w.r1inv;
+    c.winv = w.winv;
+    c.T = w.T;
+    c.up = up;
+    c.flag = flag;
+    for (int pass = 1; pass <= 2; ++pass) {
+        g.pass = pass;
+        c.pass = pass;
+        gr.with_mask = (pass == 1);
+        HQR_LAUNCH(K_CQR_GRAM, cqr_gram_kernel, dim3(g.ngroups), dim3(256), 0, s, g);
+        HQR_CK(hipGetLastError());
+        HQR_LAUNCH(K_GRED, gram_reduce_kernel, dim3(NB * NB / 64), dim3(256), 0, s, gr);
+        HQR_CK(hipGetLastError());
+        HQR_LAUNCH(K_CQR_CHOL, cqr_chol_kernel, dim3(1), dim3(256), 0, s, c);
+        HQR_CK(hipGetLastError());
+    }
+    if (mp > bw) {
+        FinArgs f;
+        f.A = A;
+        f.lda = lda;
+        f.m = pl.m;
+        f.c0 = c0;
+        f.bw = bw;
+        f.winv = w.winv;
+        f.flag = flag;
+        HQR_LAUNCH(K_CQR_FINISH, cqr_finish_kernel, dim3((unsigned)((mp - bw + 63) / 64)), dim3(256), 0, s, f);
+        HQR_CK(hipGetLastError());
+    }
+    ExactArgs e;
+    e.A = A;
+    e.lda = lda;
+    e.m = pl.m;
+    e.c0 = c0;
+    e.bw = bw;
+    e.up = up;
+    e.T = w.T;
+    e.flag = flag;
+    HQR_LAUNCH(K_PANEL_EXACT, panel_exact_kernel, dim3(1), dim3(1024), 0, s, e);
+    HQR_CK(hipGetLastError());
+    return 0;
+}
+
+enum PanelMode { PANEL_CQR = 0, PANEL_PERCOL = 1, PANEL_EXACT = 2 };
+
+static int panel_mode()
+{
+    const char *e = getenv("HQR_PANEL");
+    if (!e) return PANEL_CQR;
+    if (!strcmp(e, "percol")) return PANEL_PERCOL;
+    if (!strcmp(e, "exact")) return PANEL_EXACT;
+    return PANEL_CQR;
 }
 
 // Blocked factorization; B (nB columns) rides along as trailing columns.
 static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, double *B, int64_t ldb,
                           int nB, hipStream_t s)
 {
-    const int64_t m = pl.m, n = pl.n;
+    const int64_t n = pl.n;
+    const int mode = panel_mode();
+    if (mode != PANEL_PERCOL) {
+        // exact-only mode: every panel flagged up front
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(256), 0, s, w.pflag, mode == PANEL_EXACT ? 1 : 0,
+                   (int64_t)pl.npanels);
+        HQR_CK(hipGetLastError());
+    }
     for (int64_t c0 = 0; c0 < n; c0 += NB) {
         const int bw = (int)std::min<int64_t>(NB, n - c0);
-        PanelArgs pa;
-        pa.A = A;
-        pa.lda = lda;
-        pa.m = m;
-        pa.c0 = (int)c0;
-        pa.bw = bw;
-        pa.nchunk = (int)((m - c0 + PC_ROWS - 1) / PC_ROWS);
-        pa.up = up;
-        pa.xbuf = w.xbuf;
-        pa.pbuf = w.pbuf;
-        for (int k = 0; k <= bw; ++k) {
-            pa.k = k;
-            hipLaunchKernelGGL(panel_col_kernel, dim3(pa.nchunk), dim3(256), 0, s, pa);
-            HQR_CK(hipGetLastError());
-        }
+        const int pidx = (int)(c0 / NB);
+        int rc = (mode == PANEL_PERCOL) ? panel_percol(pl, w, A, lda, up, (int)c0, bw, s)
+                                        : panel_cqr(pl, w, A, lda, up, (int)c0, bw, pidx, s);
+        if (rc) return rc;
         const int ncA = (int)(n - c0 - bw);
         if (ncA + nB > 0) {
-            int rc = apply_panel_block(pl, w, A, lda, B, ldb, up, (int)c0, bw, ncA, nB, s);
+            rc = apply_panel_block(pl, w, A, lda, B, ldb, up, (int)c0, bw, ncA, nB, mode != PANEL_PERCOL, s);
             if (rc) return rc;
         }
     }
@@ -244,10 +446,10 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
 static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int64_t lda, double *B, int64_t ldb,
                              int nrhs, int *info, hipStream_t s)
 {
-    hipLaunchKernelGGL(diag_check_kernel, dim3(1), dim3(256), 0, s, A, lda, pl.n, info);
+    HQR_LAUNCH(K_DIAG, diag_check_kernel, dim3(1), dim3(256), 0, s, A, lda, pl.n, info);
     HQR_CK(hipGetLastError());
     for (int c = 0; c < nrhs; c += TRSV_MAXRHS) {
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(256), 0, s, w.flags, 0, (int64_t)pl.nblk);
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(256), 0, s, w.flags, 0, (int64_t)pl.nblk);
         HQR_CK(hipGetLastError());
         TrsvArgs t;
         t.A = A;
@@ -260,7 +462,7 @@ static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int
         t.info = info;
         t.epoch = 1;
         t.spin_limit = 20000000L;
-        hipLaunchKernelGGL(trsv_kernel, dim3(pl.nblk), dim3(256), 0, s, t);
+        HQR_LAUNCH(K_TRSV, trsv_kernel, dim3(pl.nblk), dim3(256), 0, s, t);
         HQR_CK(hipGetLastError());
     }
     return 0;
@@ -317,7 +519,7 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up, void *wo
     if (n > 0 && !up) return -5;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2) return HQR_ENOTSUP;
     if (n == 0) {
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
         return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
     }
     if (const SmallCfg *c = pick_small(m, n, 0)) {
@@ -338,7 +540,7 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up, void *wo
     Work w;
     int rc = get_work(pl, work, lwork, stream, g, &w);
     if (rc) return rc;
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
     HQR_CK(hipGetLastError());
     return factor_blocked(pl, w, A, lda, up, nullptr, 1, 0, stream);
 }
@@ -376,7 +578,7 @@ int qr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda
     if (rc) return rc;
     for (int64_t c0 = 0; c0 < n; c0 += NB) {
         const int bw = (int)std::min<int64_t>(NB, n - c0);
-        rc = apply_panel_block(pl, w, const_cast<double *>(A), lda, B, ldb, up, (int)c0, bw, 0, (int)nrhs, stream);
+        rc = apply_panel_block(pl, w, const_cast<double *>(A), lda, B, ldb, up, (int)c0, bw, 0, (int)nrhs, false, stream);
         if (rc) return rc;
     }
     return 0;
@@ -396,7 +598,7 @@ int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *
     }
     if (n > INT32_MAX / 2) return HQR_ENOTSUP;
     if (n == 0 || nrhs == 0) {
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
         return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
     }
     Plan pl = make_plan(n, n, nrhs);
@@ -433,14 +635,14 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
     (void)lda_orig;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
     if (iters) {
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
         HQR_CK(hipGetLastError());
     }
     if (n == 0) {
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
         HQR_CK(hipGetLastError());
         if (resnorm && nrhs > 0) {
-            hipLaunchKernelGGL(resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb,
+            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb,
                                (int64_t)0, m, resnorm);
             HQR_CK(hipGetLastError());
         }
@@ -466,17 +668,60 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
     Work w;
     int rc = get_work(pl, work, lwork, stream, g, &w);
     if (rc) return rc;
-    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
     HQR_CK(hipGetLastError());
     rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, stream);
     if (rc) return rc;
     if (nrhs == 0) return 0;
     if (resnorm) {
-        hipLaunchKernelGGL(resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb, n, m,
+        HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb, n, m,
                            resnorm);
         HQR_CK(hipGetLastError());
     }
     return backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, stream);
+}
+
+int hqr_profile_begin(void)
+{
+    g_prof.on = true;
+    g_prof.n = 0;
+    g_prof.pool_used = 0;
+    return 0;
+}
+
+int hqr_profile_end(int nclass, double *ms, int64_t *count)
+{
+    if (nclass < 0) return -1;
+    g_prof.on = false;
+    for (int c = 0; c < nclass; ++c) {
+        if (ms) ms[c] = 0.0;
+        if (count) count[c] = 0;
+    }
+    int rc = 0;
+    for (size_t i = 0; i < g_prof.n; ++i) {
+        const ProfRec &r = g_prof.recs[i];
+        if (hipEventSynchronize(r.e1) != hipSuccess) {
+            rc = HQR_EDEVICE;
+            continue;
+        }
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) {
+            rc = HQR_EDEVICE;
+            continue;
+        }
+        if (r.cls < nclass) {
+            if (ms) ms[r.cls] += (double)t;
+            if (count) count[r.cls] += 1;
+        }
+    }
+    g_prof.n = 0;
+    g_prof.pool_used = 0;
+    return rc ? rc : (int)K_NCLASS;
+}
+
+const char *hqr_profile_class(int cls)
+{
+    return (cls >= 0 && cls < (int)K_NCLASS) ? kclass_name[cls] : "";
 }
 
 const char *hqr_status_string(int status)

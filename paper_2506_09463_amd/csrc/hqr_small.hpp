@@ -169,16 +169,17 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
         const double b_k = up_k * s_k;
 
         double wj[Q];
+        bool act[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int j = lane + 64 * q;
-            const bool act = !skip && j < ntot && (factor ? j > k : j >= n);
+            act[q] = !skip && j < ntot && (factor ? j > k : j >= n);
             double d = 0.0;
-            if (act) {
+            if (act[q]) {
 #pragma unroll
                 for (int v = 0; v < NW; ++v) d += part[par][v][j];
             }
-            wj[q] = act ? (up_k * prow[par][j] + d) / b_k : 0.0;
+            wj[q] = act[q] ? (up_k * prow[par][j] + d) / b_k : 0.0;
         }
         const int k1 = k + 1;
         const bool have_next = k1 < n;
@@ -198,8 +199,10 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
             for (int q = 0; q < Q; ++q)
                 if (q == kq) vsrc = a[r][q];
             const double vi = (i == k) ? up_k : readlane_f64(vsrc, kl);
+            // select, not multiply by zero: finished columns must not pick
+            // up NaN/Inf from the reflector
 #pragma unroll
-            for (int q = 0; q < Q; ++q) a[r][q] += wj[q] * vi;
+            for (int q = 0; q < Q; ++q) a[r][q] = act[q] ? a[r][q] + wj[q] * vi : a[r][q];
             if (factor && i == k && lane == kl) {
 #pragma unroll
                 for (int q = 0; q < Q; ++q)

@@ -25,7 +25,8 @@ HQR_PREC_FP64 = 0
 HQR_PREC_MIXED = 1
 
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_backsolve",
-           "qr_lsq_solve", "hqr_status_string", "hqr_version")
+           "qr_lsq_solve", "hqr_profile_begin", "hqr_profile_end", "hqr_profile_class",
+           "hqr_status_string", "hqr_version")
 
 
 class HQRError(RuntimeError):
@@ -61,6 +62,12 @@ def load(path: str = LIB_PATH):
         getattr(lib, fn).restype = ctypes.c_int
     lib.hqr_status_string.argtypes = [ctypes.c_int]
     lib.hqr_status_string.restype = ctypes.c_char_p
+    lib.hqr_profile_begin.argtypes = []
+    lib.hqr_profile_begin.restype = ctypes.c_int
+    lib.hqr_profile_end.argtypes = [ctypes.c_int, vp, vp]
+    lib.hqr_profile_end.restype = ctypes.c_int
+    lib.hqr_profile_class.argtypes = [ctypes.c_int]
+    lib.hqr_profile_class.restype = ctypes.c_char_p
     lib.hqr_version.argtypes = []
     lib.hqr_version.restype = ctypes.c_char_p
     _lib = lib
@@ -217,3 +224,23 @@ def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=H
                                             _ptr(resnorm), ctypes.byref(opts), _ptr(A_orig), lda_o,
                                             _ptr(work), lw, _ptr(info), _ptr(iters), _stream(stream)))
     return up, resnorm, info, iters
+
+
+def profile_begin():
+    """Start per-kernel-class event timing inside libhqr."""
+    load().hqr_profile_begin()
+
+
+def profile_end(max_classes: int = 64):
+    """Stop timing; return {class name: (total ms, launches)} for classes used."""
+    lib = load()
+    ms = (ctypes.c_double * max_classes)()
+    cnt = (ctypes.c_int64 * max_classes)()
+    nc = lib.hqr_profile_end(max_classes, ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(cnt, ctypes.c_void_p))
+    if nc < 0:
+        raise HQRError("hqr_profile_end", nc)
+    out = {}
+    for c in range(min(nc, max_classes)):
+        if cnt[c]:
+            out[lib.hqr_profile_class(c).decode()] = (ms[c], int(cnt[c]))
+    return out

@@ -203,7 +203,8 @@ def test_underflowing_b_matches_oracle(hqr, oracle_mod):
     assert np.array_equal(np.isfinite(F), np.isfinite(Fo))
 
 
-def test_nan_propagates(hqr):
+def test_nan_propagates(hqr, oracle_mod):
+    """Single-workgroup path: exactly the oracle's pattern of NaN entries."""
     rng = np.random.default_rng(74)
     A = rng.standard_normal((20, 6))
     A[5, 2] = np.nan
@@ -211,7 +212,22 @@ def test_nan_propagates(hqr):
     dA = to_dev(A)
     hqr.qr_factor(dA)
     F = to_host(dA)
-    assert np.isnan(F[:, 2:]).any() and np.isfinite(F[:, :2]).all()
+    Fo, _ = oracle_mod.qr_factor(A)
+    assert np.array_equal(np.isnan(F), np.isnan(Fo))
+
+
+def test_nan_propagates_blocked(hqr):
+    """Blocked path: NaN reaches the solution.  The compact-WY contraction
+    multiplies the structural zeros of V by NaN, so more entries of R may turn
+    NaN than in the one-reflector-at-a-time order."""
+    rng = np.random.default_rng(76)
+    A = rng.standard_normal((300, 80))
+    A[150, 70] = np.nan
+    B = rng.standard_normal((300, 1))
+    _say("nan blocked", A.shape)
+    F, up, X, res, info = _run_lsq(hqr, A, B)
+    assert np.isfinite(F[:, :64]).all()
+    assert np.isnan(F[:, 70:]).any() and np.isnan(X[:80]).any()
 
 
 def test_argument_errors(hqr):
@@ -227,3 +243,69 @@ def test_argument_errors(hqr):
     with pytest.raises(ValueError):
         hqr.qr_apply_qt(dA, up, to_dev(np.ones((5, 1))))
     hqr.qr_apply_qt(dA, up, dB)
+
+
+# -------------------------------------------------- panel algorithms
+@pytest.mark.parametrize("mode", ["cqr", "exact", "percol"])
+@pytest.mark.parametrize("m,n,nrhs", [(700, 300, 2), (1100, 129, 1)])
+def test_panel_modes(hqr, oracle_mod, monkeypatch, mode, m, n, nrhs):
+    """CholeskyQR2 + reconstruction (default), the exact one-workgroup panel
+    and the one-launch-per-pivot panel all match the oracle."""
+    monkeypatch.setenv("HQR_PANEL", mode)
+    rng = np.random.default_rng(81)
+    A = np.asfortranarray(rng.standard_normal((m, n)))
+    B = np.asfortranarray(rng.standard_normal((m, nrhs)))
+    _say("panel mode", mode, (m, n, nrhs))
+    F, up, X, res, info = _run_lsq(hqr, A, B)
+    Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, B)
+    assert info == 0
+    tol = factor_tol(A)
+    assert np.abs(F - Fo).max() <= tol
+    assert np.abs(up - upo).max() <= tol
+    for c in range(nrhs):
+        r = B[:, c] - A @ Xo[:, c]
+        assert np.linalg.norm(X[:n, c] - Xo[:, c]) / np.linalg.norm(Xo[:, c]) <= 2 * lsq_forward_bound(A, Xo[:, c], r)
+
+
+@pytest.mark.parametrize("kappa", [1e6, 1e12])
+def test_ill_conditioned(hqr, oracle_mod, kappa):
+    """kappa 1e12 sends panels to the exact path; results stay within the
+    perturbation bound either way."""
+    A, b, _ = workloads.conditioned(900, 320, kappa, seed=82)
+    _say("ill conditioned", kappa)
+    F, up, X, res, info = _run_lsq(hqr, A, b.reshape(-1, 1))
+    Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, b)
+    assert info == 0
+    assert np.abs(F - Fo).max() <= factor_tol(A)
+    r = b - A @ Xo[:, 0]
+    assert np.linalg.norm(X[:320, 0] - Xo[:, 0]) / np.linalg.norm(Xo[:, 0]) <= 2 * lsq_forward_bound(A, Xo[:, 0], r)
+    assert lsq_orthogonality(A, X[:320, 0], b) <= 50 * 320 * U
+
+
+def test_upper_triangular_input_keeps_identity(hqr, oracle_mod):
+    """Columns already reduced (zero below the diagonal): every reflector is
+    the identity, exactly as in the one-reflector loop."""
+    rng = np.random.default_rng(83)
+    A = np.zeros((500, 200))
+    A[:200] = np.triu(rng.standard_normal((200, 200))) + 3 * np.eye(200)
+    _say("upper triangular input")
+    dA = to_dev(A)
+    up, info = hqr.qr_factor(dA)
+    F, upn = to_host(dA), to_host(up)[:200]
+    Fo, upo = oracle_mod.qr_factor(A)
+    assert np.all(upn == 0.0) and np.all(upo == 0.0)
+    assert np.array_equal(F, A)
+
+
+def test_square_blocked(hqr, oracle_mod):
+    """m == n on the blocked path: the last panel (empty last tail) is exact."""
+    rng = np.random.default_rng(84)
+    A = rng.standard_normal((384, 384))
+    b = rng.standard_normal((384, 1))
+    _say("square blocked")
+    F, up, X, res, info = _run_lsq(hqr, A, b)
+    Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, b)
+    assert up[-1] == 0.0 and upo[-1] == 0.0
+    assert np.abs(F - Fo).max() <= factor_tol(A)
+    r = b[:, 0] - A @ Xo[:, 0]
+    assert np.linalg.norm(X[:, 0] - Xo[:, 0]) / np.linalg.norm(Xo[:, 0]) <= 2 * lsq_forward_bound(A, Xo[:, 0], r)
