@@ -114,6 +114,26 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
                  void *work, int64_t lwork, int *info, int *iters,
                  hipStream_t stream);
 
+/* Many independent least-squares problems of uneven size in ONE persistent
+ * launch (a batch of the per-iteration subproblems an SLSQP-like solver
+ * produces).  Arrays of length `count` are HOST arrays; A[i], up[i], B[i],
+ * resnorm[i] are device pointers.  Instance i: m[i] x n[i] (n[i] <= m[i] <=
+ * 4096), nrhs[i] right-hand sides (n[i] + nrhs[i] <= 2048); A[i] is factored
+ * in place exactly as by qr_factor's one-reflector-at-a-time definition,
+ * B[i] becomes (Q^T B) with x in rows 0..n-1, resnorm[i] (if resnorm and
+ * resnorm[i] are non-NULL, nrhs[i] doubles) gets ||(Q^T B)[n:m]||, and
+ * info[i] (device int array of `count`) gets 0 or the smallest k+1 with
+ * R[k][k] == 0.  Instances are scheduled longest-first; each result depends
+ * only on its own instance, never on the rest of the batch.
+ * Workspace: hqr_batched_workspace_size(count) bytes (or NULL). */
+int64_t hqr_batched_workspace_size(int count);
+int qr_lsq_solve_batched(int count, const int64_t *m, const int64_t *n,
+                         const int64_t *nrhs, double *const *A,
+                         const int64_t *lda, double *const *up,
+                         double *const *B, const int64_t *ldb,
+                         double *const *resnorm, int *info, void *work,
+                         int64_t lwork, hipStream_t stream);
+
 /* Kernel timing for measurement.  hqr_profile_begin() starts recording: every
  * kernel the library launches afterwards (on any stream) is bracketed by a
  * pair of HIP events on that stream, grouped by kernel class.

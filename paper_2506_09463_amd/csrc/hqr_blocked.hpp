@@ -188,6 +188,7 @@ struct VtxArgs {
     int64_t m;
     int c0, bw;
     int ncA, nB;          // trailing A columns, B columns
+    int aoff;             // first trailing A column is c0 + bw + aoff
     int nx;               // bw + ncA + nB
     int nxpad;            // row stride of the partial buffers
     int64_t split_rows;   // rows per split (multiple of KC)
@@ -211,7 +212,7 @@ HQR_DEV double x_elem(const VtxArgs &p, int64_t gi, int x)
         if (x < p.bw) return v_elem(p.A, p.lda, p.up, p.c0, gi, x);
         x -= p.bw;
     }
-    if (x < p.ncA) return HQR_AT(p.A, gi, p.c0 + p.bw + x, p.lda);
+    if (x < p.ncA) return HQR_AT(p.A, gi, p.c0 + p.bw + p.aoff + x, p.lda);
     return HQR_AT(p.B, gi, x - p.ncA, p.ldb);
 }
 
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
                 xvmask |= 1u << q;
             } else {
                 if (p.with_v) x -= p.bw;
-                ptr = (x < p.ncA) ? p.A + (size_t)(p.c0 + p.bw + x) * p.lda : p.B + (size_t)(x - p.ncA) * p.ldb;
+                ptr = (x < p.ncA) ? p.A + (size_t)(p.c0 + p.bw + p.aoff + x) * p.lda : p.B + (size_t)(x - p.ncA) * p.ldb;
             }
         }
         xcol[q] = ptr;
@@ -441,7 +442,8 @@ struct UpdArgs {
     const double *up;
     int64_t m;
     int c0, bw;
-    int ncA, nB;          // updated A columns start at c0+bw; then B columns
+    int ncA, nB;          // updated A columns start at c0+bw+aoff; then B columns
+    int aoff;
     int xoff;             // X index of the first updated column in wp
     const double *wp;     // [NB][nxpad]
     int nxpad;
@@ -449,7 +451,7 @@ struct UpdArgs {
 
 HQR_DEV double *col_ptr(const UpdArgs &p, int c)
 {
-    if (c < p.ncA) return p.A + (size_t)(p.c0 + p.bw + c) * p.lda;
+    if (c < p.ncA) return p.A + (size_t)(p.c0 + p.bw + p.aoff + c) * p.lda;
     return p.B + (size_t)(c - p.ncA) * p.ldb;
 }
 

@@ -73,83 +73,172 @@ HQR_DEV double quad_sum(double v)
 
 // Inverse of the upper-triangular n x n block of U into X (upper, zeros
 // below, identity beyond n).  Column j belongs to lanes 4j..4j+3 of one wave
-// (256 threads); rows are produced bottom-up, each dot product split over
-// the four lanes, so no workgroup barrier is needed between rows.
-HQR_DEV void inv_upper64(double (*X)[LD65], const double (*U)[LD65], int n, int tid)
+// (256 threads); lane q keeps X[q + 4t][j], t < 16, in registers.  Rows are
+// produced bottom-up; the 16 entries of U's row each lane needs are loaded
+// unconditionally (so the loads pipeline), products are selected, not
+// branched, and the four partial sums are added across the lanes.
+HQR_DEV void inv_upper64(double (*X)[LD65], const double (*U)[LD65], int n, int tid, double *dinv)
 {
     const int j = tid >> 2, q = tid & 3;
-    for (int i = q; i < NB; i += 4) X[i][j] = (i == j && j >= n) ? 1.0 : 0.0;
-    __builtin_amdgcn_wave_barrier();
+    if (tid < NB) dinv[tid] = (tid < n) ? 1.0 / U[tid][tid] : 1.0;
+    __syncthreads();
+    double x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == j) ? dinv[j] : 0.0;
     if (j < n) {
-        const double xjj = 1.0 / U[j][j];
-        if (q == 0) X[j][j] = xjj;
-        __builtin_amdgcn_wave_barrier();
         for (int i = j - 1; i >= 0; --i) {
-            double s = 0.0;
-            for (int l = i + 1 + q; l <= j; l += 4) s += U[i][l] * X[l][j];
-            s = quad_sum(s);
-            const double xij = -s / U[i][i];
-            if (q == 0) X[i][j] = xij;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            double u[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) u[t] = U[i][q + 4 * t];
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; t += 2) {
+                const int l0 = q + 4 * t, l1 = l0 + 4;
+                s0 += (l0 > i && l0 <= j) ? u[t] * x[t] : 0.0;
+                s1 += (l1 > i && l1 <= j) ? u[t + 1] * x[t + 1] : 0.0;
+            }
+            const double xi = -quad_sum(s0 + s1) * dinv[i];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == i) ? xi : x[t];
         }
     }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) X[q + 4 * t][j] = x[t];
     __syncthreads();
 }
 
 // Inverse of the unit lower triangle (strict lower entries of L, unit
-// diagonal implied) into X (lower, unit diagonal, zeros above); same lane
-// layout as inv_upper64, rows produced top-down.
+// diagonal implied) into X (lower, unit diagonal, zeros above); same layout,
+// rows produced top-down.
 HQR_DEV void inv_unit_lower64(double (*X)[LD65], const double (*L)[LD65], int n, int tid)
 {
     const int j = tid >> 2, q = tid & 3;
-    for (int i = q; i < NB; i += 4) X[i][j] = (i == j) ? 1.0 : 0.0;
-    __builtin_amdgcn_wave_barrier();
+    double x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == j) ? 1.0 : 0.0;
     if (j < n) {
         for (int i = j + 1; i < n; ++i) {
-            double s = 0.0;
-            for (int l = j + q; l < i; l += 4) s += L[i][l] * X[l][j];
-            s = quad_sum(s);
-            if (q == 0) X[i][j] = -s;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            double u[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) u[t] = L[i][q + 4 * t];
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int t = 0; t < 16; t += 2) {
+                const int l0 = q + 4 * t, l1 = l0 + 4;
+                s0 += (l0 >= j && l0 < i) ? u[t] * x[t] : 0.0;
+                s1 += (l1 >= j && l1 < i) ? u[t + 1] * x[t + 1] : 0.0;
+            }
+            const double xi = -quad_sum(s0 + s1);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == i) ? xi : x[t];
         }
     }
     __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) X[q + 4 * t][j] = x[t];
+    __syncthreads();
+}
+
+// Register of a 16-entry array picked by a runtime index (select chain, so
+// the array stays in registers).
+HQR_DEV double pick16(const double (&v)[16], int t)
+{
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) r = (q == t) ? v[q] : r;
+    return r;
 }
 
 // In-place upper Cholesky G = R^T R of the n x n block (R in the upper part,
 // zeros below, identity beyond n).  Thread (column j = tid & 63, row group
-// tid >> 6) owns the entries G[i][j], i = group + 4t; step k reads row k
-// unscaled and updates rows > k, so one barrier per step suffices; the rows
-// are scaled at the end.  *bad reports a pivot^2 below ratio * G_kk.
-HQR_DEV void chol64(double (*G)[LD65], int n, int tid, double ratio, double *gdiag, double *rdiag, int *bad)
+// rg = tid >> 6) keeps G[rg + 4t][j], t < 16, in registers.  Row k is
+// broadcast through a double-buffered LDS row written by its owners after
+// their step-(k-1) update, so each step needs one barrier.  *bad reports a
+// pivot^2 below ratio * G_kk.
+HQR_DEV void chol64(double (*G)[LD65], int n, int tid, double ratio, double *gdiag, double *rdiag, int *bad,
+                    double (*rowbuf)[NB])
 {
     const int j = tid & 63, rg = tid >> 6;
+    double g[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) g[t] = G[rg + 4 * t][j];
     if (tid < NB) gdiag[tid] = (tid < n) ? G[tid][tid] : 1.0;
     if (tid == 0) *bad = 0;
+    if (rg == 0) rowbuf[0][j] = g[0];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        const double piv = G[k][k];
+        const double *rk = rowbuf[k & 1];
+        const double piv = rk[k];
+        const double inv = 1.0 / piv;
+        const double rkj = rk[j];
         const double rkk = sqrt(fmax(piv, 0.0));
+        double rkv[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) rkv[t] = rk[rg + 4 * t];
+        const double coef = rkj * inv;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int i = rg + 4 * t;
+            g[t] = (i > k && i <= j && j < n) ? g[t] - rkv[t] * coef : g[t];
+        }
+        // row k of R
+        if (rg == (k & 3)) G[k][j] = (j > k && j < n) ? rkj / rkk : ((j == k) ? rkk : 0.0);
         if (tid == 0) {
             rdiag[k] = rkk;
             if (!(piv > ratio * gdiag[k])) *bad = 1;
         }
-        const double inv2 = 1.0 / piv;
-        if (j > k && j < n) {
-            const double gkj = G[k][j];
-            for (int i = k + 1 + ((rg - (k + 1)) & 3); i <= j; i += 4) G[i][j] -= G[k][i] * gkj * inv2;
-        }
+        const int kn = k + 1;
+        if (kn < n && rg == (kn & 3)) rowbuf[kn & 1][j] = pick16(g, kn >> 2);
         __syncthreads();
     }
-    // R[k][j] = G[k][j] / R_kk (row k as it stood at step k), R_kk on the diagonal
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, c = idx % NB;
-        double v;
-        if (i < n && c < n) v = (c > i) ? G[i][c] / rdiag[i] : ((c == i) ? rdiag[i] : 0.0);
-        else v = (i == c) ? 1.0 : 0.0;
-        G[i][c] = v;
+        if (i > c || i >= n || c >= n) G[i][c] = (i == c && i >= n) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+}
+
+// In place: M (n x n, top block of Q) becomes L (strict lower, unit diagonal
+// implied) and U (upper) of the LU factorization without pivoting of
+// M - S, with s_k = -sgn(pivot k) (sgn(0) = +1) chosen at step k.  Same
+// register layout as chol64; column k reaches the wave's lanes by readlane.
+HQR_DEV void lu_sign64(double (*M)[LD65], int n, int tid, double *sgn, double *udiag, double (*rowbuf)[NB])
+{
+    const int j = tid & 63, rg = tid >> 6;
+    double mv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) mv[t] = M[rg + 4 * t][j];
+    if (rg == 0) rowbuf[0][j] = mv[0];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double *rk = rowbuf[k & 1];
+        const double q = rk[k];
+        const double s = (q >= 0.0) ? -1.0 : 1.0;
+        const double ukk = q - s;
+        const double ukj = rk[j] / ukk;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int i = rg + 4 * t;
+            const double lik = readlane_f64(mv[t], k); // column k, row i
+            mv[t] = (i > k && i < n && j > k && j < n) ? mv[t] - lik * ukj : mv[t];
+        }
+        if (tid == 0) {
+            sgn[k] = s;
+            udiag[k] = ukk;
+        }
+        const int kn = k + 1;
+        if (kn < n && rg == (kn & 3)) rowbuf[kn & 1][j] = pick16(mv, kn >> 2);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int i = rg + 4 * t;
+        double v = mv[t];
+        if (i < n && j < n) {
+            if (i > j) v = v / udiag[j];
+            else if (i == j) v = udiag[j];
+        }
+        M[i][j] = v;
     }
     __syncthreads();
 }
@@ -274,6 +363,7 @@ struct CholArgs {
     double *T;          // [NB][NB]  (pass 2 out) T for the stored vectors
     double *up;         // global up (pass 2 out)
     int *flag;
+    long long *tstamp;  // optional per-phase timestamps (thread 0), may be null
 };
 
 // One workgroup, 256 threads.
@@ -284,10 +374,18 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     __shared__ double M2[NB][LD65];
     __shared__ double M3[NB][LD65];
     __shared__ double gdiag[NB], rdiag[NB], sgn[NB], upv[NB], rh[NB];
+    __shared__ double rowbuf[2][NB];
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int bw = p.bw;
     if (p.pass == 2 && *((volatile int *)p.flag)) return;
+    int tsi = 0;
+#define HQR_TS()                                                                 \
+    do {                                                                         \
+        if (p.tstamp && tid == 0) p.tstamp[tsi] = (long long)wall_clock64();     \
+        ++tsi;                                                                   \
+    } while (0)
+    HQR_TS();
 
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, j = idx % NB;
@@ -300,13 +398,15 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         structural = ((all & need) != need);
     }
     __syncthreads();
-    chol64(M0, bw, tid, CQR_RATIO, gdiag, rdiag, &bad);
+    HQR_TS();
+    chol64(M0, bw, tid, CQR_RATIO, gdiag, rdiag, &bad, rowbuf);
+    HQR_TS();
     if (tid == 0 && (bad || structural)) atomicExch(p.flag, 1);
     __syncthreads();
     if (bad || __hip_atomic_load(p.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
 
     if (p.pass == 1) {
-        inv_upper64(M1, M0, bw, tid);
+        inv_upper64(M1, M0, bw, tid, gdiag);
         for (int idx = tid; idx < NB * NB; idx += 256) {
             p.r1[idx] = M0[idx / NB][idx % NB];
             p.r1inv[idx] = M1[idx / NB][idx % NB];
@@ -315,7 +415,8 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     }
 
     // ---- pass 2: M0 = R2
-    inv_upper64(M1, M0, bw, tid);                       // M1 = R2^{-1}
+    inv_upper64(M1, M0, bw, tid, gdiag);                // M1 = R2^{-1}
+    HQR_TS();
     for (int idx = tid; idx < NB * NB; idx += 256) M2[idx / NB][idx % NB] = p.r1inv[idx];
     __syncthreads();
     mm64(M3, M2, M1, lane, w);                          // M3 = R^{-1} = R1^{-1} R2^{-1}
@@ -332,34 +433,10 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     __syncthreads();
     mm64(M0, M2, M3, lane, w);                          // M0 = Q_top
     __syncthreads();
-    // modified LU of Q_top - S (in place in M0): thread (column j, row group)
-    // owns M0[i][j]; step k reads column k and row k as they stand and updates
-    // the trailing block, so one barrier per step; L is scaled at the end.
-    {
-        const int j = tid & 63, rg = tid >> 6;
-        for (int k = 0; k < bw; ++k) {
-            const double q = M0[k][k];
-            const double s = (q >= 0.0) ? -1.0 : 1.0;
-            const double ukk = q - s;
-            if (tid == 0) {
-                sgn[k] = s;
-                rdiag[k] = ukk;
-            }
-            if (j > k && j < bw) {
-                const double ukj = M0[k][j] / ukk;
-                for (int i = k + 1 + ((rg - (k + 1)) & 3); i < bw; i += 4) M0[i][j] -= M0[i][k] * ukj;
-            }
-            __syncthreads();
-        }
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            const int i = idx / NB, c = idx % NB;
-            if (i < bw && c < bw) {
-                if (i > c) M0[i][c] = M0[i][c] / rdiag[c];
-                else if (i == c) M0[i][c] = rdiag[c];
-            }
-        }
-        __syncthreads();
-    }
+    HQR_TS();
+    // modified LU of Q_top - S (in place in M0)
+    lu_sign64(M0, bw, tid, sgn, rdiag, rowbuf);
+    HQR_TS();
     // R_house = S R: write the upper triangle of the panel's top block
     for (int idx = tid; idx < bw * bw; idx += 256) {
         const int c = idx / bw, r = idx % bw;
@@ -380,7 +457,8 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
             M1[i][j] = (i <= j && i < bw && j < bw) ? M0[i][j] : ((i == j) ? 1.0 : 0.0);
         }
         __syncthreads();
-        inv_upper64(M2, M1, NB, tid);
+        inv_upper64(M2, M1, NB, tid, gdiag);
+        HQR_TS();
         mm64(M1, M3, M2, lane, w);                      // M1 = R^{-1} U^{-1}
         __syncthreads();
         for (int idx = tid; idx < NB * NB; idx += 256) {
@@ -388,16 +466,22 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
             p.winv[idx] = (j < bw) ? M1[i][j] * upv[j] : 0.0;
         }
     }
-    // T_Y = -U S L^{-T};  T_V = T_Y / (up_i up_j)
+    // T_Y = -(U S) L^{-T};  T_V = T_Y / (up_i up_j)
+    __syncthreads();
+    HQR_TS();
     inv_unit_lower64(M2, M0, bw, tid);                  // M2 = L^{-1}
+    HQR_TS();
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int i = idx / NB, l = idx % NB;
+        M1[i][l] = (i <= l && l < bw) ? M0[i][l] * sgn[l] : 0.0; // U S
+        M3[l][i] = M2[i][l];                                     // L^{-T}
+    }
+    __syncthreads();
+    mm64(M2, M1, M3, lane, w);
+    __syncthreads();
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, j = idx % NB;
-        double t = 0.0;
-        if (i <= j && j < bw) {
-            for (int l = i; l <= j; ++l) t += M0[i][l] * sgn[l] * M2[j][l];
-            t = -t / (upv[i] * upv[j]);
-        }
-        p.T[idx] = t;
+        p.T[idx] = (i <= j && j < bw) ? -M2[i][j] / (upv[i] * upv[j]) : 0.0;
     }
     // stored tails of the top block: L[i][j] * up_j (strict lower)
     for (int idx = tid; idx < bw * bw; idx += 256) {
@@ -405,6 +489,8 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         if (r > c) HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) = M0[r][c] * upv[c];
     }
     if (tid < bw) p.up[p.c0 + tid] = upv[tid];
+    HQR_TS();
+#undef HQR_TS
 }
 
 // ------------------------------------------ bottom rows: Y_bot * diag(up)

@@ -13,6 +13,10 @@
 #include "hqr_small.hpp"
 #include "hqr_blocked.hpp"
 #include "hqr_cqr.hpp"
+#include "hqr_batched.hpp"
+
+#include <numeric>
+#include <vector>
 
 namespace hqr {
 
@@ -21,12 +25,12 @@ namespace hqr {
 // by a pair of HIP events recorded on the launch's own stream.
 enum KClass {
     K_SMALL, K_PANEL, K_VTX, K_TFACTOR, K_WSOLVE, K_UPDATE, K_DIAG, K_TRSV, K_RESNORM, K_FILL,
-    K_CQR_GRAM, K_CQR_CHOL, K_CQR_FINISH, K_PANEL_EXACT, K_GRED, K_NCLASS
+    K_CQR_GRAM, K_CQR_CHOL, K_CQR_FINISH, K_PANEL_EXACT, K_GRED, K_BATCHED, K_NCLASS
 };
 static const char *kclass_name[K_NCLASS] = {"small_lsq", "panel_col", "vtx", "tfactor", "wsolve",
                                             "update", "diag_check", "trsv", "resnorm", "fill",
                                             "cqr_gram", "cqr_chol", "cqr_finish", "panel_exact",
-                                            "gram_reduce"};
+                                            "gram_reduce", "batched_lsq"};
 struct ProfRec {
     int cls;
     hipEvent_t e0, e1;
@@ -165,6 +169,7 @@ static Plan make_plan(int64_t m, int64_t n, int64_t nrhs)
 
 struct Work {
     double *xbuf, *pbuf, *wpart, *T, *wp;
+    double *wpart2, *T2, *wp2;            // second set for the look-ahead stream
     int *flags;
     int *iscratch;
     double *gpart, *r1, *r1inv, *winv, *G;
@@ -187,6 +192,9 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *wpart = take(sizeof(double) * (size_t)p.nsplit_max * NB * p.nxpad);
     char *T = take(sizeof(double) * NB * NB);
     char *wp = take(sizeof(double) * NB * (size_t)p.nxpad);
+    char *wpart2 = take(sizeof(double) * (size_t)p.nsplit_max * NB * p.nxpad);
+    char *T2 = take(sizeof(double) * NB * NB);
+    char *wp2 = take(sizeof(double) * NB * (size_t)p.nxpad);
     char *fl = take(sizeof(int) * (size_t)std::max(p.nblk, 1));
     char *is = take(sizeof(int) * 64);
     char *gp = take(sizeof(double) * (size_t)p.ngroups * NB * NB);
@@ -211,6 +219,9 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
         w->wpart = (double *)wpart;
         w->T = (double *)T;
         w->wp = (double *)wp;
+        w->wpart2 = (double *)wpart2;
+        w->T2 = (double *)T2;
+        w->wp2 = (double *)wp2;
         w->flags = (int *)fl;
         w->iscratch = (int *)is;
     }
@@ -229,10 +240,17 @@ static int pick_nsplit(int64_t rows, int ntiles, int nsplit_max)
         if ((call) != hipSuccess) return HQR_EDEVICE;  \
     } while (0)
 
+// Buffers one trailing update works in.
+struct TrailBufs {
+    double *wpart, *T, *wp;
+};
+
 // Apply the compact-WY block of panel (c0, bw) to trailing A columns
-// [c0+bw, c0+bw+ncA) and all nB columns of B.
-static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t lda, double *B, int64_t ldb,
-                             const double *up, int c0, int bw, int ncA, int nB, bool have_t, hipStream_t s)
+// [c0+bw+aoff, c0+bw+aoff+ncA) and all nB columns of B.  With have_t the
+// panel's T is already in tb.T; otherwise it is formed from V^T V.
+static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int64_t lda, double *B, int64_t ldb,
+                             const double *up, int c0, int bw, int aoff, int ncA, int nB, bool have_t,
+                             hipStream_t s)
 {
     const int64_t rows = pl.m - c0;
     VtxArgs v;
@@ -246,6 +264,7 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
     v.bw = bw;
     v.ncA = ncA;
     v.nB = nB;
+    v.aoff = aoff;
     v.with_v = have_t ? 0 : 1;
     const int vcols = have_t ? 0 : bw;
     v.nx = vcols + ncA + nB;
@@ -254,7 +273,7 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
     const int nsplit = pick_nsplit(rows, ntiles, pl.nsplit_max);
     v.split_rows = rup((rows + nsplit - 1) / nsplit, KC);
     const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
-    v.wpart = w.wpart;
+    v.wpart = tb.wpart;
     HQR_LAUNCH(K_VTX, vtx_kernel, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
     HQR_CK(hipGetLastError());
 
@@ -265,10 +284,10 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
         t.up = up;
         t.c0 = c0;
         t.bw = bw;
-        t.wpart = w.wpart;
+        t.wpart = tb.wpart;
         t.nsplit = nsplit_eff;
         t.nxpad = pl.nxpad;
-        t.T = w.T;
+        t.T = tb.T;
         HQR_LAUNCH(K_TFACTOR, tfactor_kernel, dim3(1), dim3(256), 0, s, t);
         HQR_CK(hipGetLastError());
     }
@@ -276,14 +295,14 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
     const int ncols = ncA + nB;
     if (ncols == 0) return 0;
     WArgs wa;
-    wa.wpart = w.wpart;
+    wa.wpart = tb.wpart;
     wa.nsplit = nsplit_eff;
     wa.nxpad = pl.nxpad;
     wa.xoff = vcols;
     wa.ncols = ncols;
     wa.bw = bw;
-    wa.T = w.T;
-    wa.wp = w.wp;
+    wa.T = tb.T;
+    wa.wp = tb.wp;
     HQR_LAUNCH(K_WSOLVE, wsolve_kernel, dim3((ncols + WS_COLS - 1) / WS_COLS), dim3(256), 0, s, wa);
     HQR_CK(hipGetLastError());
 
@@ -298,8 +317,9 @@ static int apply_panel_block(const Plan &pl, const Work &w, double *A, int64_t l
     u.bw = bw;
     u.ncA = ncA;
     u.nB = nB;
+    u.aoff = aoff;
     u.xoff = vcols;
-    u.wp = w.wp;
+    u.wp = tb.wp;
     u.nxpad = pl.nxpad;
     HQR_LAUNCH(K_UPDATE, update_kernel, dim3((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols + UPD_TILE - 1) / UPD_TILE), dim3(256), 0, s, u);
     HQR_CK(hipGetLastError());
@@ -332,7 +352,7 @@ static int panel_percol(const Plan &pl, const Work &w, double *A, int64_t lda, d
 // exact one-workgroup panel when the device flags the panel.  Leaves T (for
 // the stored vectors) in w.T.
 static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
-                     hipStream_t s)
+                     double *Tout, hipStream_t s)
 {
     const int64_t mp = pl.m - c0;
     int *flag = w.pflag + pidx;
@@ -365,9 +385,10 @@ static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, doub
     c.r1 = w.r1;
     c.r1inv = w.r1inv;
     c.winv = w.winv;
-    c.T = w.T;
+    c.T = Tout;
     c.up = up;
     c.flag = flag;
+    c.tstamp = nullptr;
     for (int pass = 1; pass <= 2; ++pass) {
         g.pass = pass;
         c.pass = pass;
@@ -398,7 +419,7 @@ static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, doub
     e.c0 = c0;
     e.bw = bw;
     e.up = up;
-    e.T = w.T;
+    e.T = Tout;
     e.flag = flag;
     HQR_LAUNCH(K_PANEL_EXACT, panel_exact_kernel, dim3(1), dim3(1024), 0, s, e);
     HQR_CK(hipGetLastError());
@@ -416,30 +437,115 @@ static int panel_mode()
     return PANEL_CQR;
 }
 
+// Side stream and events for the look-ahead (one per device, created on first
+// use, default priority).
+struct SideStream {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+static SideStream g_side[16];
+
+static SideStream *side_stream()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
+    SideStream &ss = g_side[dev];
+    if (ss.device != dev) {
+        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        for (auto &e : ss.ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        ss.device = dev;
+    }
+    return &ss;
+}
+
+static bool lookahead_enabled()
+{
+    const char *e = getenv("HQR_LOOKAHEAD");
+    return !(e && e[0] == '0');
+}
+
 // Blocked factorization; B (nB columns) rides along as trailing columns.
+//
+// With look-ahead (default), panel p+1 is factored on the caller's stream
+// while the rest of panel p's trailing update runs on a side stream:
+//   main: P(p) -> [a] -> N(p) (next panel's columns) -> P(p+1) -> wait r(p) -> N(p+1) -> ...
+//   side: wait a -> R(p) (all later columns and B) -> [r(p)]
+// N and R use separate W buffers; T alternates between two buffers by panel
+// parity (P(p+2) is issued after main has waited for R(p)).
 static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, double *B, int64_t ldb,
                           int nB, hipStream_t s)
 {
     const int64_t n = pl.n;
     const int mode = panel_mode();
-    if (mode != PANEL_PERCOL) {
+    const bool have_t = (mode != PANEL_PERCOL);
+    if (have_t) {
         // exact-only mode: every panel flagged up front
         HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(256), 0, s, w.pflag, mode == PANEL_EXACT ? 1 : 0,
                    (int64_t)pl.npanels);
         HQR_CK(hipGetLastError());
     }
+    SideStream *ss = (lookahead_enabled() && pl.npanels > 1) ? side_stream() : nullptr;
+    const TrailBufs bufN{w.wpart, nullptr, w.wp};
+    const TrailBufs bufR{w.wpart2, nullptr, w.wp2};
+    double *Tbuf[2] = {w.T, w.T2};
+    auto do_panel = [&](int64_t c0, int bw, int pidx) -> int {
+        if (mode == PANEL_PERCOL) return panel_percol(pl, w, A, lda, up, (int)c0, bw, s);
+        return panel_cqr(pl, w, A, lda, up, (int)c0, bw, pidx, Tbuf[pidx & 1], s);
+    };
+    if (!ss) {
+        for (int64_t c0 = 0; c0 < n; c0 += NB) {
+            const int bw = (int)std::min<int64_t>(NB, n - c0);
+            const int pidx = (int)(c0 / NB);
+            int rc = do_panel(c0, bw, pidx);
+            if (rc) return rc;
+            const int ncA = (int)(n - c0 - bw);
+            TrailBufs b = bufN;
+            b.T = Tbuf[pidx & 1];
+            if (ncA + nB > 0) {
+                rc = apply_panel_block(pl, b, A, lda, B, ldb, up, (int)c0, bw, 0, ncA, nB, have_t, s);
+                if (rc) return rc;
+            }
+        }
+        return 0;
+    }
+    hipEvent_t ev_a = ss->ev[0], ev_r = ss->ev[1], ev_join = ss->ev[2], ev_fork = ss->ev[3];
+    // side stream starts after everything already on the caller's stream
+    HQR_CK(hipEventRecord(ev_fork, s));
+    HQR_CK(hipStreamWaitEvent(ss->stream, ev_fork, 0));
+    int rc = do_panel(0, (int)std::min<int64_t>(NB, n), 0);
+    if (rc) return rc;
+    bool pending_r = false;
     for (int64_t c0 = 0; c0 < n; c0 += NB) {
         const int bw = (int)std::min<int64_t>(NB, n - c0);
         const int pidx = (int)(c0 / NB);
-        int rc = (mode == PANEL_PERCOL) ? panel_percol(pl, w, A, lda, up, (int)c0, bw, s)
-                                        : panel_cqr(pl, w, A, lda, up, (int)c0, bw, pidx, s);
-        if (rc) return rc;
-        const int ncA = (int)(n - c0 - bw);
-        if (ncA + nB > 0) {
-            rc = apply_panel_block(pl, w, A, lda, B, ldb, up, (int)c0, bw, ncA, nB, mode != PANEL_PERCOL, s);
+        const int64_t c1 = c0 + bw;                       // next panel
+        const int bw1 = (int)std::min<int64_t>(NB, std::max<int64_t>(0, n - c1));
+        const int ncR = (int)std::max<int64_t>(0, n - c1 - bw1);
+        TrailBufs bn = bufN, br = bufR;
+        bn.T = br.T = Tbuf[pidx & 1];
+        // R(p) on the side stream: columns beyond the next panel, and B
+        HQR_CK(hipEventRecord(ev_a, s));
+        HQR_CK(hipStreamWaitEvent(ss->stream, ev_a, 0));
+        if (ncR + nB > 0) {
+            rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, have_t, ss->stream);
             if (rc) return rc;
         }
+        // main: wait for R(p-1) (it updated this panel's next columns), then N(p), then P(p+1)
+        if (pending_r) HQR_CK(hipStreamWaitEvent(s, ev_r, 0));
+        if (bw1 > 0) {
+            rc = apply_panel_block(pl, bn, A, lda, B, ldb, up, (int)c0, bw, 0, bw1, 0, have_t, s);
+            if (rc) return rc;
+            rc = do_panel(c1, bw1, pidx + 1);
+            if (rc) return rc;
+        }
+        HQR_CK(hipEventRecord(ev_r, ss->stream));
+        pending_r = true;
     }
+    // join: the caller's stream waits for the last side-stream work
+    HQR_CK(hipEventRecord(ev_join, ss->stream));
+    HQR_CK(hipStreamWaitEvent(s, ev_join, 0));
     return 0;
 }
 
@@ -495,6 +601,121 @@ static int get_work(const Plan &pl, void *work, int64_t lwork, hipStream_t s, Wo
 } // namespace hqr
 
 using namespace hqr;
+
+
+// ------------------------------------------------------------ batched path
+namespace hqr {
+
+// Pinned staging buffer for the descriptor upload; `ready` fences reuse.
+struct Staging {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ready = nullptr;
+};
+static Staging g_stage;
+
+static int stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s)
+{
+    if (g_stage.ready) HQR_CK(hipEventSynchronize(g_stage.ready));
+    if (g_stage.bytes < bytes) {
+        if (g_stage.host) (void)hipHostFree(g_stage.host);
+        g_stage.host = nullptr;
+        g_stage.bytes = 0;
+        if (hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault) != hipSuccess) return HQR_ENOMEM;
+        g_stage.bytes = bytes;
+    }
+    if (!g_stage.ready) HQR_CK(hipEventCreateWithFlags(&g_stage.ready, hipEventDisableTiming));
+    memcpy(g_stage.host, src, bytes);
+    HQR_CK(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, s));
+    HQR_CK(hipEventRecord(g_stage.ready, s));
+    return 0;
+}
+
+static int num_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+} // namespace hqr
+
+extern "C" int64_t hqr_batched_workspace_size(int count)
+{
+    if (count < 0) return -1;
+    return (int64_t)(align256(sizeof(BatchDesc) * (size_t)std::max(count, 1)) + 256);
+}
+
+extern "C" int qr_lsq_solve_batched(int count, const int64_t *m, const int64_t *n, const int64_t *nrhs,
+                                    double *const *A, const int64_t *lda, double *const *up, double *const *B,
+                                    const int64_t *ldb, double *const *resnorm, int *info, void *work,
+                                    int64_t lwork, hipStream_t stream)
+{
+    if (count < 0) return -1;
+    if (count == 0) return 0;
+    if (!m) return -2;
+    if (!n) return -3;
+    if (!nrhs) return -4;
+    if (!A) return -5;
+    if (!lda) return -6;
+    if (!up) return -7;
+    if (!B) return -8;
+    if (!ldb) return -9;
+    if (!info) return -11;
+    std::vector<BatchDesc> d((size_t)count);
+    std::vector<double> cost((size_t)count);
+    int max_ntot = 0;
+    for (int i = 0; i < count; ++i) {
+        if (m[i] < 0 || m[i] > BATCH_MAX_ROWS) return -2;
+        if (n[i] < 0 || n[i] > m[i]) return -3;
+        if (nrhs[i] < 0 || n[i] + nrhs[i] > BATCH_MAX_COLS) return -4;
+        if (lda[i] < std::max<int64_t>(1, m[i])) return -6;
+        if (ldb[i] < std::max<int64_t>(1, m[i])) return -9;
+        if (n[i] > 0 && (!A[i] || !up[i])) return -5;
+        if (nrhs[i] > 0 && !B[i]) return -8;
+        d[i] = BatchDesc{m[i], n[i], nrhs[i], lda[i], ldb[i], A[i], B[i], up[i], resnorm ? resnorm[i] : nullptr, i};
+        const double mm = (double)m[i], nn = (double)n[i];
+        cost[i] = 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * (double)nrhs[i] + mm;
+        max_ntot = std::max<int>(max_ntot, (int)(n[i] + nrhs[i]));
+    }
+    // longest first; ties by caller order, so the order depends on shapes only
+    std::vector<int> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<BatchDesc> sorted((size_t)count);
+    for (int i = 0; i < count; ++i) sorted[i] = d[order[i]];
+
+    const size_t need = (size_t)hqr_batched_workspace_size(count);
+    WorkGuard g;
+    char *base = (char *)work;
+    if (!base) {
+        if (hipMallocAsync((void **)&base, need, stream) != hipSuccess) return HQR_ENOMEM;
+        g.ptr = base;
+        g.s = stream;
+    } else if (lwork < (int64_t)need) {
+        return HQR_ENOMEM;
+    }
+    BatchDesc *ddesc = (BatchDesc *)base;
+    int *head = (int *)(base + align256(sizeof(BatchDesc) * (size_t)count));
+    int rc = stage_upload(sorted.data(), sizeof(BatchDesc) * (size_t)count, ddesc, stream);
+    if (rc) return rc;
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, head, 0, (int64_t)1);
+    HQR_CK(hipGetLastError());
+    BatchArgs a;
+    a.desc = ddesc;
+    a.count = count;
+    a.head = head;
+    a.info = info;
+    a.max_ntot = max_ntot;
+    const int grid = std::min(count, 2 * num_cus());
+    HQR_LAUNCH(K_BATCHED, batched_lsq_kernel, dim3(grid), dim3(1024), 0, stream, a);
+    HQR_CK(hipGetLastError());
+    return 0;
+}
 
 extern "C" {
 
@@ -578,7 +799,7 @@ int qr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda
     if (rc) return rc;
     for (int64_t c0 = 0; c0 < n; c0 += NB) {
         const int bw = (int)std::min<int64_t>(NB, n - c0);
-        rc = apply_panel_block(pl, w, const_cast<double *>(A), lda, B, ldb, up, (int)c0, bw, 0, (int)nrhs, false, stream);
+        rc = apply_panel_block(pl, TrailBufs{w.wpart, w.T, w.wp}, const_cast<double *>(A), lda, B, ldb, up, (int)c0, bw, 0, 0, (int)nrhs, false, stream);
         if (rc) return rc;
     }
     return 0;

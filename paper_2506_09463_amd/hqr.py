@@ -25,7 +25,8 @@ HQR_PREC_FP64 = 0
 HQR_PREC_MIXED = 1
 
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_backsolve",
-           "qr_lsq_solve", "hqr_profile_begin", "hqr_profile_end", "hqr_profile_class",
+           "qr_lsq_solve", "hqr_batched_workspace_size", "qr_lsq_solve_batched",
+           "hqr_profile_begin", "hqr_profile_end", "hqr_profile_class",
            "hqr_status_string", "hqr_version")
 
 
@@ -62,6 +63,10 @@ def load(path: str = LIB_PATH):
         getattr(lib, fn).restype = ctypes.c_int
     lib.hqr_status_string.argtypes = [ctypes.c_int]
     lib.hqr_status_string.restype = ctypes.c_char_p
+    lib.hqr_batched_workspace_size.argtypes = [ctypes.c_int]
+    lib.hqr_batched_workspace_size.restype = i64
+    lib.qr_lsq_solve_batched.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, ip, vp, i64, vp]
+    lib.qr_lsq_solve_batched.restype = ctypes.c_int
     lib.hqr_profile_begin.argtypes = []
     lib.hqr_profile_begin.restype = ctypes.c_int
     lib.hqr_profile_end.argtypes = [ctypes.c_int, vp, vp]
@@ -244,3 +249,51 @@ def profile_end(max_classes: int = 64):
         if cnt[c]:
             out[lib.hqr_profile_class(c).decode()] = (ms[c], int(cnt[c]))
     return out
+
+
+def qr_lsq_solve_batched(As, Bs, ups=None, resnorms=None, info=None, work=None, stream=None):
+    """Solve a list of least-squares problems in one persistent launch.
+
+    As, Bs: lists of column-major float64 device tensors (A_i m_i x n_i,
+    B_i m_i x nrhs_i), overwritten in place like qr_lsq_solve.  Returns
+    (ups, resnorms, info) with info a device int32 tensor of len(As)."""
+    torch = _torch()
+    lib = load()
+    count = len(As)
+    if len(Bs) != count:
+        raise ValueError("As and Bs differ in length")
+    if count == 0:
+        return [], [], torch.zeros(0, dtype=torch.int32)
+    dev = As[0].device
+    ms = (ctypes.c_int64 * count)()
+    ns = (ctypes.c_int64 * count)()
+    rs = (ctypes.c_int64 * count)()
+    ldas = (ctypes.c_int64 * count)()
+    ldbs = (ctypes.c_int64 * count)()
+    pa = (ctypes.c_void_p * count)()
+    pb = (ctypes.c_void_p * count)()
+    pu = (ctypes.c_void_p * count)()
+    pr = (ctypes.c_void_p * count)()
+    if ups is None:
+        ups = [torch.empty(max(A.shape[1], 1), dtype=torch.float64, device=dev) for A in As]
+    if resnorms is None:
+        resnorms = [torch.empty(max(Bm.shape[1], 1), dtype=torch.float64, device=dev) for Bm in Bs]
+    for i, (A, Bm) in enumerate(zip(As, Bs)):
+        if Bm.shape[0] != A.shape[0]:
+            raise ValueError("instance %d: B must have m rows" % i)
+        ms[i], ns[i], rs[i] = A.shape[0], A.shape[1], Bm.shape[1]
+        ldas[i], ldbs[i] = _ld(A, "A[%d]" % i), _ld(Bm, "B[%d]" % i)
+        pa[i], pb[i] = A.data_ptr(), Bm.data_ptr()
+        pu[i], pr[i] = ups[i].data_ptr(), resnorms[i].data_ptr()
+    if info is None:
+        info = torch.zeros(count, dtype=torch.int32, device=dev)
+    lw = 0 if work is None else work.numel() * work.element_size()
+    cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
+    _check("qr_lsq_solve_batched", lib.qr_lsq_solve_batched(
+        count, cast(ms), cast(ns), cast(rs), cast(pa), cast(ldas), cast(pu), cast(pb), cast(ldbs),
+        cast(pr), _ptr(info), _ptr(work), lw, _stream(stream)))
+    return ups, resnorms, info
+
+
+def batched_workspace_size(count: int) -> int:
+    return int(load().hqr_batched_workspace_size(count))

@@ -1,0 +1,121 @@
+"""GPU parity of the batched persistent launch (qr_lsq_solve_batched).
+
+Each instance is checked against the FP64 oracle with the same tolerances as
+the single-problem tests; info is exact; a result computed alone and inside
+a batch is bitwise identical (the batch composition never changes an
+instance's arithmetic).
+"""
+import numpy as np
+import pytest
+
+from paper_2506_09463_amd import workloads
+from tests.gpu_util import U, factor_tol, lsq_forward_bound, lsq_orthogonality, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hqr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2506_09463_amd as h
+    h.load()
+    return h
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _solve_batch(hqr, problems):
+    import torch
+    As = [to_dev(A) for A, _ in problems]
+    Bs = [to_dev(B) for _, B in problems]
+    ups, res, info = hqr.qr_lsq_solve_batched(As, Bs)
+    torch.cuda.synchronize()
+    out = []
+    for i, (A, B) in enumerate(problems):
+        n = A.shape[1]
+        out.append((to_host(As[i]), to_host(ups[i])[:n], to_host(Bs[i]), to_host(res[i])[:B.shape[1]]))
+    return out, to_host(info).astype(int)
+
+
+def _mixed_problems(seed, count, nmax, nrhs):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(count):
+        n = int(rng.integers(1, nmax + 1))
+        m = n + int(rng.integers(0, n + 1))
+        probs.append((np.asfortranarray(rng.standard_normal((m, n))),
+                      np.asfortranarray(rng.standard_normal((m, nrhs)))))
+    return probs
+
+
+def test_batched_parity(hqr, oracle_mod):
+    probs = _mixed_problems(91, 40, 200, 8)
+    # edge instances: square, single column, zero column, singular
+    rng = np.random.default_rng(92)
+    probs.append((np.asfortranarray(rng.standard_normal((50, 50))), np.asfortranarray(rng.standard_normal((50, 2)))))
+    probs.append((np.asfortranarray(rng.standard_normal((7, 1))), np.asfortranarray(rng.standard_normal((7, 3)))))
+    Z = rng.standard_normal((30, 10))
+    Z[:, 4] = 0.0
+    probs.append((np.asfortranarray(Z), np.asfortranarray(rng.standard_normal((30, 1)))))
+    _say("batched parity", len(probs))
+    out, info = _solve_batch(hqr, probs)
+    for i, ((A, B), (F, up, X, res)) in enumerate(zip(probs, out)):
+        m, n = A.shape
+        Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, B)
+        assert info[i] == infoo, i
+        assert np.array_equal(up == 0.0, upo == 0.0), i
+        if infoo:
+            qtbo = oracle_mod.apply_qt(Fo, upo, B)
+            assert np.abs(X - qtbo).max() <= 1e-10 * m, i
+            continue
+        tol = factor_tol(A)
+        assert np.abs(F - Fo).max() <= tol, i
+        for c in range(B.shape[1]):
+            r = B[:, c] - A @ Xo[:, c]
+            assert np.linalg.norm(X[:n, c] - Xo[:, c]) / np.linalg.norm(Xo[:, c]) <= 2 * lsq_forward_bound(A, Xo[:, c], r), i
+            assert abs(res[c] - reso[c]) <= 50 * m * U * max(reso[c], 1e-300) + tol, i
+
+
+def test_batched_alone_equals_in_batch(hqr):
+    probs = _mixed_problems(93, 25, 300, 4)
+    _say("alone vs in batch")
+    out, info = _solve_batch(hqr, probs)
+    for i in (0, 7, 24):
+        alone, info1 = _solve_batch(hqr, [probs[i]])
+        for a, b in zip(alone[0], out[i]):
+            assert np.array_equal(a, b), i
+        assert info1[0] == info[i]
+
+
+def test_batched_workload_sample(hqr, oracle_mod):
+    """A slice of the 2000-instance workload (n ~ U{16..512}, m = n + U{0..n},
+    8 right-hand sides): every instance passes the orthogonality check and a
+    sample matches the oracle."""
+    probs = workloads.batch_problem(count=120, seed=workloads.SEED_BATCH)
+    _say("workload sample", len(probs))
+    out, info = _solve_batch(hqr, probs)
+    assert np.all(info == 0)
+    for i, ((A, B), (F, up, X, res)) in enumerate(zip(probs, out)):
+        n = A.shape[1]
+        for c in range(B.shape[1]):
+            assert lsq_orthogonality(A, X[:n, c], B[:, c]) <= 50 * n * U, i
+    for i in (0, 5, 60, 119):
+        A, B = probs[i]
+        n = A.shape[1]
+        Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, B)
+        F, up, X, res = out[i]
+        assert np.abs(F - Fo).max() <= factor_tol(A)
+        for c in range(B.shape[1]):
+            r = B[:, c] - A @ Xo[:, c]
+            assert np.linalg.norm(X[:n, c] - Xo[:, c]) / np.linalg.norm(Xo[:, c]) <= 2 * lsq_forward_bound(A, Xo[:, c], r)
+
+
+def test_batched_argument_errors(hqr):
+    A = to_dev(np.ones((3, 4)))
+    B = to_dev(np.ones((3, 1)))
+    with pytest.raises(hqr.HQRError) as e:
+        hqr.qr_lsq_solve_batched([A], [B])
+    assert e.value.status == -3

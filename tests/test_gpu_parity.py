@@ -309,3 +309,20 @@ def test_square_blocked(hqr, oracle_mod):
     assert np.abs(F - Fo).max() <= factor_tol(A)
     r = b[:, 0] - A @ Xo[:, 0]
     assert np.linalg.norm(X[:, 0] - Xo[:, 0]) / np.linalg.norm(Xo[:, 0]) <= 2 * lsq_forward_bound(A, Xo[:, 0], r)
+
+
+@pytest.mark.parametrize("lookahead", ["0", "1"])
+def test_lookahead_on_off(hqr, oracle_mod, monkeypatch, lookahead):
+    """The side-stream look-ahead changes only the grouping of partial sums."""
+    monkeypatch.setenv("HQR_LOOKAHEAD", lookahead)
+    rng = np.random.default_rng(85)
+    A = np.asfortranarray(rng.standard_normal((1200, 450)))
+    B = np.asfortranarray(rng.standard_normal((1200, 3)))
+    _say("lookahead", lookahead)
+    F, up, X, res, info = _run_lsq(hqr, A, B)
+    Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, B)
+    assert info == 0
+    assert np.abs(F - Fo).max() <= factor_tol(A)
+    for c in range(3):
+        r = B[:, c] - A @ Xo[:, c]
+        assert np.linalg.norm(X[:450, c] - Xo[:, c]) / np.linalg.norm(Xo[:, c]) <= 2 * lsq_forward_bound(A, Xo[:, c], r)
