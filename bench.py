@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=1280)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--workload", default="large", choices=["large", "small", "batched", "mixed", "served"],
+                    help="large (default, the headline line), or one of the other configurations")
+    ap.add_argument("--count", type=int, default=2000, help="batched: number of instances")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -97,6 +100,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     hqr.load()
+    if args.workload != "large":
+        return OTHER[args.workload](args)
     dev = torch.device("cuda:0")
     m, n = args.m, args.n
     t0 = time.time()
@@ -211,6 +216,233 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def _line(metric_unit, value, ms, args, config, roofline=None, cpu=None, hib=True, dtype="f64"):
+    metric, unit = metric_unit
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": hib, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+            "roofline": roofline, "cpu_baseline": cpu}
+
+
+def run_batched(args):
+    """2000 uneven instances (n ~ U{16..512}, m = n + U{0..n}, 8 RHS) in one launch."""
+    import torch
+    import paper_2506_09463_amd as hqr
+    from paper_2506_09463_amd import workloads
+    t0 = time.time()
+    probs = workloads.batch_problem(count=args.count, seed=workloads.SEED_BATCH)
+    print("[bench] %d instances generated in %.1f s" % (len(probs), time.time() - t0), file=sys.stderr, flush=True)
+    A0 = [hqr.colmajor(A) for A, _ in probs]
+    B0 = [hqr.colmajor(B) for _, B in probs]
+    As = [a.clone() for a in A0]
+    Bs = [b.clone() for b in B0]
+    # clone() keeps strides, so the copies stay column-major
+    ups = [torch.empty(A.shape[1], dtype=torch.float64, device="cuda") for A, _ in probs]
+    res = [torch.empty(B.shape[1], dtype=torch.float64, device="cuda") for _, B in probs]
+    info = torch.zeros(len(probs), dtype=torch.int32, device="cuda")
+    work = torch.empty(hqr.batched_workspace_size(len(probs)), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    fl = sum(qr_flops(A.shape[0], A.shape[1]) for A, _ in probs)
+    fl_all = fl + sum(4.0 * A.shape[0] * A.shape[1] * B.shape[1] + A.shape[1] ** 2 * B.shape[1] for A, B in probs)
+
+    def restore():
+        for a, a0 in zip(As, A0):
+            a.copy_(a0)
+        for b, b0 in zip(Bs, B0):
+            b.copy_(b0)
+
+    for _ in range(args.warmup):
+        restore()
+        hqr.qr_lsq_solve_batched(As, Bs, ups=ups, resnorms=res, info=info, work=work, stream=stream)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        restore()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        hqr.qr_lsq_solve_batched(As, Bs, ups=ups, resnorms=res, info=info, work=work, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    assert int(info.abs().sum().item()) == 0
+    # same GPU, same instances, one plain qr_lsq_solve call each
+    restore()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(len(probs)):
+        hqr.qr_lsq_solve(As[i], Bs[i], up=ups[i], resnorm=res[i], info=info[i:i + 1], stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1)
+    print("[bench] batched %.3f ms, loop of single solves %.3f ms" % (ms, loop_ms), file=sys.stderr, flush=True)
+    achieved = fl_all / (ms * 1e-3) / 1e12
+    roof = {"kernel": "batched_lsq", "bound": "alu", "achieved": achieved, "peak": PEAK_F64_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS, "traffic": None, "launches": 1,
+            "avg_launch_ms": ms}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        k = 0
+        while k < len(probs) and time.perf_counter() - t0 < 10.0:
+            A, B = probs[k]
+            oracle.lsq_solve(A, B)
+            k += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": k / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "oracle lsq_solve of the first %d instances of the batch (caller order), %.1f s" % (k, dt)}
+    cfg = {"workload": "batched FP64 LSQ: %d instances, n ~ U{16..512}, m = n + U{0..n}, 8 RHS, one persistent launch"
+           % len(probs), "count": len(probs), "factor_gflop": fl / 1e9, "total_gflop": fl_all / 1e9,
+           "loop_of_single_solves_ms": loop_ms, "speedup_vs_loop": loop_ms / ms}
+    print(json.dumps(_line(("batched LSQ solves/s", "solves/s"), len(probs) / (ms * 1e-3), ms, args, cfg, roof, cpu)),
+          flush=True)
+
+
+def run_small(args):
+    """One 128 x 64 FP64 least-squares solve: median of back-to-back calls and single-call latency."""
+    import torch
+    import paper_2506_09463_amd as hqr
+    from paper_2506_09463_amd import workloads
+    A_h, b_h = workloads.small_problem(seed=workloads.SEED_SMALL)
+    m, n = A_h.shape
+    A0 = hqr.colmajor(A_h)
+    B0 = hqr.colmajor(b_h.reshape(-1, 1))
+    A, B = A0.clone(), B0.clone()
+    up = torch.empty(n, dtype=torch.float64, device="cuda")
+    res = torch.empty(1, dtype=torch.float64, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    reps = 1000
+    for _ in range(20):
+        hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=info, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=info, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    per_call = e0.elapsed_time(e1) / reps
+    lat = []
+    for _ in range(50):
+        A.copy_(A0)
+        B.copy_(B0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=info, stream=stream)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    hqr.profile_begin()
+    hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=info, stream=stream)
+    prof = hqr.profile_end()
+    kms = prof.get("small_lsq", (float("nan"), 1))[0]
+    fl = qr_flops(m, n)
+    one_cu_peak = PEAK_F64_TFLOPS / 256.0
+    achieved = fl / (kms * 1e-3) / 1e12
+    roof = {"kernel": "small_lsq", "bound": "alu", "achieved": achieved, "peak": one_cu_peak, "unit": "TFLOP/s",
+            "frac": achieved / one_cu_peak, "traffic": None, "launches": 1, "avg_launch_ms": kms,
+            "note": "one workgroup: peak is one CU's FP64 rate (78.6/256 TFLOP/s)"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        ts = []
+        for _ in range(100):
+            t0 = time.perf_counter()
+            oracle.lsq_solve(A_h, b_h)
+            ts.append(time.perf_counter() - t0)
+        cpu = {"value": fl / np.median(ts) / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": "oracle lsq_solve of the same 128x64 problem, median of 100 (%.1f us)" % (np.median(ts) * 1e6)}
+    cfg = {"workload": "FP64 QR + LSQ solve, 128x64, 1 RHS", "m": m, "n": n, "us_per_call_back_to_back": per_call * 1e3,
+           "single_call_latency_us_median": float(np.median(lat)) * 1e3, "kernel_us": kms * 1e3}
+    print(json.dumps(_line((METRIC, "GFLOP/s"), fl / (per_call * 1e-3) / 1e9, per_call, args, cfg, roof, cpu)),
+          flush=True)
+
+
+def run_served(args):
+    """Poisson stream of LSQ requests: n log-uniform in [16, 2048], m = n + U{0..n/2},
+    1-4 RHS, 3 successive solves per instance on its cached factor, 64 GB
+    admission budget.  Saturation throughput first (everything submitted at
+    t=0), then arrival rates 0.5/0.8/0.95 x saturation; p50/p99 latency."""
+    import torch
+    from paper_2506_09463_amd.server import GpuExecutor, Server, make_stream, poisson_arrivals, GiB
+
+    ninst = args.count if args.count != 2000 else 300
+    t0 = time.time()
+    base = make_stream(ninst, seed=6, solves_per_instance=3)
+    # pre-pin host data so uploads are asynchronous
+    for r in base:
+        r.B = torch.from_numpy(np.asfortranarray(r.B)).pin_memory()
+        if r.A is not None:
+            r.A = torch.from_numpy(np.asfortranarray(r.A)).pin_memory()
+    print("[bench] %d requests (%d instances) in %.1f s" % (len(base), ninst, time.time() - t0),
+          file=sys.stderr, flush=True)
+    import copy
+
+    def fresh():
+        out = []
+        for r in base:
+            c = copy.copy(r)
+            c.t_arrival, c.t_done, c.x, c.status = 0.0, -1.0, None, "new"
+            out.append(c)
+        return out
+
+    class _B:  # numpy-like view for shape access on pinned tensors
+        pass
+
+    def run(rate):
+        reqs = fresh()
+        ex = GpuExecutor(nstreams=2)
+        srv = Server(ex, budget_bytes=64 * GiB)
+        start = time.perf_counter()
+        if rate is None:
+            for r in reqs:
+                r.t_arrival = start
+                srv.submit(r)
+            srv.drain(timeout=600)
+        else:
+            arr = poisson_arrivals(rate, len(reqs), seed=7)
+            i = 0
+            while i < len(reqs) or srv.busy():
+                now = time.perf_counter() - start
+                while i < len(reqs) and arr[i] <= now:
+                    reqs[i].t_arrival = start + arr[i]
+                    srv.submit(reqs[i])
+                    i += 1
+                srv.step()
+                if time.perf_counter() - start > 900:
+                    raise TimeoutError("served run did not finish")
+        torch.cuda.synchronize()
+        return srv.stats()
+
+    run(None)  # warm-up
+    sat = run(None)
+    print("[bench] saturation: %s" % sat, file=sys.stderr, flush=True)
+    rate_sat = sat["throughput_per_s"]
+    loads = {}
+    for f in (0.5, 0.8, 0.95):
+        st = run(f * rate_sat)
+        loads["%.2f" % f] = st
+        print("[bench] load %.2f: %s" % (f, st), file=sys.stderr, flush=True)
+    cfg = {"workload": "served LSQ stream: %d instances x 3 solves, n log-uniform [16,2048], m = n + U{0..n/2}, "
+                       "1-4 RHS, factor reuse, 64 GB budget, 2 streams" % ninst,
+           "requests": len(base), "saturation": sat, "poisson_loads": loads,
+           "note": "precision flag carried; mixed-flagged requests are served in FP64 by this executor"}
+    p99 = loads["0.80"]["p99_ms"]
+    print(json.dumps(_line(("p99 latency at 0.8 x saturation", "ms"), p99, sat["mean_ms"], args, cfg,
+                           None, None, hib=False)), flush=True)
+
+
+OTHER = {"batched": run_batched, "small": run_small, "served": run_served}
 
 
 if __name__ == "__main__":

@@ -134,6 +134,20 @@ int qr_lsq_solve_batched(int count, const int64_t *m, const int64_t *n,
                          double *const *resnorm, int *info, void *work,
                          int64_t lwork, hipStream_t stream);
 
+/* The same persistent launch over a mix of new and already-factored
+ * problems (factor reuse across successive solves): factored[i] (HOST int
+ * array) nonzero means A[i] and up[i] already hold qr_factor's output for
+ * instance i, which is then only applied to B[i] (Q^T B, residual norms,
+ * back-substitution; A[i], up[i] untouched); zero means factor as in
+ * qr_lsq_solve_batched.  Other arguments as there. */
+int qr_lsq_batched_mixed(int count, const int64_t *m, const int64_t *n,
+                         const int64_t *nrhs, double *const *A,
+                         const int64_t *lda, double *const *up,
+                         double *const *B, const int64_t *ldb,
+                         double *const *resnorm, const int *factored,
+                         int *info, void *work, int64_t lwork,
+                         hipStream_t stream);
+
 /* Kernel timing for measurement.  hqr_profile_begin() starts recording: every
  * kernel the library launches afterwards (on any stream) is bracketed by a
  * pair of HIP events on that stream, grouped by kernel class.

@@ -24,6 +24,7 @@ struct BatchDesc {
     double *up;
     double *resnorm; // may be null
     int64_t index;   // position in the caller's arrays (info slot)
+    int64_t factor;  // 1: factor A (B fused); 0: A, up hold a stored factorization
 };
 
 struct BatchArgs {
@@ -63,13 +64,25 @@ HQR_DEV void batch_instance(const BatchDesc &d, int *info, double *xs, double *d
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t m = d.m, n = d.n, ntot = d.n + d.nrhs;
+    const bool factor = d.factor != 0;
+    const int64_t jlo = factor ? 0 : n;        // first column a reflector updates (beyond k)
     for (int64_t k = 0; k < n; ++k) {
         const double *ak = d.A + (size_t)k * d.lda;
         // stage the pivot column (rows k..m-1)
         for (int64_t i = k + tid; i < m; i += 1024) xs[i] = ak[i];
+        if (!factor && tid == 0) {
+            sc[0] = d.up[k];
+            sc[3] = ak[k];                     // R[k][k] as stored
+        }
         __syncthreads();
-        // dots of the tail with every column j >= k, max|x| and #nonzero
-        for (int64_t j = k + w; j < ntot; j += BATCH_NW) {
+        if (!factor && sc[0] == 0.0) {         // identity reflector
+            __syncthreads();
+            continue;
+        }
+        // dots of the tail with every column j updated (and with itself when
+        // factoring: ||tail||^2, max|x|, #nonzero)
+        const int64_t jfirst = factor ? k : n;
+        for (int64_t j = jfirst + w; j < ntot; j += BATCH_NW) {
             const double *cj = bcol(d, j);
             double s = 0.0, mx = 0.0, nz = 0.0;
             for (int64_t i = k + 1 + lane; i < m; i += 64) {
@@ -92,7 +105,7 @@ HQR_DEV void batch_instance(const BatchDesc &d, int *info, double *xs, double *d
             if (lane == 0) dots[j] = s;
         }
         __syncthreads();
-        if (tid == 0) {
+        if (factor && tid == 0) {
             const double x0 = xs[k];
             double upk, sk;
             if (sc[2] == 0.0) {
@@ -123,7 +136,8 @@ HQR_DEV void batch_instance(const BatchDesc &d, int *info, double *xs, double *d
         const double upk = sc[0], sk = sc[3];
         if (upk != 0.0) {
             const double bk = upk * sk;
-            for (int64_t j = k + 1 + w; j < ntot; j += BATCH_NW) {
+            const int64_t jup = factor ? k + 1 : jlo;
+            for (int64_t j = jup + w; j < ntot; j += BATCH_NW) {
                 double *cj = bcol(d, j);
                 const double wj = (upk * cj[k] + dots[j]) / bk;
                 for (int64_t i = k + lane; i < m; i += 64) {
@@ -132,7 +146,7 @@ HQR_DEV void batch_instance(const BatchDesc &d, int *info, double *xs, double *d
                 }
             }
         }
-        if (tid == 0) d.A[(size_t)k * d.lda + k] = sk;
+        if (factor && tid == 0) d.A[(size_t)k * d.lda + k] = sk;
         __syncthreads();
     }
     // residual norms

@@ -100,7 +100,7 @@ struct SmallCfg {
 template <int NW, int RW, int Q>
 static SmallCfg make_small()
 {
-    const size_t st = sizeof(double) * (2 * NW * (Q * 64 + 2) + 2 * Q * 64 + NW) + 16;
+    const size_t st = sizeof(double) * (2 * NW * (Q * 64 + 2) + 2 * Q * 64 + NW + Q * 64 + 2 * NW * RW) + 16;
     return SmallCfg{NW, RW, Q, small_lsq_kernel<NW, RW, Q>, st};
 }
 
@@ -650,10 +650,10 @@ extern "C" int64_t hqr_batched_workspace_size(int count)
     return (int64_t)(align256(sizeof(BatchDesc) * (size_t)std::max(count, 1)) + 256);
 }
 
-extern "C" int qr_lsq_solve_batched(int count, const int64_t *m, const int64_t *n, const int64_t *nrhs,
-                                    double *const *A, const int64_t *lda, double *const *up, double *const *B,
-                                    const int64_t *ldb, double *const *resnorm, int *info, void *work,
-                                    int64_t lwork, hipStream_t stream)
+static int lsq_batched_impl(int count, const int64_t *m, const int64_t *n, const int64_t *nrhs, double *const *A,
+                            const int64_t *lda, double *const *up, double *const *B, const int64_t *ldb,
+                            double *const *resnorm, const int *factored, int *info, void *work, int64_t lwork,
+                            hipStream_t stream)
 {
     if (count < 0) return -1;
     if (count == 0) return 0;
@@ -677,7 +677,8 @@ extern "C" int qr_lsq_solve_batched(int count, const int64_t *m, const int64_t *
         if (ldb[i] < std::max<int64_t>(1, m[i])) return -9;
         if (n[i] > 0 && (!A[i] || !up[i])) return -5;
         if (nrhs[i] > 0 && !B[i]) return -8;
-        d[i] = BatchDesc{m[i], n[i], nrhs[i], lda[i], ldb[i], A[i], B[i], up[i], resnorm ? resnorm[i] : nullptr, i};
+        d[i] = BatchDesc{m[i], n[i], nrhs[i], lda[i], ldb[i], A[i], B[i], up[i], resnorm ? resnorm[i] : nullptr, i,
+                         (factored && factored[i]) ? 0 : 1};
         const double mm = (double)m[i], nn = (double)n[i];
         cost[i] = 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * (double)nrhs[i] + mm;
         max_ntot = std::max<int>(max_ntot, (int)(n[i] + nrhs[i]));
@@ -715,6 +716,23 @@ extern "C" int qr_lsq_solve_batched(int count, const int64_t *m, const int64_t *
     HQR_LAUNCH(K_BATCHED, batched_lsq_kernel, dim3(grid), dim3(1024), 0, stream, a);
     HQR_CK(hipGetLastError());
     return 0;
+}
+
+extern "C" int qr_lsq_solve_batched(int count, const int64_t *m, const int64_t *n, const int64_t *nrhs,
+                                    double *const *A, const int64_t *lda, double *const *up, double *const *B,
+                                    const int64_t *ldb, double *const *resnorm, int *info, void *work,
+                                    int64_t lwork, hipStream_t stream)
+{
+    return lsq_batched_impl(count, m, n, nrhs, A, lda, up, B, ldb, resnorm, nullptr, info, work, lwork, stream);
+}
+
+extern "C" int qr_lsq_batched_mixed(int count, const int64_t *m, const int64_t *n, const int64_t *nrhs,
+                                    double *const *A, const int64_t *lda, double *const *up, double *const *B,
+                                    const int64_t *ldb, double *const *resnorm, const int *factored, int *info,
+                                    void *work, int64_t lwork, hipStream_t stream)
+{
+    if (!factored) return -11;
+    return lsq_batched_impl(count, m, n, nrhs, A, lda, up, B, ldb, resnorm, factored, info, work, lwork, stream);
 }
 
 extern "C" {

@@ -34,6 +34,7 @@ struct SmallArgs {
     double *resnorm;
     int *info;
     int ldl; // leading dimension of the LDS staging copy (>= m)
+    long long *tstamp; // optional phase timestamps (thread 0), may be null
 };
 
 // Leading dimension of the LDS staging copy: odd, so that lanes reading one
@@ -46,6 +47,16 @@ static inline size_t small_dyn_lds(int m, int n, int nrhs)
     return sizeof(double) * (size_t)small_ldl(m) * (size_t)(n + nrhs);
 }
 
+// a[q] for a runtime q < Q (select chain; the array stays in registers)
+template <int Q>
+HQR_DEV double pickq(const double (&a)[Q], int q)
+{
+    double r = a[0];
+#pragma unroll
+    for (int t = 1; t < Q; ++t) r = (t == q) ? a[t] : r;
+    return r;
+}
+
 template <int NW, int RW, int Q>
 __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
 {
@@ -55,6 +66,8 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
     __shared__ double part[2][NW][PW];
     __shared__ double prow[2][NC];
     __shared__ double scal[NW];
+    __shared__ double sup[NC];   // reflector leading components (global up[] at the end)
+    __shared__ double vcol[NW][RW], xcol[NW][RW];
     __shared__ int sinfo;
     extern __shared__ double lds[];
 
@@ -62,6 +75,13 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
     const int m = p.m, n = p.n, nrhs = p.nrhs, ntot = n + nrhs, L = p.ldl;
     const bool factor = (p.mode & SMALL_FACTOR) != 0;
     const int row0 = w * RW;
+    int tsi = 0;
+#define HQR_STS()                                                                \
+    do {                                                                         \
+        if (p.tstamp && tid == 0) p.tstamp[tsi] = (long long)wall_clock64();     \
+        ++tsi;                                                                   \
+    } while (0)
+    HQR_STS();
 
     // ---- stage [A | B] into LDS (coalesced), then into registers
     for (int idx = tid; idx < m * ntot; idx += NT) {
@@ -69,6 +89,9 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
         lds[c * L + i] = (c < n) ? HQR_AT(p.A, i, c, p.lda) : HQR_AT(p.B, i, c - n, p.ldb);
     }
     if (tid == 0) sinfo = 0;
+    // apply mode reads the stored up[] once; no global memory in the step loop
+    if (!factor)
+        for (int k = tid; k < n; k += NT) sup[k] = p.up[k];
     __syncthreads();
 
     double a[RW][Q];
@@ -111,6 +134,7 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
     }
     __syncthreads();
 
+    HQR_STS();
     for (int k = 0; k < n; ++k) {
         const int par = k & 1, nxt = par ^ 1;
         // ---- reflector k, derived identically by every thread
@@ -160,9 +184,9 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
                 s_k = (x0 >= 0.0) ? -nu : nu;
                 up_k = x0 - s_k;
             }
-            if (tid == 0) p.up[k] = up_k;
+            if (tid == 0) sup[k] = up_k;
         } else {
-            up_k = p.up[k];
+            up_k = sup[k];
             s_k = x0; // R[k][k] as stored
         }
         const bool skip = (up_k == 0.0);
@@ -184,40 +208,61 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
         const int k1 = k + 1;
         const bool have_next = k1 < n;
 
-        // ---- apply H_k to my rows; accumulate the partials of step k+1
+        // ---- apply H_k to my rows; accumulate the partials of step k+1.
+        // Columns k and k+1 of this wave's rows are broadcast through LDS by
+        // their owner lanes (same wave: program order orders the accesses);
+        // every lane recomputes the updated column k+1 (x') itself with the
+        // same fused multiply-add its owner uses.
         const int kq = k >> 6, kl = k & 63, k1q = k1 >> 6, k1l = k1 & 63;
+        double wk1 = 0.0;
+        if (factor && have_next && !skip) {
+            double d = 0.0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) d += part[par][v][k1];
+            wk1 = (up_k * prow[par][k1] + d) / b_k;
+        }
+        if (lane == kl) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) vcol[w][r] = pickq<Q>(a[r], kq);
+        }
+        if (lane == k1l && have_next) {
+#pragma unroll
+            for (int r = 0; r < RW; ++r) xcol[w][r] = pickq<Q>(a[r], k1q);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double vv[RW], xv[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            vv[r] = vcol[w][r];
+            xv[r] = xcol[w][r];
+        }
+        const int rb = __builtin_amdgcn_readfirstlane(row0);
+        const bool upd1 = factor && !skip;
         double pn[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) pn[q] = 0.0;
         double mx = 0.0, nz = 0.0;
 #pragma unroll
         for (int r = 0; r < RW; ++r) {
-            const int i = row0 + r;
+            const int i = rb + r; // wave-uniform
             if (i < k || i >= m) continue;
-            double vsrc = 0.0;
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (q == kq) vsrc = a[r][q];
-            const double vi = (i == k) ? up_k : readlane_f64(vsrc, kl);
+            const double vi = (i == k) ? up_k : vv[r];
             // select, not multiply by zero: finished columns must not pick
             // up NaN/Inf from the reflector
 #pragma unroll
             for (int q = 0; q < Q; ++q) a[r][q] = act[q] ? a[r][q] + wj[q] * vi : a[r][q];
-            if (factor && i == k && lane == kl) {
+            if (factor && i == k) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    if (q == kq) a[r][q] = s_k;
+                for (int q = 0; q < Q; ++q) a[r][q] = (lane == kl && q == kq) ? s_k : a[r][q];
             }
             if (!have_next) continue;
             if (i == k1) {
 #pragma unroll
                 for (int q = 0; q < Q; ++q) prow[nxt][lane + 64 * q] = a[r][q];
             } else if (i > k1) {
-                double xs = 0.0;
-#pragma unroll
-                for (int q = 0; q < Q; ++q)
-                    if (q == k1q) xs = a[r][q];
-                double xi = readlane_f64(xs, k1l);
+                const double xi = upd1 ? xv[r] + wk1 * vi : xv[r];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) pn[q] += xi * a[r][q];
                 mx = fmax(mx, fabs(xi));
@@ -235,6 +280,7 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
         __syncthreads();
     }
 
+    HQR_STS();
     // ---- registers -> LDS
 #pragma unroll
     for (int r = 0; r < RW; ++r)
@@ -272,6 +318,7 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
         }
     }
 
+    HQR_STS();
     // ---- back-substitution: smallest k with R[k][k] == 0 blocks the solve
     if (p.mode & SMALL_SOLVE) {
         if (tid == 0) {
@@ -304,13 +351,18 @@ __global__ void __launch_bounds__(NW * 64) small_lsq_kernel(SmallArgs p)
     }
     __syncthreads();
 
+    HQR_STS();
     // ---- LDS -> global
+    if (factor)
+        for (int k = tid; k < n; k += NT) p.up[k] = sup[k];
     const int c0 = factor ? 0 : n;
     for (int idx = tid + c0 * m; idx < m * ntot; idx += NT) {
         const int c = idx / m, i = idx - c * m;
         if (c < n) HQR_AT(p.A, i, c, p.lda) = lds[c * L + i];
         else HQR_AT(p.B, i, c - n, p.ldb) = lds[c * L + i];
     }
+    HQR_STS();
+#undef HQR_STS
 }
 
 } // namespace hqr

@@ -25,7 +25,7 @@ HQR_PREC_FP64 = 0
 HQR_PREC_MIXED = 1
 
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_backsolve",
-           "qr_lsq_solve", "hqr_batched_workspace_size", "qr_lsq_solve_batched",
+           "qr_lsq_solve", "hqr_batched_workspace_size", "qr_lsq_solve_batched", "qr_lsq_batched_mixed",
            "hqr_profile_begin", "hqr_profile_end", "hqr_profile_class",
            "hqr_status_string", "hqr_version")
 
@@ -67,6 +67,8 @@ def load(path: str = LIB_PATH):
     lib.hqr_batched_workspace_size.restype = i64
     lib.qr_lsq_solve_batched.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, ip, vp, i64, vp]
     lib.qr_lsq_solve_batched.restype = ctypes.c_int
+    lib.qr_lsq_batched_mixed.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ip, vp, i64, vp]
+    lib.qr_lsq_batched_mixed.restype = ctypes.c_int
     lib.hqr_profile_begin.argtypes = []
     lib.hqr_profile_begin.restype = ctypes.c_int
     lib.hqr_profile_end.argtypes = [ctypes.c_int, vp, vp]
@@ -251,7 +253,7 @@ def profile_end(max_classes: int = 64):
     return out
 
 
-def qr_lsq_solve_batched(As, Bs, ups=None, resnorms=None, info=None, work=None, stream=None):
+def qr_lsq_solve_batched(As, Bs, ups=None, resnorms=None, info=None, work=None, stream=None, factored=None):
     """Solve a list of least-squares problems in one persistent launch.
 
     As, Bs: lists of column-major float64 device tensors (A_i m_i x n_i,
@@ -289,9 +291,15 @@ def qr_lsq_solve_batched(As, Bs, ups=None, resnorms=None, info=None, work=None, 
         info = torch.zeros(count, dtype=torch.int32, device=dev)
     lw = 0 if work is None else work.numel() * work.element_size()
     cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
-    _check("qr_lsq_solve_batched", lib.qr_lsq_solve_batched(
-        count, cast(ms), cast(ns), cast(rs), cast(pa), cast(ldas), cast(pu), cast(pb), cast(ldbs),
-        cast(pr), _ptr(info), _ptr(work), lw, _stream(stream)))
+    if factored is None:
+        _check("qr_lsq_solve_batched", lib.qr_lsq_solve_batched(
+            count, cast(ms), cast(ns), cast(rs), cast(pa), cast(ldas), cast(pu), cast(pb), cast(ldbs),
+            cast(pr), _ptr(info), _ptr(work), lw, _stream(stream)))
+    else:
+        fl = (ctypes.c_int * count)(*[1 if f else 0 for f in factored])
+        _check("qr_lsq_batched_mixed", lib.qr_lsq_batched_mixed(
+            count, cast(ms), cast(ns), cast(rs), cast(pa), cast(ldas), cast(pu), cast(pb), cast(ldbs),
+            cast(pr), cast(fl), _ptr(info), _ptr(work), lw, _stream(stream)))
     return ups, resnorms, info
 
 

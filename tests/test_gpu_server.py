@@ -1,0 +1,57 @@
+"""Served workload on the GPU: every result computed in the continuous-batching
+mix equals the result of the same requests served alone (bitwise for the
+batched path, within the stated tolerance for the whole-GPU path), and
+matches the oracle."""
+import numpy as np
+import pytest
+
+from paper_2506_09463_amd.server import GpuExecutor, Server, make_stream
+from tests.gpu_util import lsq_forward_bound
+
+pytestmark = pytest.mark.gpu
+
+
+def _serve(reqs, nstreams=2):
+    ex = GpuExecutor(nstreams=nstreams)
+    srv = Server(ex, budget_bytes=8 << 30)
+    for r in reqs:
+        srv.submit(r)
+        srv.step()
+    srv.drain(timeout=300)
+    return srv
+
+
+def _clone(r):
+    import copy
+    c = copy.copy(r)
+    c.t_arrival, c.t_done, c.x, c.status = 0.0, -1.0, None, "new"
+    return c
+
+
+def test_served_mix_equals_alone(oracle_mod):
+    import torch
+    assert torch.cuda.is_available()
+    reqs = make_stream(24, seed=6, solves_per_instance=3, nmax=700)
+    keep = {r.rid: _clone(r) for r in reqs}
+    mats = {r.instance: r.A.copy() for r in reqs if r.kind == "factor_solve"}
+    print("[case] served mix", len(reqs), flush=True)
+    srv = _serve(reqs)
+    assert len(srv.done) == len(reqs) and not srv.rejected
+    by_inst = {}
+    for r in reqs:
+        by_inst.setdefault(r.instance, []).append(keep[r.rid])
+    for inst, group in list(by_inst.items())[:10]:
+        print("[case] alone instance", inst, flush=True)
+        alone = _serve(group, nstreams=1)
+        for a in alone.done:
+            mix = next(r for r in reqs if r.rid == a.rid)
+            if a.n <= 512:
+                assert np.array_equal(a.x, mix.x), (inst, a.rid)
+            else:
+                assert np.allclose(a.x, mix.x, rtol=1e-9, atol=1e-12), (inst, a.rid)
+    for r in reqs[:12]:
+        A = mats[r.instance]
+        xo, *_ = oracle_mod.lsq_solve(A, r.B)
+        for c in range(r.nrhs):
+            rr = r.B[:, c] - A @ xo[:, c]
+            assert np.linalg.norm(r.x[:, c] - xo[:, c]) / np.linalg.norm(xo[:, c]) <= 2 * lsq_forward_bound(A, xo[:, c], rr)
