@@ -442,7 +442,76 @@ def run_served(args):
                            None, None, hib=False)), flush=True)
 
 
-OTHER = {"batched": run_batched, "small": run_small, "served": run_served}
+def run_mixed(args):
+    """Mixed precision (FP32-MFMA trailing updates, FP64 refinement) against
+    plain FP64 on the same GPU: 128x64 at kappa 1e2 and 1e6 (seeds 3, 4), and
+    the 8192x4096 kappa-1e6 matrix where the FP32 contraction can pay off.
+    Each step restores A and b (untimed) and times one call, which includes
+    the refinement and its convergence read-back."""
+    import torch
+    import paper_2506_09463_amd as hqr
+    from paper_2506_09463_amd import workloads
+    import oracle
+    oracle.build(force=False)
+    stream = torch.cuda.current_stream()
+
+    def timed(A0, B0, prec, steps):
+        m, n = A0.shape
+        A, B = A0.clone(), B0.clone()
+        up = torch.empty(n, dtype=torch.float64, device="cuda")
+        res = torch.empty(B0.shape[1], dtype=torch.float64, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        iters = torch.zeros(1, dtype=torch.int32, device="cuda")
+        kw = dict(precision=prec, A_orig=A0) if prec == hqr.HQR_PREC_MIXED else {}
+        ts = []
+        for i in range(args.warmup + steps):
+            A.copy_(A0)
+            B.copy_(B0)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=info, iters=iters, stream=stream, **kw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if i >= args.warmup:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts)), B[:n, 0].double().cpu().numpy(), int(info.item()), int(iters.item())
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    cases = []
+    for kappa, seed in ((1e2, workloads.SEED_MIXED[0]), (1e6, workloads.SEED_MIXED[1])):
+        A_h, b_h, _ = workloads.conditioned(128, 64, kappa, seed=seed)
+        A0, B0 = hqr.colmajor(A_h), hqr.colmajor(b_h.reshape(-1, 1))
+        ms64, x64, _, _ = timed(A0, B0, hqr.HQR_PREC_FP64, max(args.steps, 20))
+        msmx, xmx, info, it = timed(A0, B0, hqr.HQR_PREC_MIXED, max(args.steps, 20))
+        xref, _ = oracle.lsq_reference(A_h, b_h)
+        xo = oracle.lsq_solve(A_h, b_h)[0][:, 0]
+        cases.append({"shape": "128x64", "kappa": kappa, "ms_fp64": ms64, "ms_mixed": msmx,
+                      "speedup_vs_fp64": ms64 / msmx, "refine_steps": it, "info": info,
+                      "err_vs_xref": rel(xmx, xref), "err_vs_oracle": rel(xmx, xo),
+                      "fp64_err_vs_xref": rel(x64, xref)})
+        print("[bench] mixed %s" % cases[-1], file=sys.stderr, flush=True)
+    m, n = 8192, 4096
+    A_h, b_h, _ = workloads.conditioned(m, n, 1e6, seed=workloads.SEED_LARGE)
+    A0, B0 = hqr.colmajor(A_h), hqr.colmajor(b_h.reshape(-1, 1))
+    ms64, x64, _, _ = timed(A0, B0, hqr.HQR_PREC_FP64, args.steps)
+    msmx, xmx, info, it = timed(A0, B0, hqr.HQR_PREC_MIXED, args.steps)
+    big = {"shape": "8192x4096", "kappa": 1e6, "ms_fp64": ms64, "ms_mixed": msmx, "speedup_vs_fp64": ms64 / msmx,
+           "refine_steps": it, "info": info, "err_vs_fp64_gpu": rel(xmx, x64),
+           "gflops_mixed": qr_flops(m, n) / (msmx * 1e-3) / 1e9}
+    print("[bench] mixed %s" % big, file=sys.stderr, flush=True)
+    cfg = {"workload": "mixed-precision QR + LSQ with refinement: 128x64 at kappa 1e2/1e6 and 8192x4096 at kappa 1e6",
+           "cases": cases + [big],
+           "note": "value = 8192x4096 rate in (2mn^2-2/3n^3)/s; errors are relative 2-norm errors of x; x_ref = "
+                   "oracle solution refined with 80-bit residuals"}
+    print(json.dumps(_line((METRIC, "GFLOP/s"), big["gflops_mixed"], msmx, args, cfg, None, None, dtype="f32+f64")),
+          flush=True)
+
+
+OTHER = {"batched": run_batched, "small": run_small, "mixed": run_mixed, "served": run_served}
 
 
 if __name__ == "__main__":

@@ -223,6 +223,9 @@ HQR_DEV double x_elem(const VtxArgs &p, int64_t gi, int x)
 // while the current one is multiplied.
 constexpr int VTX_COLS = 128;
 
+// F32: operands rounded to FP32, FP32 MFMA with FP32 accumulation (the
+// partial sums are stored widened to FP64).
+template <bool F32>
 __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
 {
     __shared__ double Vs[KC][NB + 1];
@@ -233,8 +236,12 @@ __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
     const int64_t r_end = min<int64_t>(p.m, r_begin + p.split_rows);
 
     f64x4 acc[8];
+    f32x4 acc32[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 8; ++t) {
+        acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+        acc32[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
 
     // staging layout: thread t loads rows (t % KC) of columns t / KC + 8 q
     constexpr int VPT = KC * NB / 256;       // V elements per thread
@@ -305,20 +312,24 @@ __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const double b = Xs[kr][16 * t + (lane & 15)];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+                if (F32)
+                    acc32[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(to_f32(a), to_f32(b), acc32[t], 0, 0, 0);
+                else
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
             }
         }
         __syncthreads();
     }
-    // D[i][j] at lane j + 16*(i%4), register i/4
+    // FP64 MFMA: D[i][j] at lane j + 16*(i%4), register i/4;
+    // FP32 MFMA: D[i][j] at lane j + 16*(i/4), register i%4
     double *out = p.wpart + (size_t)blockIdx.y * NB * p.nxpad;
 #pragma unroll
     for (int t = 0; t < 8; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = 16 * w + 4 * r + (lane >> 4);
+            const int i = F32 ? 16 * w + 4 * (lane >> 4) + r : 16 * w + 4 * r + (lane >> 4);
             const int x = x0 + 16 * t + (lane & 15);
-            if (x < p.nxpad) out[(size_t)i * p.nxpad + x] = acc[t][r];
+            if (x < p.nxpad) out[(size_t)i * p.nxpad + x] = F32 ? (double)acc32[t][r] : acc[t][r];
         }
 }
 
@@ -462,6 +473,9 @@ HQR_DEV double *col_ptr(const UpdArgs &p, int c)
 // four 128-byte segments.
 constexpr int UPD_TILE = 128;
 
+// F32: V and W' rounded to FP32, the product accumulated in FP32 by FP32
+// MFMA from zero, then subtracted from the FP64 trailing matrix.
+template <bool F32>
 __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -474,23 +488,28 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
     const bool masked = rb < (int64_t)p.c0 + p.bw; // rows that meet the triangle of V
 
     f64x4 acc[4][4]; // [column tile][row tile]
+    f32x4 acc32[4][4];
     double *cptr[4][4];
+    // accumulator register r of lane (li, lk) holds column cb + 16 tj + ccol(r), row li
+#define HQR_CCOL(r) (F32 ? 4 * lk + (r) : 4 * (r) + lk)
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int c = cb + 16 * tj + 4 * r + lk;
+            const int c = cb + 16 * tj + HQR_CCOL(r);
             cptr[tj][r] = (c < ncols) ? col_ptr(p, c) : nullptr;
         }
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-        for (int ti = 0; ti < 4; ++ti)
+        for (int ti = 0; ti < 4; ++ti) {
+            acc32[tj][ti] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb + 16 * ti + li;
-                acc[tj][ti][r] = (cptr[tj][r] && gi < p.m) ? cptr[tj][r][gi] : 0.0;
+                acc[tj][ti][r] = (!F32 && cptr[tj][r] && gi < p.m) ? cptr[tj][r][gi] : 0.0;
             }
+        }
 
     const double *wrow = p.wp + p.xoff + cb + li;
 #pragma unroll 2
@@ -512,7 +531,12 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti) acc[tj][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tj], b[ti], acc[tj][ti], 0, 0, 0);
+            for (int ti = 0; ti < 4; ++ti) {
+                if (F32)
+                    acc32[tj][ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(to_f32(a[tj]), to_f32(b[ti]), acc32[tj][ti], 0, 0, 0);
+                else
+                    acc[tj][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tj], b[ti], acc[tj][ti], 0, 0, 0);
+            }
     }
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
@@ -521,8 +545,12 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb + 16 * ti + li;
-                if (cptr[tj][r] && gi < p.m) cptr[tj][r][gi] = acc[tj][ti][r];
+                if (cptr[tj][r] && gi < p.m) {
+                    if (F32) cptr[tj][r][gi] = cptr[tj][r][gi] + (double)acc32[tj][ti][r];
+                    else cptr[tj][r][gi] = acc[tj][ti][r];
+                }
             }
+#undef HQR_CCOL
 }
 
 // ------------------------------------------------------------ triangular
@@ -558,6 +586,9 @@ struct TrsvArgs {
 
 constexpr int TRSV_MAXRHS = 8;
 
+// TRANS: solve R^T x = b instead (forward substitution; workgroup b owns
+// row block b and waits for the blocks above it).
+template <bool TRANS>
 __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
 {
     __shared__ double xs[64][TRSV_MAXRHS];
@@ -568,7 +599,7 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
     const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
     if (*((volatile int *)p.info) != 0) return;
     const int nblk = (int)((p.n + 63) / 64);
-    const int ib = nblk - 1 - (int)blockIdx.x;
+    const int ib = TRANS ? (int)blockIdx.x : nblk - 1 - (int)blockIdx.x;
     const int64_t r0 = (int64_t)ib * 64;
     const int nr = (int)min<int64_t>(64, p.n - r0);
     const int nrhs = p.nrhs;
@@ -578,7 +609,8 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
 #pragma unroll
     for (int c = 0; c < TRSV_MAXRHS; ++c) acc[c] = 0.0;
     __syncthreads();
-    for (int jb = nblk - 1; jb > ib; --jb) {
+    for (int jj = 0; jj < (TRANS ? ib : nblk - 1 - ib); ++jj) {
+        const int jb = TRANS ? jj : nblk - 1 - jj;
         if (tid == 0) {
             long s = 0;
             while (__hip_atomic_load(&p.flags[jb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != p.epoch) {
@@ -601,7 +633,7 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
         if (lane < nr) {
 #pragma unroll 4
             for (int l = g; l < nc; l += 4) {
-                const double rv = HQR_AT(p.A, r0 + lane, c0 + l, p.lda);
+                const double rv = TRANS ? HQR_AT(p.A, c0 + l, r0 + lane, p.lda) : HQR_AT(p.A, r0 + lane, c0 + l, p.lda);
 #pragma unroll
                 for (int c = 0; c < TRSV_MAXRHS; ++c) acc[c] += rv * xs[l][c];
             }
@@ -630,11 +662,20 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
             double t = 0.0;
             if (lane < nr)
                 t = accs[lane][c] - (((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c]);
-            for (int i = nr - 1; i >= 0; --i) {
-                const double ti = readlane_f64(t, i);
-                const double xi = ti / Rd[i][i];
-                if (lane < i) t -= Rd[lane][i] * xi;
-                if (lane == i) t = xi;
+            if (TRANS) {
+                for (int i = 0; i < nr; ++i) {
+                    const double ti = readlane_f64(t, i);
+                    const double xi = ti / Rd[i][i];
+                    if (lane > i && lane < nr) t -= Rd[i][lane] * xi;
+                    if (lane == i) t = xi;
+                }
+            } else {
+                for (int i = nr - 1; i >= 0; --i) {
+                    const double ti = readlane_f64(t, i);
+                    const double xi = ti / Rd[i][i];
+                    if (lane < i) t -= Rd[lane][i] * xi;
+                    if (lane == i) t = xi;
+                }
             }
             accs[lane][c] = t;
         }
@@ -684,6 +725,96 @@ __global__ void __launch_bounds__(256) resnorm_kernel(const double *B, int64_t l
     if (lane == 0) ss[g] = t;
     __syncthreads();
     if (tid == 0) out[blockIdx.x] = gmx * sqrt(((ss[0] + ss[1]) + ss[2]) + ss[3]);
+}
+
+// r = b - A x  (FP64), one thread per row; x staged in LDS in chunks.
+__global__ void __launch_bounds__(256) resid_kernel(const double *A, int64_t lda, const double *b, const double *x,
+                                                    double *r, int64_t m, int64_t n)
+{
+    __shared__ double xs[1024];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += 1024) {
+        const int64_t nj = min<int64_t>(1024, n - j0);
+        __syncthreads();
+        for (int64_t j = threadIdx.x; j < nj; j += 256) xs[j] = x[j0 + j];
+        __syncthreads();
+        if (i < m)
+            for (int64_t j = 0; j < nj; ++j) s += HQR_AT(A, i, j0 + j, lda) * xs[j];
+    }
+    if (i < m) r[i] = b[i] - s;
+}
+
+// g = A^T r (FP64): one wave per column, lanes down the rows.
+__global__ void __launch_bounds__(256) gemvt_kernel(const double *A, int64_t lda, const double *r, double *g,
+                                                    int64_t m, int64_t n)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= n) return;
+    const double *aj = A + (size_t)j * lda;
+    double s = 0.0;
+    for (int64_t i = lane; i < m; i += 64) s += aj[i] * r[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) g[j] = s;
+}
+
+// One correction step of the semi-normal equations: x += dx.  Records in
+// stat[0] the first (1-based) step that converged: ||dx|| <= tol ||x||, or
+// ||dx|| stopped shrinking (more than half the previous ||dx||) at a level
+// below 1e-8 ||x|| (the corrections reached FP64 rounding).  stat[1] = 1
+// when the corrections stall above that level for two steps (failure).
+// st[0] keeps the previous ||dx||.  One workgroup.
+__global__ void __launch_bounds__(1024) csne_update_kernel(double *x, const double *dx, int64_t n, double tol,
+                                                           int step, int *stat, double *st)
+{
+    __shared__ double s1[16], s2[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double a = 0.0, b = 0.0;
+    for (int64_t j = tid; j < n; j += 1024) {
+        const double xn = x[j] + dx[j];
+        x[j] = xn;
+        a += dx[j] * dx[j];
+        b += xn * xn;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    if (lane == 0) {
+        s1[w] = a;
+        s2[w] = b;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double da = 0.0, xb = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            da += s1[q];
+            xb += s2[q];
+        }
+        const double ndx = sqrt(da), nx = sqrt(xb);
+        if (step == 0) {
+            stat[1] = 0;
+            stat[2] = 0;
+        }
+        if (stat[0] == 0) {
+            if (ndx <= tol * nx) {
+                stat[0] = step + 1;
+            } else if (step > 0 && ndx > 0.5 * st[0]) {
+                if (ndx <= 1e-8 * nx) {
+                    stat[0] = step + 1;
+                } else {
+                    stat[2] += 1;
+                    if (stat[2] >= 2) stat[1] = 1;
+                }
+            } else {
+                stat[2] = 0;
+            }
+        }
+        st[0] = ndx;
+    }
 }
 
 __global__ void fill_int_kernel(int *p, int v, int64_t count)

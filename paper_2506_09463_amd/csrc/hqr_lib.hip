@@ -25,12 +25,12 @@ namespace hqr {
 // by a pair of HIP events recorded on the launch's own stream.
 enum KClass {
     K_SMALL, K_PANEL, K_VTX, K_TFACTOR, K_WSOLVE, K_UPDATE, K_DIAG, K_TRSV, K_RESNORM, K_FILL,
-    K_CQR_GRAM, K_CQR_CHOL, K_CQR_FINISH, K_PANEL_EXACT, K_GRED, K_BATCHED, K_NCLASS
+    K_CQR_GRAM, K_CQR_CHOL, K_CQR_FINISH, K_PANEL_EXACT, K_GRED, K_BATCHED, K_REFINE, K_NCLASS
 };
 static const char *kclass_name[K_NCLASS] = {"small_lsq", "panel_col", "vtx", "tfactor", "wsolve",
                                             "update", "diag_check", "trsv", "resnorm", "fill",
                                             "cqr_gram", "cqr_chol", "cqr_finish", "panel_exact",
-                                            "gram_reduce", "batched_lsq"};
+                                            "gram_reduce", "batched_lsq", "refine"};
 struct ProfRec {
     int cls;
     hipEvent_t e0, e1;
@@ -148,13 +148,17 @@ struct Plan {
     int nblk;        // triangular blocks
     int ngroups;     // CholeskyQR row groups of the first panel (upper bound)
     int npanels;
+    int nb;          // panel width (<= NB)
+    bool f32;        // trailing-update contractions in FP32
 };
 
 static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
-static Plan make_plan(int64_t m, int64_t n, int64_t nrhs)
+static Plan make_plan(int64_t m, int64_t n, int64_t nrhs, int nb = NB, bool f32 = false)
 {
     Plan p;
+    p.nb = nb;
+    p.f32 = f32;
     p.m = m;
     p.n = n;
     p.nrhs = nrhs;
@@ -163,7 +167,7 @@ static Plan make_plan(int64_t m, int64_t n, int64_t nrhs)
     p.nsplit_max = 16;
     p.nblk = (int)((n + 63) / 64);
     p.ngroups = (int)((m + CQR_ROWS - 1) / CQR_ROWS);
-    p.npanels = (int)((n + NB - 1) / NB);
+    p.npanels = (int)((n + nb - 1) / nb);
     return p;
 }
 
@@ -173,6 +177,8 @@ struct Work {
     int *flags;
     int *iscratch;
     double *gpart, *r1, *r1inv, *winv, *G;
+    double *borig, *rvec, *gvec, *mstat_d;   // mixed precision: original B, residual, A^T r, ||dx||
+    int *mstat;                              // mixed precision: [first converged step, stagnation, run]
     unsigned long long *mask, *mask_all;
     int *pflag;
 };
@@ -203,10 +209,20 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *wi = take(sizeof(double) * NB * NB);
     char *mk = take(sizeof(unsigned long long) * (size_t)p.ngroups);
     char *pf = take(sizeof(int) * (size_t)std::max(p.npanels, 1));
+    char *bo = take(sizeof(double) * (size_t)p.m * (size_t)std::max<int64_t>(p.nrhs, 1));
+    char *rv = take(sizeof(double) * (size_t)std::max<int64_t>(p.m, 1));
+    char *gv = take(sizeof(double) * (size_t)std::max<int64_t>(p.m, 1));
+    char *msd = take(sizeof(double) * 64);
+    char *ms = take(sizeof(int) * 64);
     char *gg = take(sizeof(double) * NB * NB);
     char *ma = take(sizeof(unsigned long long));
     if (w) {
         w->G = (double *)gg;
+        w->borig = (double *)bo;
+        w->rvec = (double *)rv;
+        w->gvec = (double *)gv;
+        w->mstat_d = (double *)msd;
+        w->mstat = (int *)ms;
         w->mask_all = (unsigned long long *)ma;
         w->gpart = (double *)gp;
         w->r1 = (double *)r1;
@@ -250,7 +266,7 @@ struct TrailBufs {
 // panel's T is already in tb.T; otherwise it is formed from V^T V.
 static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int64_t lda, double *B, int64_t ldb,
                              const double *up, int c0, int bw, int aoff, int ncA, int nB, bool have_t,
-                             hipStream_t s)
+                             hipStream_t s, bool f32 = false)
 {
     const int64_t rows = pl.m - c0;
     VtxArgs v;
@@ -274,7 +290,10 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     v.split_rows = rup((rows + nsplit - 1) / nsplit, KC);
     const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
     v.wpart = tb.wpart;
-    HQR_LAUNCH(K_VTX, vtx_kernel, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
+    if (f32)
+        HQR_LAUNCH(K_VTX, vtx_kernel<true>, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
+    else
+        HQR_LAUNCH(K_VTX, vtx_kernel<false>, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
     HQR_CK(hipGetLastError());
 
     if (!have_t) {
@@ -321,7 +340,11 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     u.xoff = vcols;
     u.wp = tb.wp;
     u.nxpad = pl.nxpad;
-    HQR_LAUNCH(K_UPDATE, update_kernel, dim3((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols + UPD_TILE - 1) / UPD_TILE), dim3(256), 0, s, u);
+    const dim3 ug((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols + UPD_TILE - 1) / UPD_TILE);
+    if (f32)
+        HQR_LAUNCH(K_UPDATE, update_kernel<true>, ug, dim3(256), 0, s, u);
+    else
+        HQR_LAUNCH(K_UPDATE, update_kernel<false>, ug, dim3(256), 0, s, u);
     HQR_CK(hipGetLastError());
     return 0;
 }
@@ -495,16 +518,16 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
         return panel_cqr(pl, w, A, lda, up, (int)c0, bw, pidx, Tbuf[pidx & 1], s);
     };
     if (!ss) {
-        for (int64_t c0 = 0; c0 < n; c0 += NB) {
-            const int bw = (int)std::min<int64_t>(NB, n - c0);
-            const int pidx = (int)(c0 / NB);
+        for (int64_t c0 = 0; c0 < n; c0 += pl.nb) {
+            const int bw = (int)std::min<int64_t>(pl.nb, n - c0);
+            const int pidx = (int)(c0 / pl.nb);
             int rc = do_panel(c0, bw, pidx);
             if (rc) return rc;
             const int ncA = (int)(n - c0 - bw);
             TrailBufs b = bufN;
             b.T = Tbuf[pidx & 1];
             if (ncA + nB > 0) {
-                rc = apply_panel_block(pl, b, A, lda, B, ldb, up, (int)c0, bw, 0, ncA, nB, have_t, s);
+                rc = apply_panel_block(pl, b, A, lda, B, ldb, up, (int)c0, bw, 0, ncA, nB, have_t, s, pl.f32);
                 if (rc) return rc;
             }
         }
@@ -514,14 +537,14 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
     // side stream starts after everything already on the caller's stream
     HQR_CK(hipEventRecord(ev_fork, s));
     HQR_CK(hipStreamWaitEvent(ss->stream, ev_fork, 0));
-    int rc = do_panel(0, (int)std::min<int64_t>(NB, n), 0);
+    int rc = do_panel(0, (int)std::min<int64_t>(pl.nb, n), 0);
     if (rc) return rc;
     bool pending_r = false;
-    for (int64_t c0 = 0; c0 < n; c0 += NB) {
-        const int bw = (int)std::min<int64_t>(NB, n - c0);
-        const int pidx = (int)(c0 / NB);
+    for (int64_t c0 = 0; c0 < n; c0 += pl.nb) {
+        const int bw = (int)std::min<int64_t>(pl.nb, n - c0);
+        const int pidx = (int)(c0 / pl.nb);
         const int64_t c1 = c0 + bw;                       // next panel
-        const int bw1 = (int)std::min<int64_t>(NB, std::max<int64_t>(0, n - c1));
+        const int bw1 = (int)std::min<int64_t>(pl.nb, std::max<int64_t>(0, n - c1));
         const int ncR = (int)std::max<int64_t>(0, n - c1 - bw1);
         TrailBufs bn = bufN, br = bufR;
         bn.T = br.T = Tbuf[pidx & 1];
@@ -529,13 +552,13 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
         HQR_CK(hipEventRecord(ev_a, s));
         HQR_CK(hipStreamWaitEvent(ss->stream, ev_a, 0));
         if (ncR + nB > 0) {
-            rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, have_t, ss->stream);
+            rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, have_t, ss->stream, pl.f32);
             if (rc) return rc;
         }
         // main: wait for R(p-1) (it updated this panel's next columns), then N(p), then P(p+1)
         if (pending_r) HQR_CK(hipStreamWaitEvent(s, ev_r, 0));
         if (bw1 > 0) {
-            rc = apply_panel_block(pl, bn, A, lda, B, ldb, up, (int)c0, bw, 0, bw1, 0, have_t, s);
+            rc = apply_panel_block(pl, bn, A, lda, B, ldb, up, (int)c0, bw, 0, bw1, 0, have_t, s, pl.f32);
             if (rc) return rc;
             rc = do_panel(c1, bw1, pidx + 1);
             if (rc) return rc;
@@ -550,7 +573,7 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
 }
 
 static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int64_t lda, double *B, int64_t ldb,
-                             int nrhs, int *info, hipStream_t s)
+                             int nrhs, int *info, hipStream_t s, bool trans = false)
 {
     HQR_LAUNCH(K_DIAG, diag_check_kernel, dim3(1), dim3(256), 0, s, A, lda, pl.n, info);
     HQR_CK(hipGetLastError());
@@ -568,7 +591,10 @@ static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int
         t.info = info;
         t.epoch = 1;
         t.spin_limit = 20000000L;
-        HQR_LAUNCH(K_TRSV, trsv_kernel, dim3(pl.nblk), dim3(256), 0, s, t);
+        if (trans)
+            HQR_LAUNCH(K_TRSV, trsv_kernel<true>, dim3(pl.nblk), dim3(256), 0, s, t);
+        else
+            HQR_LAUNCH(K_TRSV, trsv_kernel<false>, dim3(pl.nblk), dim3(256), 0, s, t);
         HQR_CK(hipGetLastError());
     }
     return 0;
@@ -595,6 +621,138 @@ static int get_work(const Plan &pl, void *work, int64_t lwork, hipStream_t s, Wo
         return HQR_ENOMEM;
     }
     work_bytes(pl, w, base);
+    return 0;
+}
+
+// The FP64 path: small problems in one register-resident workgroup, larger
+// ones by the blocked factorization, then residual norms and back-substitution.
+static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B, int64_t ldb,
+                    double *resnorm, void *work, int64_t lwork, int *info, hipStream_t s)
+{
+    if (n == 0) {
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
+        HQR_CK(hipGetLastError());
+        if (resnorm && nrhs > 0) {
+            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, (const double *)B, ldb,
+                       (int64_t)0, m, resnorm);
+            HQR_CK(hipGetLastError());
+        }
+        return 0;
+    }
+    if (const SmallCfg *c = pick_small(m, n, nrhs)) {
+        SmallArgs a{};
+        a.m = (int)m;
+        a.n = (int)n;
+        a.nrhs = (int)nrhs;
+        a.mode = SMALL_FACTOR | SMALL_SOLVE | (resnorm ? SMALL_RESNORM : 0);
+        a.lda = lda;
+        a.ldb = ldb;
+        a.A = A;
+        a.B = B;
+        a.up = up;
+        a.resnorm = resnorm;
+        a.info = info;
+        return launch_small(c, a, s) == hipSuccess ? 0 : HQR_EDEVICE;
+    }
+    Plan pl = make_plan(m, n, nrhs);
+    WorkGuard g;
+    Work w;
+    int rc = get_work(pl, work, lwork, s, g, &w);
+    if (rc) return rc;
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
+    HQR_CK(hipGetLastError());
+    rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, s);
+    if (rc) return rc;
+    if (nrhs == 0) return 0;
+    if (resnorm) {
+        HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, (const double *)B, ldb, n, m,
+                   resnorm);
+        HQR_CK(hipGetLastError());
+    }
+    return backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, s);
+}
+
+// Mixed precision: FP32 trailing contractions in the factorization, then
+// corrections of the semi-normal equations with FP64 residuals:
+//   r = b - A0 x,  g = A0^T r,  R^T z = g,  R dx = z,  x += dx
+// (A0 = the unmodified FP64 matrix, R = the factor's triangle).  A run of
+// max_iter steps is enqueued; the stream is synchronized once at the end to
+// read the convergence record and, without convergence, the FP64 path is
+// run on the restored inputs (info gets HQR_INFO_NOCONV).
+static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B,
+                     int64_t ldb, double *resnorm, const hqr_opts *opt, const double *A0, int64_t lda0, void *work,
+                     int64_t lwork, int *info, int *iters, hipStream_t s)
+{
+    const double tol = (opt && opt->tol > 0.0) ? opt->tol : 1e-13;
+    const int max_iter = (opt && opt->max_iter >= 0) ? opt->max_iter : 10;
+    const int nb = (n <= 256) ? 16 : NB;
+    Plan pl = make_plan(m, n, nrhs, nb, true);
+    WorkGuard g;
+    Work w;
+    int rc = get_work(pl, work, lwork, s, g, &w);
+    if (rc) return rc;
+    HQR_CK(hipMemcpy2DAsync(w.borig, sizeof(double) * m, B, sizeof(double) * ldb, sizeof(double) * m, nrhs,
+                            hipMemcpyDeviceToDevice, s));
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
+    HQR_CK(hipGetLastError());
+    rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, s);
+    if (rc) return rc;
+    rc = backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, s);
+    if (rc) return rc;
+    int total_first = 0;
+    bool converged = true;
+    for (int64_t c = 0; c < nrhs; ++c) {
+        double *x = B + (size_t)c * ldb;
+        const double *b0 = w.borig + (size_t)c * m;
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, w.mstat, 0, (int64_t)4);
+        HQR_CK(hipGetLastError());
+        for (int it = 0; it < max_iter; ++it) {
+            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
+                       (const double *)x, w.rvec, m, n);
+            HQR_LAUNCH(K_REFINE, gemvt_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, A0, lda0,
+                       (const double *)w.rvec, w.gvec, m, n);
+            HQR_CK(hipGetLastError());
+            rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, true);
+            if (rc) return rc;
+            rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, false);
+            if (rc) return rc;
+            HQR_LAUNCH(K_REFINE, csne_update_kernel, dim3(1), dim3(1024), 0, s, x, (const double *)w.gvec, n, tol,
+                       it, w.mstat, w.mstat_d);
+            HQR_CK(hipGetLastError());
+        }
+        if (resnorm) {
+            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
+                       (const double *)x, w.rvec, m, n);
+            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3(1), dim3(256), 0, s, (const double *)w.rvec,
+                       std::max<int64_t>(m, 1), (int64_t)0, m, resnorm + c);
+            HQR_CK(hipGetLastError());
+        }
+        int st[4] = {0, 0, 0, 0};
+        HQR_CK(hipMemcpyAsync(st, w.mstat, sizeof(st), hipMemcpyDeviceToHost, s));
+        HQR_CK(hipStreamSynchronize(s));
+        if (st[0] == 0 || st[1]) converged = false;
+        total_first = std::max(total_first, st[0]);
+    }
+    int hinfo = 0;
+    HQR_CK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+    HQR_CK(hipStreamSynchronize(s));
+    if (!converged && hinfo == 0) {
+        // FP64 fallback on the restored inputs: the same call as precision FP64
+        HQR_CK(hipMemcpy2DAsync(A, sizeof(double) * lda, A0, sizeof(double) * lda0, sizeof(double) * m, n,
+                                hipMemcpyDeviceToDevice, s));
+        HQR_CK(hipMemcpy2DAsync(B, sizeof(double) * ldb, w.borig, sizeof(double) * m, sizeof(double) * m, nrhs,
+                                hipMemcpyDeviceToDevice, s));
+        rc = lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, nullptr, 0, info, s);
+        if (rc) return rc;
+        hinfo = HQR_INFO_NOCONV;
+        HQR_CK(hipMemcpyAsync(info, &hinfo, sizeof(int), hipMemcpyHostToDevice, s));
+        total_first = max_iter;
+        HQR_CK(hipStreamSynchronize(s));
+    }
+    if (iters) {
+        HQR_CK(hipMemcpyAsync(iters, &total_first, sizeof(int), hipMemcpyHostToDevice, s));
+        HQR_CK(hipStreamSynchronize(s));
+    }
     return 0;
 }
 
@@ -743,7 +901,7 @@ int64_t hqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, int precision)
     if (n < 0 || n > m) return -2;
     if (nrhs < 0) return -3;
     if (precision != HQR_PREC_FP64 && precision != HQR_PREC_MIXED) return -4;
-    Plan pl = make_plan(m, n, nrhs);
+    Plan pl = (precision == HQR_PREC_MIXED) ? make_plan(m, n, nrhs, (n <= 256) ? 16 : NB, true) : make_plan(m, n, nrhs);
     return (int64_t)work_bytes(pl, nullptr, nullptr);
 }
 
@@ -868,7 +1026,17 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
     if (prec == HQR_PREC_MIXED) {
         if (!A_orig) return -11;
         if (lda_orig < std::max<int64_t>(1, m)) return -12;
-        return HQR_ENOTSUP; // mixed precision: not in this build yet
+        if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
+        if (iters) {
+            HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
+            HQR_CK(hipGetLastError());
+        }
+        if (n == 0 || nrhs == 0) {
+            HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+            return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
+        }
+        return lsq_mixed(m, n, nrhs, A, lda, up, B, ldb, resnorm, opt, A_orig, lda_orig, work, lwork, info, iters,
+                         stream);
     }
     (void)A_orig;
     (void)lda_orig;
@@ -877,47 +1045,7 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
         HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
         HQR_CK(hipGetLastError());
     }
-    if (n == 0) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
-        HQR_CK(hipGetLastError());
-        if (resnorm && nrhs > 0) {
-            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb,
-                               (int64_t)0, m, resnorm);
-            HQR_CK(hipGetLastError());
-        }
-        return 0;
-    }
-    if (const SmallCfg *c = pick_small(m, n, nrhs)) {
-        SmallArgs a{};
-        a.m = (int)m;
-        a.n = (int)n;
-        a.nrhs = (int)nrhs;
-        a.mode = SMALL_FACTOR | SMALL_SOLVE | (resnorm ? SMALL_RESNORM : 0);
-        a.lda = lda;
-        a.ldb = ldb;
-        a.A = A;
-        a.B = B;
-        a.up = up;
-        a.resnorm = resnorm;
-        a.info = info;
-        return launch_small(c, a, stream) == hipSuccess ? 0 : HQR_EDEVICE;
-    }
-    Plan pl = make_plan(m, n, nrhs);
-    WorkGuard g;
-    Work w;
-    int rc = get_work(pl, work, lwork, stream, g, &w);
-    if (rc) return rc;
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
-    HQR_CK(hipGetLastError());
-    rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, stream);
-    if (rc) return rc;
-    if (nrhs == 0) return 0;
-    if (resnorm) {
-        HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, stream, (const double *)B, ldb, n, m,
-                           resnorm);
-        HQR_CK(hipGetLastError());
-    }
-    return backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, stream);
+    return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, work, lwork, info, stream);
 }
 
 int hqr_profile_begin(void)

@@ -1,0 +1,76 @@
+"""Mixed precision on the GPU: FP32-MFMA trailing updates in the
+factorization, FP64 reflector generation and back-substitution, then
+corrections of the semi-normal equations with FP64 residuals.  The solution
+must be within 1e-10 (relative) of the extended-precision reference and of
+the plain FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2506_09463_amd import workloads
+from tests.gpu_util import lsq_forward_bound, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hqr():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2506_09463_amd as h
+    h.load()
+    return h
+
+
+def _mixed(hqr, A, b, **kw):
+    import torch
+    m, n = A.shape
+    dA, dB, dA0 = to_dev(A), to_dev(b.reshape(m, -1)), to_dev(A)
+    up, res, info, it = hqr.qr_lsq_solve(dA, dB, precision=hqr.HQR_PREC_MIXED, A_orig=dA0, **kw)
+    torch.cuda.synchronize()
+    return to_host(dB)[:n], to_host(res), int(info.item()), int(it.item())
+
+
+@pytest.mark.parametrize("m,n,kappa,seed", [(128, 64, 1e2, 3), (128, 64, 1e6, 4), (1000, 400, 1e6, 14),
+                                            (300, 70, 1e4, 15)])
+def test_mixed_reaches_1e10(hqr, oracle_mod, m, n, kappa, seed):
+    A, b, _ = workloads.conditioned(m, n, kappa, seed=seed)
+    print("[case] mixed", (m, n, kappa), flush=True)
+    X, res, info, iters = _mixed(hqr, A, b)
+    assert info == 0 and 1 <= iters <= 10
+    xref, rref = oracle_mod.lsq_reference(A, b)
+    xo = oracle_mod.lsq_solve(A, b)[0][:, 0]
+    x = X[:, 0]
+    assert np.linalg.norm(x - xref) / np.linalg.norm(xref) <= 1e-10
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-10
+    assert abs(res[0] - np.linalg.norm(b - A @ x)) <= 1e-12 * max(1.0, np.linalg.norm(b))
+
+
+def test_mixed_multiple_rhs(hqr, oracle_mod):
+    A, b, _ = workloads.conditioned(256, 100, 1e5, seed=16)
+    rng = np.random.default_rng(17)
+    B = np.stack([b, rng.standard_normal(256)], axis=1)
+    X, res, info, iters = _mixed(hqr, A, B)
+    for c in range(2):
+        xref, _ = oracle_mod.lsq_reference(A, B[:, c])
+        assert np.linalg.norm(X[:, c] - xref) / np.linalg.norm(xref) <= 1e-10
+
+
+@pytest.mark.parametrize("m,n", [(300, 100), (128, 64)])
+def test_mixed_fallback_when_refinement_cannot_converge(hqr, oracle_mod, m, n):
+    """With no refinement steps allowed the run cannot converge: the inputs
+    are restored, the FP64 path runs (bitwise the plain FP64 call) and the
+    result is flagged."""
+    import torch
+    A, b, _ = workloads.conditioned(m, n, 1e6, seed=18)
+    print("[case] fallback", (m, n), flush=True)
+    X, res, info, iters = _mixed(hqr, A, b, max_iter=0)
+    assert info & hqr.HQR_INFO_NOCONV
+    dA, dB = to_dev(A), to_dev(b.reshape(m, 1))
+    _, res64, info64, _ = hqr.qr_lsq_solve(dA, dB)
+    torch.cuda.synchronize()
+    assert int(info64.item()) == 0
+    assert np.array_equal(X, to_host(dB)[:n])
+    assert np.array_equal(res, to_host(res64))
+    xo = oracle_mod.lsq_solve(A, b)[0][:, 0]
+    r = b - A @ xo
+    assert np.linalg.norm(X[:, 0] - xo) / np.linalg.norm(xo) <= 2 * lsq_forward_bound(A, xo, r)
