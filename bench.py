@@ -33,27 +33,90 @@ METRIC = "QR GFLOP/s (2mn²−⅔n³) vs plain FP64; batched LSQ solves/s; p99 l
 PEAK_F64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch (read, write) of each kernel class on the default
+# workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled by the
+# same counters on a 1 GiB device copy (x2.0 and x1.0).  Valid only for the
+# kernel sources they were taken on (SHA-256 over csrc/); otherwise the
+# roofline's traffic is null.
+HBM_TRAFFIC = {
+    "csrc_sha256": "9c39f7631a7ed9f7c63ad63d38e47f149bea5bc050ffbd521f6243182b025e89",
+    "per_launch_bytes": {"cqr_chol": [129477, 82176], "update": [79272085, 55855379], "vtx": [69597759, 8928377],
+                         "cqr_gram": [3366868, 1590024], "wsolve": [8590799, 521192], "trsv": [68576538, 34816],
+                         "cqr_finish": [3443620, 3129344], "gram_reduce": [1621357, 32784]},
+}
+
+
+def csrc_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2506_09463_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def qr_flops(m, n):
     return 2.0 * m * n * n - 2.0 / 3.0 * n ** 3
 
 
 def class_work(m, n, nrhs, nb=64):
-    """Algorithmic work per kernel class over one solve.
+    """Algorithmic work of each kernel class over one solve, per panel of
+    width bw at row offset c0 (m_p = m - c0 rows, ncols = trailing columns
+    plus right-hand sides).  Returns {class: (bound, amount, peak, unit)}:
 
-    update: C <- C - V W' is 2 * M_p * bw * ncols flops per panel;
-    vtx: W = V^T [V | C | B] is 2 * M_p * bw * (bw + ncols) flops per panel;
-    panel_col: each of the bw+1 launches of a panel reads and writes the
-    M_p x bw panel once (16 * M_p * bw bytes)."""
-    upd = vtx = pbytes = 0.0
+      vtx         W = V^T [C | B] (T comes from the panel):
+                  2 m_p bw ncols flops                                 (FP64 MFMA)
+      update      C <- C - V W': reads and writes C, reads V and W':
+                  16 m_p ncols + 8 m_p bw + 8 bw ncols bytes (2 m_p bw ncols
+                  flops: 7.9 flop/B at bw = 64, under the FP64 ridge)  (HBM)
+      cqr_gram    Gram of the panel (pass 1), then Q1 = A_p R1^-1 and its
+                  Gram (pass 2): 2 m_p bw^2 + 4 m_p bw^2 flops         (FP64 MFMA)
+      cqr_finish  Y_bot = A_bot W^-1: 2 (m_p - bw) bw^2 flops          (FP64 MFMA)
+      gram_reduce sum of the per-workgroup Gram partials: reads
+                  ceil(m_p/128) bw^2 doubles, writes bw^2, per pass    (HBM)
+      wsolve      sum of split-K partials of W and W' = T^T W: reads
+                  nsplit bw ncols doubles, writes bw ncols             (HBM)
+      cqr_chol    64 x 64 Cholesky/inverse/LU work of one workgroup:
+                  2/3 bw^3 flops (pass 1) + 14/3 bw^3 (pass 2)          (one CU)
+      trsv        reads the n x n triangle once: 4 n^2 bytes            (HBM)
+    """
+    out = {}
+
+    def add(k, bound, amount):
+        b, a = out.get(k, (bound, 0.0))
+        out[k] = (bound, a + amount)
+
     for c0 in range(0, n, nb):
         bw = min(nb, n - c0)
         mp = m - c0
         ncols = n - c0 - bw + nrhs
-        upd += 2.0 * mp * bw * ncols
-        vtx += 2.0 * mp * bw * (bw + ncols)
-        pbytes += (bw + 1) * 16.0 * mp * bw
-    return {"update": ("mfma", upd), "vtx": ("mfma", vtx), "panel_col": ("hbm", pbytes)}
+        ngroups = -(-mp // 128)
+        ntiles = -(-ncols // 128)
+        nsplit = max(1, min(-(-512 // max(ntiles, 1)), max(1, mp // 256), 16))
+        add("vtx", "mfma", 2.0 * mp * bw * ncols)
+        add("update", "hbm", 16.0 * mp * ncols + 8.0 * mp * bw + 8.0 * bw * ncols)
+        add("cqr_gram", "mfma", 6.0 * mp * bw * bw)
+        add("cqr_finish", "mfma", 2.0 * max(mp - bw, 0) * bw * bw)
+        add("gram_reduce", "hbm", 2 * 8.0 * (ngroups + 1) * bw * bw)
+        add("wsolve", "hbm", 8.0 * (nsplit + 1) * bw * ncols)
+        add("cqr_chol", "cu", (2.0 / 3.0 + 14.0 / 3.0) * bw ** 3)
+    add("trsv", "hbm", 4.0 * n * n)
+    peaks = {"mfma": (PEAK_F64_TFLOPS, "TFLOP/s", 1e12), "hbm": (PEAK_HBM_GBS, "GB/s", 1e9),
+             "cu": (PEAK_F64_TFLOPS / 256.0, "TFLOP/s", 1e12)}
+    return {k: (b, a) + peaks[b] for k, (b, a) in out.items()}
+
+
+def roofline_entry(name, work, prof):
+    """Roofline of one kernel class from its summed event time and launch count."""
+    bound, amount, peak, unit, scale = work
+    t_ms, cnt = prof[name]
+    avg_ms = t_ms / cnt
+    achieved = amount / cnt / (avg_ms * 1e-3) / scale
+    return {"kernel": name, "bound": "alu" if bound == "cu" else bound, "achieved": achieved, "peak": peak,
+            "unit": unit, "frac": achieved / peak, "traffic": None, "launches_per_step": None,
+            "avg_launch_ms": avg_ms, "algorithmic_per_launch": amount / cnt}
 
 
 def cpu_baseline(A_host, ncols):
@@ -85,6 +148,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "small", "batched", "mixed", "served"],
                     help="large (default, the headline line), or one of the other configurations")
     ap.add_argument("--count", type=int, default=2000, help="batched: number of instances")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 3 device-to-device copies of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -99,6 +164,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": nel * 8, "copies": 3}), flush=True)
+        return
     hqr.load()
     if args.workload != "large":
         return OTHER[args.workload](args)
@@ -133,25 +207,39 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    times = []
+    # The timed region: K steps.  Then K more steps of the same workload with
+    # every library launch bracketed by HIP events on its own stream (the
+    # per-kernel durations of the roofline; the events slow a step down, so
+    # these steps are not the ones `value` comes from).
+    def run_steps(k):
+        ts = []
+        for _ in range(k):
+            restore()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            solve()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return ts
+
     wall0 = time.perf_counter()
-    for _ in range(args.steps):
-        restore()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        solve()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
+    times = run_steps(args.steps)
     wall = time.perf_counter() - wall0
+    prof = {}
+    prof_ms = None
+    if not args.no_profile:
+        hqr.profile_begin()
+        prof_ms = float(np.mean(run_steps(args.steps)))
+        prof = hqr.profile_end()
     ms = float(np.mean(times))
     if int(info.item()) != 0:
         print("bench.py: solve reported info=%d" % int(info.item()), file=sys.stderr)
         sys.exit(1)
-    print("[bench] timed %d steps: %.3f ms/step (min %.3f)" % (args.steps, ms, min(times)),
-          file=sys.stderr, flush=True)
+    print("[bench] timed %d steps: %.3f ms/step (min %.3f); with kernel events %s ms/step"
+          % (args.steps, ms, min(times), prof_ms), file=sys.stderr, flush=True)
 
     # accuracy of the last step: LSQ orthogonality and distance to x_true
     x = B[:n, 0].double().cpu().numpy()
@@ -160,31 +248,23 @@ def main():
     ortho = float(np.linalg.norm(A_h.T @ r) / (nA * (nA * np.linalg.norm(x) + np.linalg.norm(b_h))))
 
     roof = None
-    prof = {}
-    if not args.no_profile:
-        restore()
-        torch.cuda.synchronize()
-        hqr.profile_begin()
-        solve()
-        prof = hqr.profile_end()
+    classes = {}
+    if prof:
         work_by = class_work(m, n, 1)
-        dom = max((k for k in prof if k in work_by), key=lambda k: prof[k][0])
-        kind, amount = work_by[dom]
-        t_ms, cnt = prof[dom]
-        avg_ms = t_ms / cnt
-        per_launch = amount / cnt
-        if kind == "mfma":
-            achieved = per_launch / (avg_ms * 1e-3) / 1e12
-            roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_F64_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS, "traffic": None,
-                    "launches": cnt, "avg_launch_ms": avg_ms}
-        else:
-            achieved = per_launch / (avg_ms * 1e-3) / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                    "launches": cnt, "avg_launch_ms": avg_ms}
-        print("[bench] profile: " + ", ".join("%s %.3f ms/%d" % (k, v[0], v[1]) for k, v in
-                                                sorted(prof.items(), key=lambda kv: -kv[1][0])),
+        # per step: divide the summed time and launches by the step count
+        prof1 = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in prof.items()}
+        for k in prof1:
+            if k in work_by:
+                classes[k] = roofline_entry(k, work_by[k], prof1)
+        dom = max(classes, key=lambda k: prof1[k][0])
+        roof = dict(classes[dom])
+        roof["launches_per_step"] = prof1[dom][1]
+        if csrc_sha256() == HBM_TRAFFIC["csrc_sha256"] and dom in HBM_TRAFFIC["per_launch_bytes"]:
+            rd, wr = HBM_TRAFFIC["per_launch_bytes"][dom]
+            roof["traffic"] = rd + wr
+            roof["traffic_read_write"] = [rd, wr]
+        print("[bench] profile per step: " + ", ".join("%s %.3f ms/%d" % (k, v[0], v[1]) for k, v in
+                                                     sorted(prof1.items(), key=lambda kv: -kv[1][0])),
               file=sys.stderr, flush=True)
 
     cpu = None
@@ -211,7 +291,11 @@ def main():
                    "lsq_orthogonality": ortho,
                    "x_true_rel_err": float(np.linalg.norm(x - x_true) / np.linalg.norm(x_true)),
                    "wall_s_timed_loop": wall,
-                   "profile_ms": {k: round(v[0], 4) for k, v in prof.items()}},
+                   "ms_per_step_with_kernel_events": prof_ms,
+                   "profile_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
+                   "kernel_rooflines": {k: {"bound": v["bound"], "frac": round(v["frac"], 4),
+                                            "avg_launch_ms": round(v["avg_launch_ms"], 5)}
+                                        for k, v in classes.items()}},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
