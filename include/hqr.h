@@ -148,6 +148,31 @@ int qr_lsq_batched_mixed(int count, const int64_t *m, const int64_t *n,
                          int *info, void *work, int64_t lwork,
                          hipStream_t stream);
 
+/* Tuning rules that choose kernels (the autotuner's output is loaded through
+ * these).  A rule applies to problems with m_lo <= m <= m_hi and
+ * n_lo <= n <= n_hi at `precision`; the first rule added that matches wins.
+ *   op HQR_TUNE_SINGLE: path of one qr_factor / qr_apply_qt / qr_lsq_solve
+ *     problem: choice -1 = the blocked multi-kernel path, choice i >= 0 = the
+ *     one-workgroup kernel variant i (ignored where it cannot hold the
+ *     problem).  Without a rule, problems with n <= 128 that a variant holds
+ *     use the smallest such variant.
+ *   op HQR_TUNE_BATCHED: variant i of a batched launch, matched on the
+ *     largest m and n among the batch's instances that the one-workgroup
+ *     kernel takes (m <= 1024, n * nrhs within the smallest staging area);
+ *     only variants with 256 threads qualify (they share one arithmetic, so
+ *     results do not depend on the batch); without a rule, the smallest such
+ *     variant that holds the largest m.
+ * Host-side state, process-global, not thread-safe.  Returns 0 or -i. */
+#define HQR_TUNE_SINGLE  0
+#define HQR_TUNE_BATCHED 1
+int hqr_tune_set(int op, int64_t m_lo, int64_t m_hi, int64_t n_lo,
+                 int64_t n_hi, int precision, int choice);
+int hqr_tune_clear(void);
+/* Number of one-workgroup variants, and the name of variant i ("wgNTxQM":
+ * NT threads holding QM rows each, so m <= NT*QM), or NULL. */
+int hqr_tune_variants(void);
+const char *hqr_tune_variant_name(int i);
+
 /* Kernel timing for measurement.  hqr_profile_begin() starts recording: every
  * kernel the library launches afterwards (on any stream) is bracketed by a
  * pair of HIP events on that stream, grouped by kernel class.

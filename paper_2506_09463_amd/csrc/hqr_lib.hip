@@ -14,6 +14,7 @@
 #include "hqr_blocked.hpp"
 #include "hqr_cqr.hpp"
 #include "hqr_batched.hpp"
+#include "hqr_wg.hpp"
 
 #include <numeric>
 #include <vector>
@@ -88,6 +89,112 @@ static void prof_end(int cls, hipEvent_t e0, hipStream_t s)
         hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);         \
         prof_end(cls, e0_, stream);                                                \
     } while (0)
+
+// ------------------------------------------------- one-workgroup variants
+typedef void (*wg_batched_fn)(const WgDesc *, int, int *, int *);
+typedef void (*wg_single_fn)(WgDesc, int *);
+struct WgVariant {
+    const char *name;
+    int nt, qm, per_cu;
+    wg_batched_fn batched;
+    wg_single_fn single;
+    int64_t max_rows, max_x;
+};
+
+template <int NT, int QM>
+static WgVariant make_wg(const char *name)
+{
+    const int per_cu = (int)std::max<size_t>(1, (160 * 1024) / sizeof(WgShared<NT, QM>));
+    return WgVariant{name, NT, QM, std::min(per_cu, 2), wg_batched_kernel<NT, QM>, wg_single_kernel<NT, QM>,
+                     wg_max_rows<NT, QM>(), wg_max_x<NT, QM>()};
+}
+
+static const WgVariant *wg_variants(int *count)
+{
+    static const WgVariant v[] = {
+        make_wg<128, 4>("wg128x4"), // m <= 512
+        make_wg<256, 2>("wg256x2"), // m <= 512
+        make_wg<256, 4>("wg256x4"), // m <= 1024
+    };
+    *count = (int)(sizeof(v) / sizeof(v[0]));
+    return v;
+}
+
+static bool wg_fits(const WgVariant &v, int64_t m, int64_t n, int64_t nrhs)
+{
+    return m <= v.max_rows && n * nrhs <= v.max_x;
+}
+
+// Tuning rules (first match wins): op HQR_TUNE_SINGLE picks the path of one
+// problem (-1 = the blocked multi-kernel path, else a variant index), op
+// HQR_TUNE_BATCHED the variant of a batched launch from the batch's largest
+// m and n.  Without a matching rule: single problems with n <= 128 and
+// batches use the smallest variant that holds them.
+struct TuneRule {
+    int op;
+    int64_t mlo, mhi, nlo, nhi;
+    int prec, choice;
+};
+static std::vector<TuneRule> g_rules;
+
+static int tune_lookup(int op, int64_t m, int64_t n, int prec)
+{
+    for (const TuneRule &r : g_rules)
+        if (r.op == op && r.prec == prec && m >= r.mlo && m <= r.mhi && n >= r.nlo && n <= r.nhi) return r.choice;
+    return -2;
+}
+
+static const WgVariant *pick_wg_single(int64_t m, int64_t n, int64_t nrhs)
+{
+    int cnt = 0;
+    const WgVariant *v = wg_variants(&cnt);
+    const int c = tune_lookup(HQR_TUNE_SINGLE, m, n, HQR_PREC_FP64);
+    if (c == -1) return nullptr;
+    if (c >= 0 && c < cnt && wg_fits(v[c], m, n, nrhs)) return &v[c];
+    if (n > 128) return nullptr;
+    for (int i = 0; i < cnt; ++i)
+        if (wg_fits(v[i], m, n, nrhs)) return &v[i];
+    return nullptr;
+}
+
+// Batched launches use only the variants with BATCH_NT threads: with the
+// thread count fixed, the rows each thread holds (QM) change no arithmetic
+// (row-to-thread map, reduction trees and tile order depend on NT alone), so
+// an instance's result does not depend on the rest of the batch.  Whether an
+// instance goes to the one-workgroup kernel also depends on its own shape
+// only: m <= BATCH_WG_ROWS and n * nrhs within the smallest staging area.
+constexpr int BATCH_NT = 256;
+constexpr int64_t BATCH_WG_ROWS = 1024;
+
+static bool batch_variant(const WgVariant &v) { return v.nt == BATCH_NT; }
+
+static bool batch_wg_fits(int64_t m, int64_t n, int64_t nrhs)
+{
+    int cnt = 0;
+    const WgVariant *v = wg_variants(&cnt);
+    int64_t xmin = INT64_MAX;
+    for (int i = 0; i < cnt; ++i)
+        if (batch_variant(v[i])) xmin = std::min(xmin, v[i].max_x);
+    return m <= BATCH_WG_ROWS && n * nrhs <= xmin;
+}
+
+static const WgVariant *pick_wg_batched(int64_t mmax, int64_t nmax)
+{
+    int cnt = 0;
+    const WgVariant *v = wg_variants(&cnt);
+    const int c = tune_lookup(HQR_TUNE_BATCHED, mmax, nmax, HQR_PREC_FP64);
+    if (c >= 0 && c < cnt && batch_variant(v[c]) && v[c].max_rows >= mmax) return &v[c];
+    const WgVariant *best = nullptr;
+    for (int i = 0; i < cnt; ++i)
+        if (batch_variant(v[i]) && v[i].max_rows >= mmax && (!best || v[i].max_rows < best->max_rows)) best = &v[i];
+    return best;
+}
+
+static int launch_wg_single(const WgVariant *v, const WgDesc &d, int *info, hipStream_t s)
+{
+    HQR_LAUNCH(K_SMALL, v->single, dim3(1), dim3(v->nt), 0, s, d, info);
+    return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
+}
 
 // ------------------------------------------------------------- small path
 typedef void (*small_fn)(SmallArgs);
@@ -639,20 +746,13 @@ static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, 
         }
         return 0;
     }
-    if (const SmallCfg *c = pick_small(m, n, nrhs)) {
-        SmallArgs a{};
-        a.m = (int)m;
-        a.n = (int)n;
-        a.nrhs = (int)nrhs;
-        a.mode = SMALL_FACTOR | SMALL_SOLVE | (resnorm ? SMALL_RESNORM : 0);
-        a.lda = lda;
-        a.ldb = ldb;
-        a.A = A;
-        a.B = B;
-        a.up = up;
-        a.resnorm = resnorm;
-        a.info = info;
-        return launch_small(c, a, s) == hipSuccess ? 0 : HQR_EDEVICE;
+    if (const WgVariant *v = pick_wg_single(m, n, nrhs)) {
+        if (nrhs == 0) {
+            HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
+            HQR_CK(hipGetLastError());
+        }
+        const WgDesc d{m, n, nrhs, lda, ldb, A, B, up, resnorm, 0, WG_FACTOR | (nrhs > 0 ? WG_SOLVE : 0)};
+        return launch_wg_single(v, d, info, s);
     }
     Plan pl = make_plan(m, n, nrhs);
     WorkGuard g;
@@ -841,12 +941,37 @@ static int lsq_batched_impl(int count, const int64_t *m, const int64_t *n, const
         cost[i] = 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * (double)nrhs[i] + mm;
         max_ntot = std::max<int>(max_ntot, (int)(n[i] + nrhs[i]));
     }
-    // longest first; ties by caller order, so the order depends on shapes only
+    // The one-workgroup blocked kernel takes every instance the chosen variant
+    // holds; the rest (more rows, or n * nrhs beyond its staging area) go to
+    // the streaming kernel in a second launch.  Each group runs longest
+    // first; ties keep caller order, so the order depends on shapes only.
+    std::vector<char> fits((size_t)count);
+    int64_t mmax = 0, nmax = 0;
+    for (int i = 0; i < count; ++i) {
+        fits[i] = batch_wg_fits(m[i], n[i], nrhs[i]) ? 1 : 0;
+        if (fits[i]) {
+            mmax = std::max(mmax, m[i]);
+            nmax = std::max(nmax, n[i]);
+        }
+    }
+    const WgVariant *var = pick_wg_batched(mmax, nmax);
     std::vector<int> order((size_t)count);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (fits[a] != fits[b]) return fits[a] > fits[b];
+        return cost[a] > cost[b];
+    });
+    int nwg = 0;
+    while (nwg < count && fits[order[nwg]]) ++nwg;
     std::vector<BatchDesc> sorted((size_t)count);
     for (int i = 0; i < count; ++i) sorted[i] = d[order[i]];
+    static_assert(sizeof(WgDesc) == sizeof(BatchDesc), "descriptor layouts share the staging buffer");
+    std::vector<WgDesc> wsorted((size_t)nwg);
+    for (int i = 0; i < nwg; ++i) {
+        const BatchDesc &b = sorted[i];
+        wsorted[i] = WgDesc{b.m, b.n, b.nrhs, b.lda, b.ldb, b.A, b.B, b.up, b.resnorm, b.index,
+                            (b.factor ? WG_FACTOR : 0) | WG_SOLVE};
+    }
 
     const size_t need = (size_t)hqr_batched_workspace_size(count);
     WorkGuard g;
@@ -858,21 +983,33 @@ static int lsq_batched_impl(int count, const int64_t *m, const int64_t *n, const
     } else if (lwork < (int64_t)need) {
         return HQR_ENOMEM;
     }
-    BatchDesc *ddesc = (BatchDesc *)base;
+    char *dbase = base;
     int *head = (int *)(base + align256(sizeof(BatchDesc) * (size_t)count));
-    int rc = stage_upload(sorted.data(), sizeof(BatchDesc) * (size_t)count, ddesc, stream);
+    // one host image: WgDesc entries, then BatchDesc entries
+    std::vector<char> img(sizeof(BatchDesc) * (size_t)count);
+    memcpy(img.data(), wsorted.data(), sizeof(WgDesc) * (size_t)nwg);
+    memcpy(img.data() + sizeof(WgDesc) * (size_t)nwg, sorted.data() + nwg, sizeof(BatchDesc) * (size_t)(count - nwg));
+    int rc = stage_upload(img.data(), img.size(), dbase, stream);
     if (rc) return rc;
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, head, 0, (int64_t)1);
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, head, 0, (int64_t)2);
     HQR_CK(hipGetLastError());
-    BatchArgs a;
-    a.desc = ddesc;
-    a.count = count;
-    a.head = head;
-    a.info = info;
-    a.max_ntot = max_ntot;
-    const int grid = std::min(count, 2 * num_cus());
-    HQR_LAUNCH(K_BATCHED, batched_lsq_kernel, dim3(grid), dim3(1024), 0, stream, a);
-    HQR_CK(hipGetLastError());
+    if (nwg > 0) {
+        const int grid = std::min(nwg, var->per_cu * num_cus());
+        HQR_LAUNCH(K_BATCHED, var->batched, dim3(grid), dim3(var->nt), 0, stream, (const WgDesc *)dbase, nwg, head,
+                   info);
+        HQR_CK(hipGetLastError());
+    }
+    if (nwg < count) {
+        BatchArgs a;
+        a.desc = (const BatchDesc *)(dbase + sizeof(WgDesc) * (size_t)nwg);
+        a.count = count - nwg;
+        a.head = head + 1;
+        a.info = info;
+        a.max_ntot = max_ntot;
+        const int grid = std::min(count - nwg, 2 * num_cus());
+        HQR_LAUNCH(K_BATCHED, batched_lsq_kernel, dim3(grid), dim3(1024), 0, stream, a);
+        HQR_CK(hipGetLastError());
+    }
     return 0;
 }
 
@@ -919,18 +1056,11 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up, void *wo
         HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
         return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
     }
-    if (const SmallCfg *c = pick_small(m, n, 0)) {
-        SmallArgs a{};
-        a.m = (int)m;
-        a.n = (int)n;
-        a.nrhs = 0;
-        a.mode = SMALL_FACTOR;
-        a.lda = lda;
-        a.ldb = std::max<int64_t>(1, m);
-        a.A = A;
-        a.up = up;
-        a.info = info;
-        return launch_small(c, a, stream) == hipSuccess ? 0 : HQR_EDEVICE;
+    if (const WgVariant *v = pick_wg_single(m, n, 0)) {
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_CK(hipGetLastError());
+        const WgDesc d{m, n, 0, lda, std::max<int64_t>(1, m), A, nullptr, up, nullptr, 0, WG_FACTOR};
+        return launch_wg_single(v, d, info, stream);
     }
     Plan pl = make_plan(m, n, 0);
     WorkGuard g;
@@ -955,18 +1085,9 @@ int qr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda
     if (!up) return -6;
     if (!B) return -7;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
-    if (const SmallCfg *c = pick_small(m, n, nrhs)) {
-        SmallArgs a{};
-        a.m = (int)m;
-        a.n = (int)n;
-        a.nrhs = (int)nrhs;
-        a.mode = 0;
-        a.lda = lda;
-        a.ldb = ldb;
-        a.A = const_cast<double *>(A);
-        a.B = B;
-        a.up = const_cast<double *>(up);
-        return launch_small(c, a, stream) == hipSuccess ? 0 : HQR_EDEVICE;
+    if (const WgVariant *v = pick_wg_single(m, n, nrhs)) {
+        const WgDesc d{m, n, nrhs, lda, ldb, const_cast<double *>(A), B, const_cast<double *>(up), nullptr, 0, 0};
+        return launch_wg_single(v, d, nullptr, stream);
     }
     Plan pl = make_plan(m, n, nrhs);
     WorkGuard g;
@@ -1046,6 +1167,42 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
         HQR_CK(hipGetLastError());
     }
     return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, work, lwork, info, stream);
+}
+
+int hqr_tune_set(int op, int64_t m_lo, int64_t m_hi, int64_t n_lo, int64_t n_hi, int precision, int choice)
+{
+    if (op != HQR_TUNE_SINGLE && op != HQR_TUNE_BATCHED) return -1;
+    if (m_lo < 0) return -2;
+    if (m_hi < m_lo) return -3;
+    if (n_lo < 0) return -4;
+    if (n_hi < n_lo) return -5;
+    if (precision != HQR_PREC_FP64 && precision != HQR_PREC_MIXED) return -6;
+    int cnt = 0;
+    (void)wg_variants(&cnt);
+    if (choice < (op == HQR_TUNE_SINGLE ? -1 : 0) || choice >= cnt) return -7;
+    if (op == HQR_TUNE_BATCHED && !batch_variant(wg_variants(&cnt)[choice])) return -7;
+    g_rules.push_back(TuneRule{op, m_lo, m_hi, n_lo, n_hi, precision, choice});
+    return 0;
+}
+
+int hqr_tune_clear(void)
+{
+    g_rules.clear();
+    return 0;
+}
+
+int hqr_tune_variants(void)
+{
+    int cnt = 0;
+    (void)wg_variants(&cnt);
+    return cnt;
+}
+
+const char *hqr_tune_variant_name(int i)
+{
+    int cnt = 0;
+    const WgVariant *v = wg_variants(&cnt);
+    return (i >= 0 && i < cnt) ? v[i].name : nullptr;
 }
 
 int hqr_profile_begin(void)

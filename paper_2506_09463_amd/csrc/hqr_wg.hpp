@@ -1,0 +1,563 @@
+// hqr_wg.hpp -- one workgroup solves one least-squares problem, blocked.
+//
+// The factorization is the paper's one-reflector-per-column loop (Section 3,
+// Alg. 2, with the (up, b) storage of Alg. 3), grouped in panels of WG_P = 16
+// columns:
+//   * panel: the panel's rows are spread over the threads (thread t owns
+//     rows c0 + t + NT*q) and kept in registers.  For column k one block
+//     reduction gives, from each thread's own rows below the pivot,
+//     s_j = sum_r A[r][j] A[r][k] for all 16 panel columns j: j = k is the
+//     tail's squared norm, j > k the dots the reflector's application needs,
+//     j < k the dots v_j^T v_k of the compact-WY T factor.  Every thread then
+//     forms the same s = -sgn(x0)||x||, up = x0 - s, b = up s and updates its
+//     own rows, so one barrier per column suffices;
+//   * trailing update (and Q^T B, B's columns riding as trailing columns):
+//     Q_panel^T C = C - V T^T (V^T C) on FP64 MFMA, V and T staged in LDS,
+//     every wave owning whole 16-column tiles (no cross-wave reduction).
+// Then residual norms ||(Q^T B)[n:m]|| and a blocked back-substitution
+// (16-row diagonal blocks solved inside one wave, updates of the rows above
+// spread over the workgroup).
+//
+// A stored factorization (flags without WG_FACTOR) is applied instead: V is
+// read back from A and up, T rebuilt from V^T V.
+#pragma once
+
+#include <utility>
+
+#include "hqr_device.hpp"
+
+namespace hqr {
+
+constexpr int WG_P = 16;    // panel width
+constexpr int WG_LD = 17;   // LDS row stride (doubles) of V and T
+
+enum : int64_t { WG_FACTOR = 1, WG_SOLVE = 2 };
+
+struct WgDesc {
+    int64_t m, n, nrhs, lda, ldb;
+    double *A;
+    double *B;       // may be null when nrhs == 0
+    double *up;
+    double *resnorm; // may be null
+    int64_t index;   // info slot
+    int64_t flags;   // WG_FACTOR | WG_SOLVE
+};
+
+// Rows a variant holds (NT threads x QM rows) bound m; n * nrhs must fit the
+// V area for the back-substitution.
+template <int NT, int QM>
+struct WgShared {
+    double v[NT * QM * WG_LD];
+    double t[WG_P * WG_LD];
+    double red[2][NT / 64][WG_P + 1];
+    double prow[2][WG_P];
+    double aux[NT / 64];
+    int isc[4];
+};
+
+template <int NT, int QM>
+constexpr int64_t wg_max_rows() { return (int64_t)NT * QM; }
+template <int NT, int QM>
+constexpr int64_t wg_max_x() { return (int64_t)NT * QM * WG_LD; }
+
+// Sum of v[0..15] over the wave by recursive halving: lane L ends with the
+// total of index 8*b5 + 4*b4 + 2*b3 + b2 (b_i = bit i of L).
+HQR_DEV double wave_sum16(const double (&v)[WG_P], int lane)
+{
+    double a8[8], a4[4], a2[2];
+    const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0, h2 = (lane & 4) != 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const double keep = h5 ? v[8 + t] : v[t];
+        const double give = h5 ? v[t] : v[8 + t];
+        a8[t] = keep + __shfl_xor(give, 32);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double keep = h4 ? a8[4 + t] : a8[t];
+        const double give = h4 ? a8[t] : a8[4 + t];
+        a4[t] = keep + __shfl_xor(give, 16);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const double keep = h3 ? a4[2 + t] : a4[t];
+        const double give = h3 ? a4[t] : a4[2 + t];
+        a2[t] = keep + __shfl_xor(give, 8);
+    }
+    double a1 = (h2 ? a2[1] : a2[0]) + __shfl_xor(h2 ? a2[0] : a2[1], 4);
+    a1 += __shfl_xor(a1, 2);
+    a1 += __shfl_xor(a1, 1);
+    return a1;
+}
+
+HQR_DEV int wave_sum16_index(int lane)
+{
+    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+}
+
+// Block-wide sum (op 0) or max (op 1) of one value per thread; uniform result.
+template <int NT, int QM>
+HQR_DEV double wg_block_reduce(double x, int op, WgShared<NT, QM> &sh)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(x, o);
+        x = op ? fmax(x, y) : x + y;
+    }
+    __syncthreads();
+    if (lane == 0) sh.aux[w] = x;
+    __syncthreads();
+    double r = sh.aux[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) r = op ? fmax(r, sh.aux[i]) : r + sh.aux[i];
+    return r;
+}
+
+// ---------------------------------------------------------------- panel
+// One column step of the panel (k fixed at compile time so the register
+// arrays stay in registers).
+template <int NT, int QM, int k>
+HQR_DEV void wg_panel_step(const WgDesc &d, int64_t c0, int pw, double (&a)[QM][WG_P], double &myup,
+                           WgShared<NT, QM> &sh)
+{
+    constexpr int NWV = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t m = d.m;
+    if (k >= pw) return;
+
+    const int64_t pr = c0 + k;
+    const int buf = k & 1;
+    double s[WG_P];
+#pragma unroll
+    for (int j = 0; j < WG_P; ++j) s[j] = 0.0;
+    bool nz = false;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int64_t r = c0 + tid + (int64_t)NT * q;
+        if (r > pr && r < m) {
+            const double x = a[q][k];
+            nz = nz || (x != 0.0);
+#pragma unroll
+            for (int j = 0; j < WG_P; ++j) s[j] = fma(a[q][j], x, s[j]);
+        }
+    }
+    if (tid == k) {
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) sh.prow[buf][j] = a[0][j];
+    }
+    const double part = wave_sum16(s, lane);
+    const bool wnz = __ballot(nz) != 0ull;
+    if ((lane & 3) == 0) sh.red[buf][w][wave_sum16_index(lane)] = part;
+    if (lane == 0) sh.red[buf][w][WG_P] = wnz ? 1.0 : 0.0;
+    __syncthreads();
+    double S[WG_P], P[WG_P];
+    bool anynz = false;
+#pragma unroll
+    for (int j = 0; j < WG_P; ++j) {
+        double t = sh.red[buf][0][j];
+#pragma unroll
+        for (int i = 1; i < NWV; ++i) t += sh.red[buf][i][j];
+        S[j] = t;
+        P[j] = sh.prow[buf][j];
+    }
+#pragma unroll
+    for (int i = 0; i < NWV; ++i) anynz = anynz || (sh.red[buf][i][WG_P] != 0.0);
+    const double x0 = P[k];
+    double upk = 0.0, sk = x0;
+    if (anynz) {
+        const double tot = x0 * x0 + S[k];
+        double nu;
+        if (tot >= 0x1p-920 && tot <= 0x1p920) {
+            nu = sqrt(tot);
+        } else {
+            // scaled norm: max |x| over the column from the pivot down
+            double mx = 0.0;
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                const int64_t r = c0 + tid + (int64_t)NT * q;
+                if (r > pr && r < m) mx = fmax(mx, fabs(a[q][k]));
+            }
+            const double c = fmax(fabs(x0), wg_block_reduce<NT, QM>(mx, 1, sh));
+            double ss = 0.0;
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                const int64_t r = c0 + tid + (int64_t)NT * q;
+                if (r > pr && r < m) {
+                    const double y = a[q][k] / c;
+                    ss = fma(y, y, ss);
+                }
+            }
+            const double t2 = wg_block_reduce<NT, QM>(ss, 0, sh);
+            const double x0c = x0 / c;
+            nu = c * sqrt(x0c * x0c + t2);
+        }
+        sk = (x0 >= 0.0) ? -nu : nu;
+        upk = x0 - sk;
+    }
+    const double bk = upk * sk;
+    const double inv_b = anynz ? 1.0 / bk : 0.0;
+    if (tid == k) myup = upk;
+    // T column k: T[k][k] = tau_k = -1/b_k, T[i][k] = -tau_k sum_{l<k} T[i][l] (v_l^T v_k)
+    if (tid < k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < k; ++l) acc = fma(sh.t[tid * WG_LD + l], fma(P[l], upk, S[l]), acc);
+        sh.t[tid * WG_LD + k] = inv_b * acc;
+    } else if (tid == k) {
+        sh.t[tid * WG_LD + k] = -inv_b;
+    }
+    // apply H_k to the panel's columns k+1 .. pw-1 (own rows)
+    double wv[WG_P];
+#pragma unroll
+    for (int j = 0; j < WG_P; ++j) wv[j] = (j > k) ? fma(upk, P[j], S[j]) * inv_b : 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int64_t r = c0 + tid + (int64_t)NT * q;
+        if (r > pr && r < m) {
+            const double x = a[q][k];
+#pragma unroll
+            for (int j = k + 1; j < WG_P; ++j) a[q][j] = fma(wv[j], x, a[q][j]);
+        } else if (r == pr) {
+#pragma unroll
+            for (int j = k + 1; j < WG_P; ++j) a[q][j] = fma(wv[j], upk, a[q][j]);
+            a[q][k] = sk;
+        }
+    }
+    if (tid == 0) d.up[pr] = upk;
+}
+
+template <int NT, int QM, int... Ks>
+HQR_DEV void wg_panel_steps(const WgDesc &d, int64_t c0, int pw, double (&a)[QM][WG_P], double &myup,
+                            WgShared<NT, QM> &sh, std::integer_sequence<int, Ks...>)
+{
+    (wg_panel_step<NT, QM, Ks>(d, c0, pw, a, myup, sh), ...);
+}
+
+
+// Factor columns c0 .. c0+pw-1 (rows c0 .. m-1) in registers; write them
+// back, leave V (rows relative to c0, up on the diagonal, zeros above) and T
+// in LDS.  Ends with a barrier.
+template <int NT, int QM>
+HQR_DEV void wg_panel_factor(const WgDesc &d, int64_t c0, int pw, WgShared<NT, QM> &sh)
+{
+    constexpr int NWV = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t m = d.m;
+    double a[QM][WG_P];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int64_t r = c0 + tid + (int64_t)NT * q;
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) a[q][j] = (r < m && j < pw) ? d.A[(size_t)(c0 + j) * d.lda + r] : 0.0;
+    }
+    // up of the reflector whose pivot row this thread owns (V's diagonal);
+    // T row `tid` (tid < 16) lives in LDS, written and read by its thread only
+    double myup = 0.0;
+    if (tid < WG_P) {
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) sh.t[tid * WG_LD + j] = 0.0;
+    }
+    wg_panel_steps<NT, QM>(d, c0, pw, a, myup, sh, std::make_integer_sequence<int, WG_P>{});
+    // write back; V and T to LDS
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int64_t rr = tid + (int64_t)NT * q;
+        const int64_t r = c0 + rr;
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) {
+            if (r < m && j < pw) d.A[(size_t)(c0 + j) * d.lda + r] = a[q][j];
+            sh.v[rr * WG_LD + j] = (r >= m) ? 0.0 : (rr > j ? a[q][j] : (rr == j ? myup : 0.0));
+        }
+    }
+    __syncthreads();
+}
+
+// Stored factorization: V from A's tails and up, T from V^T V.  Ends with a
+// barrier.
+template <int NT, int QM>
+HQR_DEV void wg_panel_load(const WgDesc &d, int64_t c0, int pw, WgShared<NT, QM> &sh)
+{
+    constexpr int NWV = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t m = d.m;
+    const int64_t nrows = m - c0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int64_t rr = tid + (int64_t)NT * q;
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) {
+            double v = 0.0;
+            if (rr < nrows && j < pw) {
+                if (rr > j) v = d.A[(size_t)(c0 + j) * d.lda + c0 + rr];
+                else if (rr == j) v = d.up[c0 + j];
+            }
+            sh.v[rr * WG_LD + j] = v;
+        }
+    }
+    __syncthreads();
+    // G = V^T V: each wave sums the 16-row blocks w, w + NWV, .. on MFMA,
+    // then the waves add their partials into the T area in turn.
+    f64x4 g = {0.0, 0.0, 0.0, 0.0};
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int64_t nb16 = (nrows + 15) / 16;
+    for (int64_t rb = w; rb < nb16; rb += NWV) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t rr = rb * 16 + 4 * kq + s;
+            const double vv = sh.v[rr * WG_LD + i16];
+            g = __builtin_amdgcn_mfma_f64_16x16x4f64(vv, vv, g, 0, 0, 0);
+        }
+    }
+    // G[i][j] at lane j + 16 (i % 4), reg i / 4; waves add into sh.t in turn
+    for (int wv = 0; wv < NWV; ++wv) {
+        if (w == wv) {
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int i = 4 * r4 + kq;
+                double *dst = &sh.t[i * WG_LD + i16];
+                *dst = (wv == 0) ? g[r4] : *dst + g[r4];
+            }
+        }
+        __syncthreads();
+    }
+    // T row i by thread i (T upper): T[i][k] = -tau_k sum_{l=i}^{k-1} T[i][l] G[l][k]
+    double trow[WG_P];
+#pragma unroll
+    for (int j = 0; j < WG_P; ++j) trow[j] = 0.0;
+    if (tid < WG_P) {
+#pragma unroll
+        for (int k = 0; k < WG_P; ++k) {
+            if (k < pw) {
+                const double upk = d.up[c0 + k];
+                const double bk = upk * d.A[(size_t)(c0 + k) * d.lda + c0 + k];
+                const double inv_b = (upk != 0.0) ? 1.0 / bk : 0.0;
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < k; ++l) acc = fma(trow[l], sh.t[l * WG_LD + k], acc);
+                if (tid < k) trow[k] = inv_b * acc;
+                if (tid == k) trow[k] = -inv_b;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < WG_P) {
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) sh.t[tid * WG_LD + j] = trow[j];
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------- trailing update
+// C <- C - V T^T V^T C for the combined column list: A columns
+// colA .. colA+ncA-1 then all B columns; rows c0 .. m-1.
+HQR_DEV double *wg_colptr(const WgDesc &d, int64_t ci, int64_t colA, int64_t ncA, int64_t ntot)
+{
+    if (ci >= ntot) return nullptr;
+    return (ci < ncA) ? d.A + (size_t)(colA + ci) * d.lda : d.B + (size_t)(ci - ncA) * d.ldb;
+}
+
+template <int NT, int QM>
+HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA, WgShared<NT, QM> &sh)
+{
+    constexpr int NWV = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int64_t nrows = d.m - c0;
+    const int64_t ntot = ncA + d.nrhs;
+    const int64_t ntile = (ntot + 15) / 16;
+    const int64_t nb16 = (nrows + 15) / 16;
+    for (int64_t tile = w; tile < ntile; tile += NWV) {
+        // W = V^T C: A operand V^T[i][k] = V[rho(k)][i], B operand C[rho(k)][j]
+        const double *cp = wg_colptr(d, tile * 16 + i16, colA, ncA, ntot);
+        f64x4 acc[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int64_t rb = 0; rb < nb16; ++rb) {
+            const int64_t rr0 = rb * 16 + 4 * kq;
+            double cv[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cv[s] = (cp && rr0 + s < nrows) ? cp[c0 + rr0 + s] : 0.0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double av = sh.v[(rr0 + s) * WG_LD + i16];
+                acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cv[s], acc[s], 0, 0, 0);
+            }
+        }
+        f64x4 wm;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wm[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+        // W' = T^T W: A operand T^T[i][4q+k] = T[4q+k][i]; B operand = W's register q
+        f64x4 wp = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double tv = sh.t[(4 * q + kq) * WG_LD + i16];
+            wp = __builtin_amdgcn_mfma_f64_16x16x4f64(tv, wm[q], wp, 0, 0, 0);
+        }
+        // C^T <- C^T - W'^T V^T per 16-row block: D[c][row] at lane row + 16 (c % 4), reg c / 4
+        double *cq[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) cq[g] = wg_colptr(d, tile * 16 + 4 * g + kq, colA, ncA, ntot);
+        for (int64_t rb = 0; rb < nb16; ++rb) {
+            const int64_t rr = rb * 16 + i16;
+            const bool ok = rr < nrows;
+            f64x4 cacc;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) cacc[g] = (cq[g] && ok) ? cq[g][c0 + rr] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double bv = sh.v[rr * WG_LD + 4 * q + kq];
+                cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(-wp[q], bv, cacc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                if (cq[g] && ok) cq[g][c0 + rr] = cacc[g];
+        }
+    }
+}
+
+// ------------------------------------------------ residual norms, solve
+template <int NT, int QM>
+HQR_DEV void wg_resnorm(const WgDesc &d)
+{
+    constexpr int NWV = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int64_t c = w; c < d.nrhs; c += NWV) {
+        const double *bc = d.B + (size_t)c * d.ldb;
+        double s = 0.0, mx = 0.0;
+        for (int64_t i = d.n + lane; i < d.m; i += 64) {
+            s = fma(bc[i], bc[i], s);
+            mx = fmax(mx, fabs(bc[i]));
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            s += __shfl_xor(s, o);
+            mx = fmax(mx, __shfl_xor(mx, o));
+        }
+        if (mx != 0.0 && !norm_fast_path_ok(mx)) {
+            double t = 0.0;
+            for (int64_t i = d.n + lane; i < d.m; i += 64) {
+                const double y = bc[i] / mx;
+                t = fma(y, y, t);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+            if (lane == 0) d.resnorm[c] = mx * sqrt(t);
+        } else if (lane == 0) {
+            d.resnorm[c] = sqrt(s);
+        }
+    }
+}
+
+// R X = B[0:n]: info = smallest k+1 with R[k][k] == 0 (B untouched), else X
+// in B[0:n].  X staged column-major in the V area.
+template <int NT, int QM>
+HQR_DEV void wg_backsolve(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t n = d.n, nrhs = d.nrhs;
+    if (tid == 0) sh.isc[0] = 0x7fffffff;
+    __syncthreads();
+    for (int64_t k = tid; k < n; k += NT)
+        if (d.A[(size_t)k * d.lda + k] == 0.0) atomicMin(&sh.isc[0], (int)(k + 1));
+    __syncthreads();
+    const int bad = sh.isc[0];
+    if (tid == 0) info[d.index] = (bad == 0x7fffffff) ? 0 : bad;
+    if (bad != 0x7fffffff || nrhs == 0 || n == 0) {
+        __syncthreads();
+        return;
+    }
+    double *xs = sh.v;
+    for (int64_t idx = tid; idx < n * nrhs; idx += NT) {
+        const int64_t c = idx / n, i = idx % n;
+        xs[idx] = d.B[(size_t)c * d.ldb + i];
+    }
+    __syncthreads();
+    const int64_t nblk = (n + 15) / 16;
+    for (int64_t jb = nblk - 1; jb >= 0; --jb) {
+        const int64_t b0 = jb * 16;
+        const int bw = (int)((n - b0 < 16) ? n - b0 : 16);
+        if (w == 0) {
+            const int i = lane & 15, cg = lane >> 4;
+            double rrow[WG_P];
+#pragma unroll
+            for (int l = 0; l < WG_P; ++l) rrow[l] = (i < bw && l < bw) ? d.A[(size_t)(b0 + l) * d.lda + b0 + i] : 1.0;
+            for (int64_t cs = 0; cs < nrhs; cs += 4) {
+                const int64_t c = cs + cg;
+                const bool ok = (i < bw) && (c < nrhs);
+                double xi = ok ? xs[c * n + b0 + i] : 0.0;
+#pragma unroll
+                for (int l = WG_P - 1; l >= 0; --l) {
+                    if (l < bw) {
+                        const double cand = xi / rrow[l];
+                        const double xl = __shfl(cand, l + 16 * cg);
+                        if (i == l) xi = xl;
+                        else if (i < l) xi = fma(-rrow[l], xl, xi);
+                    }
+                }
+                if (ok) xs[c * n + b0 + i] = xi;
+            }
+        }
+        __syncthreads();
+        for (int64_t i = tid; i < b0; i += NT) {
+            double rv[WG_P];
+#pragma unroll
+            for (int l = 0; l < WG_P; ++l) rv[l] = (l < bw) ? d.A[(size_t)(b0 + l) * d.lda + i] : 0.0;
+            for (int64_t c = 0; c < nrhs; ++c) {
+                double acc = xs[c * n + i];
+#pragma unroll
+                for (int l = 0; l < WG_P; ++l) acc = fma(-rv[l], xs[c * n + b0 + l], acc);
+                xs[c * n + i] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    for (int64_t idx = tid; idx < n * nrhs; idx += NT) {
+        const int64_t c = idx / n, i = idx % n;
+        d.B[(size_t)c * d.ldb + i] = xs[idx];
+    }
+    __syncthreads();
+}
+
+template <int NT, int QM>
+HQR_DEV void wg_instance(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
+{
+    const bool factor = (d.flags & WG_FACTOR) != 0;
+    for (int64_t c0 = 0; c0 < d.n; c0 += WG_P) {
+        const int pw = (int)((d.n - c0 < WG_P) ? d.n - c0 : WG_P);
+        if (factor) wg_panel_factor<NT, QM>(d, c0, pw, sh);
+        else wg_panel_load<NT, QM>(d, c0, pw, sh);
+        const int64_t ncA = factor ? d.n - c0 - pw : 0;
+        wg_trailing<NT, QM>(d, c0, c0 + pw, ncA, sh);
+        __syncthreads();
+    }
+    if (d.resnorm && d.nrhs > 0) wg_resnorm<NT, QM>(d);
+    if (d.flags & WG_SOLVE) wg_backsolve<NT, QM>(d, info, sh);
+    __syncthreads();
+}
+
+// Persistent: workgroups take instances from an atomic queue head until it
+// passes `count`.
+template <int NT, int QM>
+__global__ void __launch_bounds__(NT) wg_batched_kernel(const WgDesc *desc, int count, int *head, int *info)
+{
+    __shared__ WgShared<NT, QM> sh;
+    for (;;) {
+        if (threadIdx.x == 0) sh.isc[1] = atomicAdd(head, 1);
+        __syncthreads();
+        const int id = sh.isc[1];
+        __syncthreads();
+        if (id >= count) break;
+        wg_instance<NT, QM>(desc[id], info, sh);
+    }
+}
+
+// One problem, descriptor by value (info slot d.index of `info`).
+template <int NT, int QM>
+__global__ void __launch_bounds__(NT) wg_single_kernel(WgDesc d, int *info)
+{
+    __shared__ WgShared<NT, QM> sh;
+    wg_instance<NT, QM>(d, info, sh);
+}
+
+} // namespace hqr

@@ -23,9 +23,13 @@ HQR_INFO_TIMEOUT = -2001
 HQR_INFO_NOCONV = 1 << 29
 HQR_PREC_FP64 = 0
 HQR_PREC_MIXED = 1
+HQR_TUNE_SINGLE = 0
+HQR_TUNE_BATCHED = 1
+TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_backsolve",
            "qr_lsq_solve", "hqr_batched_workspace_size", "qr_lsq_solve_batched", "qr_lsq_batched_mixed",
+           "hqr_tune_set", "hqr_tune_clear", "hqr_tune_variants", "hqr_tune_variant_name",
            "hqr_profile_begin", "hqr_profile_end", "hqr_profile_class",
            "hqr_status_string", "hqr_version")
 
@@ -77,8 +81,52 @@ def load(path: str = LIB_PATH):
     lib.hqr_profile_class.restype = ctypes.c_char_p
     lib.hqr_version.argtypes = []
     lib.hqr_version.restype = ctypes.c_char_p
+    lib.hqr_tune_set.argtypes = [ctypes.c_int, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int]
+    lib.hqr_tune_set.restype = ctypes.c_int
+    lib.hqr_tune_clear.argtypes = []
+    lib.hqr_tune_clear.restype = ctypes.c_int
+    lib.hqr_tune_variants.argtypes = []
+    lib.hqr_tune_variants.restype = ctypes.c_int
+    lib.hqr_tune_variant_name.argtypes = [ctypes.c_int]
+    lib.hqr_tune_variant_name.restype = ctypes.c_char_p
     _lib = lib
+    if os.path.exists(TUNE_DB_PATH):
+        load_tune_db(TUNE_DB_PATH)
     return lib
+
+
+# ------------------------------------------------------------------- tuning
+def tune_variants():
+    """Names of the one-workgroup kernel variants, by index."""
+    lib = load()
+    return [lib.hqr_tune_variant_name(i).decode() for i in range(lib.hqr_tune_variants())]
+
+
+def tune_clear():
+    _check("hqr_tune_clear", load().hqr_tune_clear())
+
+
+def tune_set(op, m_lo, m_hi, n_lo, n_hi, choice, precision=HQR_PREC_FP64):
+    """Add one rule (see hqr.h); `choice` is a variant index, or -1 for the
+    blocked path of single problems."""
+    _check("hqr_tune_set", load().hqr_tune_set(int(op), int(m_lo), int(m_hi), int(n_lo), int(n_hi),
+                                               int(precision), int(choice)))
+
+
+def load_tune_db(path=TUNE_DB_PATH):
+    """Replace the rules with those of an autotuner database (JSON written by
+    paper_2506_09463_amd.autotune).  Variants are stored by name."""
+    import json
+    with open(path) as f:
+        db = json.load(f)
+    names = tune_variants()
+    tune_clear()
+    for r in db.get("rules", []):
+        choice = r["choice"]
+        idx = -1 if choice == "blocked" else names.index(choice)
+        op = HQR_TUNE_SINGLE if r["op"] == "single" else HQR_TUNE_BATCHED
+        tune_set(op, r["m"][0], r["m"][1], r["n"][0], r["n"][1], idx,
+                 HQR_PREC_MIXED if r.get("precision") == "mixed" else HQR_PREC_FP64)
 
 
 def status_string(status: int) -> str:

@@ -56,3 +56,36 @@ def test_argument_validation_without_gpu(lib):
     assert lib.qr_backsolve(3, 1, None, 2, None, 3, ctypes.byref(info), None) == -4
     assert lib.hqr_status_string(-1002).decode().startswith("a HIP call")
     assert "gfx950" in lib.hqr_version().decode()
+
+
+def test_tuning_rules_without_gpu(lib):
+    """Tuning rules are host state: variant names, argument checks, clearing."""
+    from paper_2506_09463_amd import hqr
+    names = hqr.tune_variants()
+    assert len(names) >= 2 and all(n.startswith("wg") for n in names)
+    for nm in names:
+        nt, qm = (int(x) for x in nm[2:].split("x"))
+        assert nt % 64 == 0 and (nt * qm) % 16 == 0
+    assert lib.hqr_tune_variant_name(len(names)) is None
+    assert lib.hqr_tune_set(7, 0, 1, 0, 1, 0, 0) == -1          # op
+    assert lib.hqr_tune_set(0, 5, 4, 0, 1, 0, 0) == -3          # m range
+    assert lib.hqr_tune_set(0, 0, 1, 0, 1, 9, 0) == -6          # precision
+    assert lib.hqr_tune_set(0, 0, 1, 0, 1, 0, len(names)) == -7  # choice
+    assert lib.hqr_tune_set(1, 0, 1, 0, 1, 0, -1) == -7          # batched has no blocked choice
+    for i, nm in enumerate(names):                              # batched: 256-thread variants only
+        assert (lib.hqr_tune_set(1, 0, 1, 0, 1, 0, i) == 0) == nm.startswith("wg256x")
+    assert lib.hqr_tune_set(0, 0, 1, 0, 1, 0, -1) == 0
+    assert lib.hqr_tune_clear() == 0
+
+
+def test_tune_db_roundtrip(lib, tmp_path):
+    import json
+    from paper_2506_09463_amd import hqr
+    names = hqr.tune_variants()
+    db = {"rules": [{"op": "single", "m": [0, 100], "n": [0, 50], "choice": names[0]},
+                    {"op": "single", "m": [0, 100], "n": [51, 100], "choice": "blocked"},
+                    {"op": "batched", "m": [0, 1024], "n": [0, 1024], "choice": names[-1]}]}
+    p = tmp_path / "db.json"
+    p.write_text(json.dumps(db))
+    hqr.load_tune_db(str(p))
+    hqr.tune_clear()
