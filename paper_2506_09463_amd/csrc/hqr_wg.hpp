@@ -30,6 +30,7 @@ namespace hqr {
 
 constexpr int WG_P = 16;    // panel width
 constexpr int WG_LD = 17;   // LDS row stride (doubles) of V and T
+constexpr int WG_PIPE = 4;  // 16-row blocks whose loads the trailing update issues together
 
 enum : int64_t { WG_FACTOR = 1, WG_SOLVE = 2 };
 
@@ -115,58 +116,56 @@ HQR_DEV double wg_block_reduce(double x, int op, WgShared<NT, QM> &sh)
 }
 
 // ---------------------------------------------------------------- panel
-// One column step of the panel (k fixed at compile time so the register
-// arrays stay in registers).
+// One column step of the panel: k is a compile-time constant so every
+// register index is static (a runtime k would turn the register arrays into
+// selects or scratch memory).
 template <int NT, int QM, int k>
-HQR_DEV void wg_panel_step(const WgDesc &d, int64_t c0, int pw, double (&a)[QM][WG_P], double &myup,
+HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[QM][WG_P], double &myup,
                            WgShared<NT, QM> &sh)
 {
     constexpr int NWV = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t m = d.m;
     if (k >= pw) return;
-
-    const int64_t pr = c0 + k;
+    const int pr = c0 + k;
     const int buf = k & 1;
-    double s[WG_P];
-#pragma unroll
-    for (int j = 0; j < WG_P; ++j) s[j] = 0.0;
+    // partial dots of the column below the pivot with every panel column
+    double xk[QM];
     bool nz = false;
+    {
+        double s[WG_P];
 #pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        const int64_t r = c0 + tid + (int64_t)NT * q;
-        if (r > pr && r < m) {
-            const double x = a[q][k];
-            nz = nz || (x != 0.0);
+        for (int j = 0; j < WG_P; ++j) s[j] = 0.0;
 #pragma unroll
-            for (int j = 0; j < WG_P; ++j) s[j] = fma(a[q][j], x, s[j]);
+        for (int q = 0; q < QM; ++q) {
+            const int r = c0 + tid + NT * q;
+            xk[q] = a[q][k];
+            if (r > pr && r < m) {
+                nz = nz || (xk[q] != 0.0);
+#pragma unroll
+                for (int j = 0; j < WG_P; ++j) s[j] = fma(a[q][j], xk[q], s[j]);
+            }
         }
-    }
-    if (tid == k) {
+        if (tid == k) {
 #pragma unroll
-        for (int j = 0; j < WG_P; ++j) sh.prow[buf][j] = a[0][j];
+            for (int j = 0; j < WG_P; ++j) sh.prow[buf][j] = a[0][j];
+        }
+        const double part = wave_sum16(s, lane);
+        if ((lane & 3) == 0) sh.red[buf][w][wave_sum16_index(lane)] = part;
     }
-    const double part = wave_sum16(s, lane);
     const bool wnz = __ballot(nz) != 0ull;
-    if ((lane & 3) == 0) sh.red[buf][w][wave_sum16_index(lane)] = part;
     if (lane == 0) sh.red[buf][w][WG_P] = wnz ? 1.0 : 0.0;
     __syncthreads();
-    double S[WG_P], P[WG_P];
+    // every thread forms the same scalars from the reduction
     bool anynz = false;
+    double sxx = sh.red[buf][0][k];
 #pragma unroll
-    for (int j = 0; j < WG_P; ++j) {
-        double t = sh.red[buf][0][j];
-#pragma unroll
-        for (int i = 1; i < NWV; ++i) t += sh.red[buf][i][j];
-        S[j] = t;
-        P[j] = sh.prow[buf][j];
-    }
+    for (int i = 1; i < NWV; ++i) sxx += sh.red[buf][i][k];
 #pragma unroll
     for (int i = 0; i < NWV; ++i) anynz = anynz || (sh.red[buf][i][WG_P] != 0.0);
-    const double x0 = P[k];
+    const double x0 = sh.prow[buf][k];
     double upk = 0.0, sk = x0;
     if (anynz) {
-        const double tot = x0 * x0 + S[k];
+        const double tot = x0 * x0 + sxx;
         double nu;
         if (tot >= 0x1p-920 && tot <= 0x1p920) {
             nu = sqrt(tot);
@@ -175,16 +174,16 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int64_t c0, int pw, double (&a)[QM][
             double mx = 0.0;
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
-                const int64_t r = c0 + tid + (int64_t)NT * q;
-                if (r > pr && r < m) mx = fmax(mx, fabs(a[q][k]));
+                const int r = c0 + tid + NT * q;
+                if (r > pr && r < m) mx = fmax(mx, fabs(xk[q]));
             }
             const double c = fmax(fabs(x0), wg_block_reduce<NT, QM>(mx, 1, sh));
             double ss = 0.0;
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
-                const int64_t r = c0 + tid + (int64_t)NT * q;
+                const int r = c0 + tid + NT * q;
                 if (r > pr && r < m) {
-                    const double y = a[q][k] / c;
+                    const double y = xk[q] / c;
                     ss = fma(y, y, ss);
                 }
             }
@@ -195,29 +194,35 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int64_t c0, int pw, double (&a)[QM][
         sk = (x0 >= 0.0) ? -nu : nu;
         upk = x0 - sk;
     }
-    const double bk = upk * sk;
-    const double inv_b = anynz ? 1.0 / bk : 0.0;
+    const double inv_b = anynz ? 1.0 / (upk * sk) : 0.0;
     if (tid == k) myup = upk;
-    // T column k: T[k][k] = tau_k = -1/b_k, T[i][k] = -tau_k sum_{l<k} T[i][l] (v_l^T v_k)
+    // w_j = (up A[pr][j] + sum_{r>pr} A[r][j] A[r][k]) / b for every panel
+    // column; for l < k, w_l = (v_l^T v_k) / b_k, which T's column needs
+    double wv[WG_P];
+#pragma unroll
+    for (int j = 0; j < WG_P; ++j) {
+        double t = sh.red[buf][0][j];
+#pragma unroll
+        for (int i = 1; i < NWV; ++i) t += sh.red[buf][i][j];
+        wv[j] = fma(upk, sh.prow[buf][j], t) * inv_b;
+    }
+    // T column k: T[k][k] = tau_k = -1/b_k, T[i][k] = -tau_k sum_{l<k} T[i][l] v_l^T v_k
     if (tid < k) {
         double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < k; ++l) acc = fma(sh.t[tid * WG_LD + l], fma(P[l], upk, S[l]), acc);
-        sh.t[tid * WG_LD + k] = inv_b * acc;
+        for (int l = 0; l < WG_P; ++l)
+            if (l < k) acc = fma(sh.t[tid * WG_LD + l], wv[l], acc);
+        sh.t[tid * WG_LD + k] = acc;
     } else if (tid == k) {
         sh.t[tid * WG_LD + k] = -inv_b;
     }
     // apply H_k to the panel's columns k+1 .. pw-1 (own rows)
-    double wv[WG_P];
-#pragma unroll
-    for (int j = 0; j < WG_P; ++j) wv[j] = (j > k) ? fma(upk, P[j], S[j]) * inv_b : 0.0;
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
-        const int64_t r = c0 + tid + (int64_t)NT * q;
+        const int r = c0 + tid + NT * q;
         if (r > pr && r < m) {
-            const double x = a[q][k];
 #pragma unroll
-            for (int j = k + 1; j < WG_P; ++j) a[q][j] = fma(wv[j], x, a[q][j]);
+            for (int j = k + 1; j < WG_P; ++j) a[q][j] = fma(wv[j], xk[q], a[q][j]);
         } else if (r == pr) {
 #pragma unroll
             for (int j = k + 1; j < WG_P; ++j) a[q][j] = fma(wv[j], upk, a[q][j]);
@@ -228,55 +233,82 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int64_t c0, int pw, double (&a)[QM][
 }
 
 template <int NT, int QM, int... Ks>
-HQR_DEV void wg_panel_steps(const WgDesc &d, int64_t c0, int pw, double (&a)[QM][WG_P], double &myup,
+HQR_DEV void wg_panel_steps(const WgDesc &d, int c0, int pw, int m, double (&a)[QM][WG_P], double &myup,
                             WgShared<NT, QM> &sh, std::integer_sequence<int, Ks...>)
 {
-    (wg_panel_step<NT, QM, Ks>(d, c0, pw, a, myup, sh), ...);
+    (wg_panel_step<NT, QM, Ks>(d, c0, pw, m, a, myup, sh), ...);
 }
-
 
 // Factor columns c0 .. c0+pw-1 (rows c0 .. m-1) in registers; write them
 // back, leave V (rows relative to c0, up on the diagonal, zeros above) and T
 // in LDS.  Ends with a barrier.
 template <int NT, int QM>
-HQR_DEV void wg_panel_factor(const WgDesc &d, int64_t c0, int pw, WgShared<NT, QM> &sh)
+HQR_DEV void wg_panel_factor(const WgDesc &d, int c0, int pw, WgShared<NT, QM> &sh)
 {
-    constexpr int NWV = NT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t m = d.m;
-    double a[QM][WG_P];
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        const int64_t r = c0 + tid + (int64_t)NT * q;
-#pragma unroll
-        for (int j = 0; j < WG_P; ++j) a[q][j] = (r < m && j < pw) ? d.A[(size_t)(c0 + j) * d.lda + r] : 0.0;
+    const int tid = threadIdx.x;
+    const int m = (int)d.m, nrows = m - c0;
+    const size_t lda = (size_t)d.lda;
+    double *const Ap = d.A + (size_t)c0 * lda + c0;   // A[c0][c0]
+    // stage the panel in LDS (columns beyond pw as zeros), then each thread
+    // takes its rows into registers
+#pragma unroll 1
+    for (int j = 0; j < WG_P; ++j) {
+        if (j < pw) {
+            const double *col = Ap + (size_t)j * lda;
+            for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = col[rr];
+        } else {
+            for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = 0.0;
+        }
     }
-    // up of the reflector whose pivot row this thread owns (V's diagonal);
-    // T row `tid` (tid < 16) lives in LDS, written and read by its thread only
-    double myup = 0.0;
     if (tid < WG_P) {
 #pragma unroll
         for (int j = 0; j < WG_P; ++j) sh.t[tid * WG_LD + j] = 0.0;
     }
-    wg_panel_steps<NT, QM>(d, c0, pw, a, myup, sh, std::make_integer_sequence<int, WG_P>{});
-    // write back; V and T to LDS
+    __syncthreads();
+    double a[QM][WG_P];
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
-        const int64_t rr = tid + (int64_t)NT * q;
-        const int64_t r = c0 + rr;
+        const int rr = tid + NT * q;
 #pragma unroll
-        for (int j = 0; j < WG_P; ++j) {
-            if (r < m && j < pw) d.A[(size_t)(c0 + j) * d.lda + r] = a[q][j];
-            sh.v[rr * WG_LD + j] = (r >= m) ? 0.0 : (rr > j ? a[q][j] : (rr == j ? myup : 0.0));
+        for (int j = 0; j < WG_P; ++j) a[q][j] = (rr < nrows) ? sh.v[rr * WG_LD + j] : 0.0;
+    }
+    // up of the reflector whose pivot row this thread owns (V's diagonal);
+    // T row `tid` (tid < 16) lives in LDS, written and read by its thread only
+    double myup = 0.0;
+    wg_panel_steps<NT, QM>(d, c0, pw, m, a, myup, sh, std::make_integer_sequence<int, WG_P>{});
+    // back through LDS: the factored panel to A, then V (up on the diagonal,
+    // zeros above it and beyond pw) stays in LDS for the trailing update
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int rr = tid + NT * q;
+        if (rr < nrows) {
+#pragma unroll
+            for (int j = 0; j < WG_P; ++j) sh.v[rr * WG_LD + j] = a[q][j];
         }
     }
+    __syncthreads();
+#pragma unroll 1
+    for (int j = 0; j < pw; ++j) {
+        double *col = Ap + (size_t)j * lda;
+        for (int rr = tid; rr < nrows; rr += NT) col[rr] = sh.v[rr * WG_LD + j];
+    }
+    __syncthreads();
+    if (tid < WG_P && tid < nrows) {
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) {
+            if (j >= tid) sh.v[tid * WG_LD + j] = (j == tid) ? myup : 0.0;
+        }
+    }
+#pragma unroll 1
+    for (int j = pw; j < WG_P; ++j)
+        for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = 0.0;
     __syncthreads();
 }
 
 // Stored factorization: V from A's tails and up, T from V^T V.  Ends with a
 // barrier.
 template <int NT, int QM>
-HQR_DEV void wg_panel_load(const WgDesc &d, int64_t c0, int pw, WgShared<NT, QM> &sh)
+__device__ __noinline__ void wg_panel_load(const WgDesc &d, int64_t c0, int pw, WgShared<NT, QM> &sh)
 {
     constexpr int NWV = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -373,15 +405,23 @@ HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA,
         f64x4 acc[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-        for (int64_t rb = 0; rb < nb16; ++rb) {
-            const int64_t rr0 = rb * 16 + 4 * kq;
-            double cv[4];
+        // WG_PIPE 16-row blocks per round: all their loads are issued first
+        for (int64_t rb0 = 0; rb0 < nb16; rb0 += WG_PIPE) {
+            double cv[WG_PIPE][4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) cv[s] = (cp && rr0 + s < nrows) ? cp[c0 + rr0 + s] : 0.0;
+            for (int u = 0; u < WG_PIPE; ++u) {
+                const int64_t rr0 = (rb0 + u) * 16 + 4 * kq;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const double av = sh.v[(rr0 + s) * WG_LD + i16];
-                acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cv[s], acc[s], 0, 0, 0);
+                for (int s = 0; s < 4; ++s) cv[u][s] = (cp && rr0 + s < nrows) ? cp[c0 + rr0 + s] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < WG_PIPE; ++u) {
+                const int64_t rr0 = (rb0 + u) * 16 + 4 * kq;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const double av = (rr0 + s < nrows) ? sh.v[(rr0 + s) * WG_LD + i16] : 0.0;
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cv[u][s], acc[s], 0, 0, 0);
+                }
             }
         }
         f64x4 wm;
@@ -398,27 +438,33 @@ HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA,
         double *cq[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) cq[g] = wg_colptr(d, tile * 16 + 4 * g + kq, colA, ncA, ntot);
-        for (int64_t rb = 0; rb < nb16; ++rb) {
-            const int64_t rr = rb * 16 + i16;
-            const bool ok = rr < nrows;
-            f64x4 cacc;
+        for (int64_t rb0 = 0; rb0 < nb16; rb0 += WG_PIPE) {
+            f64x4 cacc[WG_PIPE];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) cacc[g] = (cq[g] && ok) ? cq[g][c0 + rr] : 0.0;
+            for (int u = 0; u < WG_PIPE; ++u) {
+                const int64_t rr = (rb0 + u) * 16 + i16;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double bv = sh.v[rr * WG_LD + 4 * q + kq];
-                cacc = __builtin_amdgcn_mfma_f64_16x16x4f64(-wp[q], bv, cacc, 0, 0, 0);
+                for (int g = 0; g < 4; ++g) cacc[u][g] = (cq[g] && rr < nrows) ? cq[g][c0 + rr] : 0.0;
             }
 #pragma unroll
-            for (int g = 0; g < 4; ++g)
-                if (cq[g] && ok) cq[g][c0 + rr] = cacc[g];
+            for (int u = 0; u < WG_PIPE; ++u) {
+                const int64_t rr = (rb0 + u) * 16 + i16;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double bv = (rr < nrows) ? sh.v[rr * WG_LD + 4 * q + kq] : 0.0;
+                    cacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-wp[q], bv, cacc[u], 0, 0, 0);
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    if (cq[g] && rr < nrows) cq[g][c0 + rr] = cacc[u][g];
+            }
         }
     }
 }
 
 // ------------------------------------------------ residual norms, solve
 template <int NT, int QM>
-HQR_DEV void wg_resnorm(const WgDesc &d)
+__device__ __noinline__ void wg_resnorm(const WgDesc &d)
 {
     constexpr int NWV = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -452,7 +498,7 @@ HQR_DEV void wg_resnorm(const WgDesc &d)
 // R X = B[0:n]: info = smallest k+1 with R[k][k] == 0 (B untouched), else X
 // in B[0:n].  X staged column-major in the V area.
 template <int NT, int QM>
-HQR_DEV void wg_backsolve(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
+__device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t n = d.n, nrhs = d.nrhs;
@@ -525,7 +571,7 @@ HQR_DEV void wg_instance(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
     const bool factor = (d.flags & WG_FACTOR) != 0;
     for (int64_t c0 = 0; c0 < d.n; c0 += WG_P) {
         const int pw = (int)((d.n - c0 < WG_P) ? d.n - c0 : WG_P);
-        if (factor) wg_panel_factor<NT, QM>(d, c0, pw, sh);
+        if (factor) wg_panel_factor<NT, QM>(d, (int)c0, pw, sh);
         else wg_panel_load<NT, QM>(d, c0, pw, sh);
         const int64_t ncA = factor ? d.n - c0 - pw : 0;
         wg_trailing<NT, QM>(d, c0, c0 + pw, ncA, sh);
