@@ -63,185 +63,313 @@ HQR_DEV void mm64(double (*out)[LD65], const double (*A)[LD65], const double (*B
         for (int r = 0; r < 4; ++r) out[16 * w + 4 * r + (lane >> 4)][16 * t + (lane & 15)] = acc[t][r];
 }
 
-// Sum over the four lanes 4c..4c+3 of a column group (same wave).
-HQR_DEV double quad_sum(double v)
-{
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    return v;
-}
 
-// Inverse of the upper-triangular n x n block of U into X (upper, zeros
-// below, identity beyond n).  Column j belongs to lanes 4j..4j+3 of one wave
-// (256 threads); lane q keeps X[q + 4t][j], t < 16, in registers.  Rows are
-// produced bottom-up; the 16 entries of U's row each lane needs are loaded
-// unconditionally (so the loads pipeline), products are selected, not
-// branched, and the four partial sums are added across the lanes.
-HQR_DEV void inv_upper64(double (*X)[LD65], const double (*U)[LD65], int n, int tid, double *dinv)
+
+
+
+
+// ------------------------------------------- 16 x 16 blocks on MFMA
+// FP64 MFMA 16x16x4 layouts: A[i][k] at lane i + 16k, B[k][j] at lane
+// j + 16k, D[i][j] at lane j + 16 (i % 4), register i / 4.  A product D
+// feeds the next MFMA as its B operand directly: register q is the B operand
+// of the k-chunk 4q..4q+3.
+
+// acc += MA[ar:ar+16][ac:ac+16] * MB[br:br+16][bc:bc+16]
+HQR_DEV f64x4 mma_blk(f64x4 acc, const double (*MA)[LD65], int ar, int ac, const double (*MB)[LD65], int br, int bc,
+                      int lane)
 {
-    const int j = tid >> 2, q = tid & 3;
-    if (tid < NB) dinv[tid] = (tid < n) ? 1.0 / U[tid][tid] : 1.0;
-    __syncthreads();
-    double x[16];
+    const int i = lane & 15, kk = lane >> 4;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == j) ? dinv[j] : 0.0;
-    if (j < n) {
-        for (int i = j - 1; i >= 0; --i) {
-            double u[16];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) u[t] = U[i][q + 4 * t];
-            double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-            for (int t = 0; t < 16; t += 2) {
-                const int l0 = q + 4 * t, l1 = l0 + 4;
-                s0 += (l0 > i && l0 <= j) ? u[t] * x[t] : 0.0;
-                s1 += (l1 > i && l1 <= j) ? u[t + 1] * x[t + 1] : 0.0;
-            }
-            const double xi = -quad_sum(s0 + s1) * dinv[i];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == i) ? xi : x[t];
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int k = 4 * q + kk;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(MA[ar + i][ac + k], MB[br + k][bc + i], acc, 0, 0, 0);
     }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) X[q + 4 * t][j] = x[t];
-    __syncthreads();
+    return acc;
 }
 
-// Inverse of the unit lower triangle (strict lower entries of L, unit
-// diagonal implied) into X (lower, unit diagonal, zeros above); same layout,
-// rows produced top-down.
-HQR_DEV void inv_unit_lower64(double (*X)[LD65], const double (*L)[LD65], int n, int tid)
+// acc += MA[ar:ar+16][ac:ac+16] * D  (D a 16 x 16 block in D layout)
+HQR_DEV f64x4 mma_blk_reg(f64x4 acc, const double (*MA)[LD65], int ar, int ac, f64x4 d, int lane)
 {
-    const int j = tid >> 2, q = tid & 3;
-    double x[16];
+    const int i = lane & 15, kk = lane >> 4;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == j) ? 1.0 : 0.0;
-    if (j < n) {
-        for (int i = j + 1; i < n; ++i) {
-            double u[16];
+    for (int q = 0; q < 4; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(MA[ar + i][ac + 4 * q + kk], d[q], acc, 0, 0, 0);
+    return acc;
+}
+
+HQR_DEV void st_blk(double (*M)[LD65], int r0, int c0, f64x4 d, double scale, int lane)
+{
 #pragma unroll
-            for (int t = 0; t < 16; ++t) u[t] = L[i][q + 4 * t];
-            double s0 = 0.0, s1 = 0.0;
+    for (int r = 0; r < 4; ++r) M[r0 + 4 * r + (lane >> 4)][c0 + (lane & 15)] = scale * d[r];
+}
+
+// X = U^{-1} for the upper-triangular n x n block of U (identity beyond n;
+// U's entries outside that block must be zero off the diagonal), by the 4
+// waves of the workgroup: wave w inverts diagonal block w (lane j < 16
+// solves for its column), then the blocks above the diagonal follow by their
+// distance from it, X_ij = -X_ii sum_{k=i+1..j} U_ik X_kj, as MFMA products.
+// Starts and ends with a barrier.
+HQR_DEV void inv_upper64_blk(double (*X)[LD65], const double (*U)[LD65], int n, int lane, int w)
+{
+    __syncthreads();
+    {
+        const int b0 = 16 * w, j = lane & 15;
+        double x[16];
 #pragma unroll
-            for (int t = 0; t < 16; t += 2) {
-                const int l0 = q + 4 * t, l1 = l0 + 4;
-                s0 += (l0 >= j && l0 < i) ? u[t] * x[t] : 0.0;
-                s1 += (l1 >= j && l1 < i) ? u[t + 1] * x[t + 1] : 0.0;
-            }
-            const double xi = -quad_sum(s0 + s1);
+        for (int i = 15; i >= 0; --i) {
+            const int gi = b0 + i;
+            double s = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) x[t] = (q + 4 * t == i) ? xi : x[t];
+            for (int l = i + 1; l < 16; ++l) s = fma(-U[gi][b0 + l], x[l], s);
+            x[i] = (i > j) ? 0.0 : ((gi < n) ? s / U[gi][gi] : ((i == j) ? 1.0 : 0.0));
         }
+        if (lane < 16) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) X[b0 + i][b0 + j] = x[i];
+        }
+        for (int idx = lane; idx < 16 * b0; idx += 64) X[b0 + idx / b0][idx % b0] = 0.0;
     }
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 16; ++t) X[q + 4 * t][j] = x[t];
+    if (w < 3) { // distance 1
+        const int i = w, j = w + 1;
+        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, U, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
+        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
+    }
+    __syncthreads();
+    if (w < 2) { // distance 2
+        const int i = w, j = w + 2;
+        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, U, 16 * i, 16 * (i + 1), X, 16 * (i + 1), 16 * j, lane);
+        t = mma_blk(t, U, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
+        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
+    }
+    __syncthreads();
+    if (w == 0) { // distance 3
+        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, U, 0, 16, X, 16, 48, lane);
+        t = mma_blk(t, U, 0, 32, X, 32, 48, lane);
+        t = mma_blk(t, U, 0, 48, X, 48, 48, lane);
+        st_blk(X, 0, 48, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 0, 0, t, lane), -1.0, lane);
+    }
     __syncthreads();
 }
 
-// Register of a 16-entry array picked by a runtime index (select chain, so
-// the array stays in registers).
-HQR_DEV double pick16(const double (&v)[16], int t)
+// X = L^{-1} for the unit lower triangle whose strict lower entries are L's
+// (n x n block; L's entries outside it must be zero), same scheme: diagonal
+// blocks by forward substitution, then X_ij = -X_ii sum_{k=j..i-1} L_ik X_kj.
+// Starts and ends with a barrier.
+HQR_DEV void inv_unit_lower64_blk(double (*X)[LD65], const double (*L)[LD65], int n, int lane, int w)
 {
-    double r = 0.0;
+    __syncthreads();
+    {
+        const int b0 = 16 * w, j = lane & 15;
+        double x[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) r = (q == t) ? v[q] : r;
-    return r;
+        for (int i = 0; i < 16; ++i) {
+            const int gi = b0 + i;
+            double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int l = 0; l < i; ++l) s = fma(-L[gi][b0 + l], x[l], s);
+            x[i] = (i < j) ? 0.0 : ((i == j) ? 1.0 : ((gi < n && b0 + j < n) ? s : 0.0));
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) X[b0 + i][b0 + j] = x[i];
+        }
+        const int c1 = b0 + 16, wid = NB - c1;
+        for (int idx = lane; idx < 16 * wid; idx += 64) X[b0 + idx / wid][c1 + idx % wid] = 0.0;
+    }
+    __syncthreads();
+    if (w < 3) { // distance 1: X_{j+1, j}
+        const int j = w, i = w + 1;
+        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, L, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
+        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
+    }
+    __syncthreads();
+    if (w < 2) { // distance 2: X_{j+2, j}
+        const int j = w, i = w + 2;
+        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, L, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
+        t = mma_blk(t, L, 16 * i, 16 * (j + 1), X, 16 * (j + 1), 16 * j, lane);
+        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
+    }
+    __syncthreads();
+    if (w == 0) { // distance 3: X_{3, 0}
+        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, L, 48, 0, X, 0, 0, lane);
+        t = mma_blk(t, L, 48, 16, X, 16, 0, lane);
+        t = mma_blk(t, L, 48, 32, X, 32, 0, lane);
+        st_blk(X, 48, 0, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 48, 48, t, lane), -1.0, lane);
+    }
+    __syncthreads();
 }
 
-// In-place upper Cholesky G = R^T R of the n x n block (R in the upper part,
-// zeros below, identity beyond n).  Thread (column j = tid & 63, row group
-// rg = tid >> 6) keeps G[rg + 4t][j], t < 16, in registers.  Row k is
-// broadcast through a double-buffered LDS row written by its owners after
-// their step-(k-1) update, so each step needs one barrier.  *bad reports a
-// pivot^2 below ratio * G_kk.
-HQR_DEV void chol64(double (*G)[LD65], int n, int tid, double ratio, double *gdiag, double *rdiag, int *bad,
-                    double (*rowbuf)[NB])
+// 16 x 16 LDS block in D layout (to accumulate an MFMA update onto it)
+HQR_DEV f64x4 ld_blk(const double (*M)[LD65], int r0, int c0, int lane)
 {
-    const int j = tid & 63, rg = tid >> 6;
-    double g[16];
+    f64x4 d;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) g[t] = G[rg + 4 * t][j];
+    for (int r = 0; r < 4; ++r) d[r] = M[r0 + 4 * r + (lane >> 4)][c0 + (lane & 15)];
+    return d;
+}
+
+// In-place upper Cholesky G = R^T R of the n x n block of G (R in the upper
+// part, zeros below, identity beyond n; G's entries outside the block must
+// be zero), by 16-column block steps.  In block step kb ONE wave computes
+// rows 16kb .. 16kb+15 of R (Crout order, lane t owning column 16kb + t:
+// R[i][c] = (G'[i][c] - sum_{l} R[l][i] R[l][c]) / R[i][i] over the block's
+// earlier rows l, the pivot R[i][i] taken from lane i by readlane, column i
+// of R read back from LDS as a broadcast); then all waves subtract
+// R_p^T R_p from the trailing upper blocks on MFMA.  gdiag gets G's original
+// diagonal, rdiag R's; *bad is set when a pivot^2 falls below ratio * G_kk.
+// Starts and ends with a barrier.
+HQR_DEV void chol64_blk(double (*G)[LD65], int n, int lane, int w, double ratio, double *gdiag, double *rdiag,
+                        int *bad)
+{
+    const int tid = 64 * w + lane;
+    __syncthreads();
     if (tid < NB) gdiag[tid] = (tid < n) ? G[tid][tid] : 1.0;
     if (tid == 0) *bad = 0;
-    if (rg == 0) rowbuf[0][j] = g[0];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double *rk = rowbuf[k & 1];
-        const double piv = rk[k];
-        const double inv = 1.0 / piv;
-        const double rkj = rk[j];
-        const double rkk = sqrt(fmax(piv, 0.0));
-        double rkv[16];
+#pragma unroll 1
+    for (int kb = 0; kb < 4; ++kb) {
+        const int b0 = 16 * kb;
+        if (w == 0) {
+            const int c = b0 + lane;
+            const bool act = c < NB;
+            double r[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) rkv[t] = rk[rg + 4 * t];
-        const double coef = rkj * inv;
+            for (int i = 0; i < 16; ++i) {
+                const int gi = b0 + i;
+                double s = act ? G[gi][c] : 0.0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int i = rg + 4 * t;
-            g[t] = (i > k && i <= j && j < n) ? g[t] - rkv[t] * coef : g[t];
+                for (int l = 0; l < i; ++l) s = fma(-G[b0 + l][gi], r[l], s);
+                const double piv = readlane_f64(s, i);
+                const double rii = (gi < n) ? sqrt(fmax(piv, 0.0)) : 1.0;
+                if (lane == 0 && gi < n && !(piv > ratio * gdiag[gi])) *bad = 1;
+                double v;
+                if (gi >= n) v = (c == gi) ? 1.0 : 0.0;
+                else if (lane < i) v = 0.0;
+                else if (lane == i) v = rii;
+                else v = (c < n) ? s / rii : 0.0;
+                r[i] = v;
+                if (act && lane >= i) G[gi][c] = v;
+            }
         }
-        // row k of R
-        if (rg == (k & 3)) G[k][j] = (j > k && j < n) ? rkj / rkk : ((j == k) ? rkk : 0.0);
-        if (tid == 0) {
-            rdiag[k] = rkk;
-            if (!(piv > ratio * gdiag[k])) *bad = 1;
+        __syncthreads();
+        // trailing upper blocks (ib <= jb): G_ij -= R_p,i^T R_p,j, R_p = rows b0..b0+15
+        const int rem = 3 - kb;
+        const int nblk = rem * (rem + 1) / 2;
+        for (int bidx = w; bidx < nblk; bidx += 4) {
+            int ib = 0, jb = 0, cnt = 0;
+            for (int a = kb + 1; a <= 3; ++a)
+                for (int b = a; b <= 3; ++b) {
+                    if (cnt == bidx) { ib = a; jb = b; }
+                    ++cnt;
+                }
+            f64x4 acc = ld_blk(G, 16 * ib, 16 * jb, lane);
+            const int i16 = lane & 15, kk = lane >> 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = b0 + 4 * q + kk;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-G[k][16 * ib + i16], G[k][16 * jb + i16], acc, 0, 0, 0);
+            }
+            st_blk(G, 16 * ib, 16 * jb, acc, 1.0, lane);
         }
-        const int kn = k + 1;
-        if (kn < n && rg == (kn & 3)) rowbuf[kn & 1][j] = pick16(g, kn >> 2);
         __syncthreads();
     }
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, c = idx % NB;
-        if (i > c || i >= n || c >= n) G[i][c] = (i == c && i >= n) ? 1.0 : 0.0;
+        if (i > c) G[i][c] = 0.0;
     }
+    if (tid < NB) rdiag[tid] = G[tid][tid];
     __syncthreads();
 }
 
-// In place: M (n x n, top block of Q) becomes L (strict lower, unit diagonal
-// implied) and U (upper) of the LU factorization without pivoting of
-// M - S, with s_k = -sgn(pivot k) (sgn(0) = +1) chosen at step k.  Same
-// register layout as chol64; column k reaches the wave's lanes by readlane.
-HQR_DEV void lu_sign64(double (*M)[LD65], int n, int tid, double *sgn, double *udiag, double (*rowbuf)[NB])
+// In place: M (n x n block; entries outside it zero) becomes L (strict
+// lower, unit diagonal implied) and U (upper, diagonal U_kk) of the LU
+// factorization without pivoting of M - S, s_k = -sgn(pivot k) (sgn(0) = +1)
+// chosen at step k; entries outside the block stay zero.  Block steps of 16:
+// ONE wave computes U's block row and L's block column (lane t owning column
+// 16kb + t of U and row 16kb + t of L, Doolittle order within the block, the
+// pivot by readlane, finished entries read back from LDS as broadcasts), then
+// all waves subtract L_p U_p from the trailing blocks on MFMA.  Starts and
+// ends with a barrier.
+HQR_DEV void lu_sign64_blk(double (*M)[LD65], int n, int lane, int w, double *sgn, double *udiag)
 {
-    const int j = tid & 63, rg = tid >> 6;
-    double mv[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) mv[t] = M[rg + 4 * t][j];
-    if (rg == 0) rowbuf[0][j] = mv[0];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double *rk = rowbuf[k & 1];
-        const double q = rk[k];
-        const double s = (q >= 0.0) ? -1.0 : 1.0;
-        const double ukk = q - s;
-        const double ukj = rk[j] / ukk;
+#pragma unroll 1
+    for (int kb = 0; kb < 4; ++kb) {
+        const int b0 = 16 * kb;
+        if (w == 0) {
+            const int t = b0 + lane;
+            const bool act = t < NB;
+            double u[16], lr[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int i = rg + 4 * t;
-            const double lik = readlane_f64(mv[t], k); // column k, row i
-            mv[t] = (i > k && i < n && j > k && j < n) ? mv[t] - lik * ukj : mv[t];
+            for (int i = 0; i < 16; ++i) {
+                const int gi = b0 + i;
+                // column role: U[gi][t] = M'[gi][t] - sum_l L[gi][b0+l] U[b0+l][t]
+                double su = act ? M[gi][t] : 0.0;
+#pragma unroll
+                for (int l = 0; l < i; ++l) su = fma(-M[gi][b0 + l], u[l], su);
+                const double q = readlane_f64(su, i);
+                const double sg = (q >= 0.0) ? -1.0 : 1.0;
+                const double ukk = q - sg;
+                const double uv = (lane > i) ? su : ((lane == i) ? ukk : 0.0);
+                u[i] = uv;
+                if (gi < n && act && lane >= i && t < n) M[gi][t] = uv;
+                // row role: L[t][gi] = (M'[t][gi] - sum_l L[t][b0+l] U[b0+l][gi]) / U_kk
+                double sl = act ? M[t][gi] : 0.0;
+#pragma unroll
+                for (int l = 0; l < i; ++l) sl = fma(-lr[l], M[b0 + l][gi], sl);
+                const double lv = (lane > i) ? sl / ukk : 0.0;
+                lr[i] = lv;
+                if (gi < n && act && lane > i && t < n) M[t][gi] = lv;
+                if (lane == 0 && gi < n) {
+                    sgn[gi] = sg;
+                    udiag[gi] = ukk;
+                }
+            }
         }
-        if (tid == 0) {
-            sgn[k] = s;
-            udiag[k] = ukk;
+        __syncthreads();
+        // trailing blocks: M_ij -= L_p,i U_p,j over the block's 16 pivots
+        const int rem = 3 - kb;
+        for (int bidx = w; bidx < rem * rem; bidx += 4) {
+            const int ib = kb + 1 + bidx / rem, jb = kb + 1 + bidx % rem;
+            f64x4 acc = ld_blk(M, 16 * ib, 16 * jb, lane);
+            const int i16 = lane & 15, kk = lane >> 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = b0 + 4 * q + kk;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-M[16 * ib + i16][k], M[k][16 * jb + i16], acc, 0, 0, 0);
+            }
+            st_blk(M, 16 * ib, 16 * jb, acc, 1.0, lane);
         }
-        const int kn = k + 1;
-        if (kn < n && rg == (kn & 3)) rowbuf[kn & 1][j] = pick16(mv, kn >> 2);
         __syncthreads();
     }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int i = rg + 4 * t;
-        double v = mv[t];
-        if (i < n && j < n) {
-            if (i > j) v = v / udiag[j];
-            else if (i == j) v = udiag[j];
-        }
-        M[i][j] = v;
-    }
-    __syncthreads();
 }
+
+// out (global, row-major 64 x 64) = (A * B) diag(cs) on columns < bw, zero
+// beyond; A, B in LDS; 256 threads, wave w computes row tile w.
+HQR_DEV void mm64_to_global(double *out, const double (*A)[LD65], const double (*B)[LD65], const double *cs,
+                            int bw, int lane, int w)
+{
+    f64x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+        const int kr = k0 + (lane >> 4);
+        const double a = A[16 * w + (lane & 15)][kr];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[kr][16 * t + (lane & 15)], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = 16 * t + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(16 * w + 4 * r + (lane >> 4)) * NB + c] = (c < bw) ? acc[t][r] * cs[c] : 0.0;
+    }
+}
+
+
+
 
 // ------------------------------------------------------------ Gram kernel
 struct CqrArgs {
@@ -374,7 +502,6 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     __shared__ double M2[NB][LD65];
     __shared__ double M3[NB][LD65];
     __shared__ double gdiag[NB], rdiag[NB], sgn[NB], upv[NB], rh[NB];
-    __shared__ double rowbuf[2][NB];
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int bw = p.bw;
@@ -399,26 +526,23 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     }
     __syncthreads();
     HQR_TS();
-    chol64(M0, bw, tid, CQR_RATIO, gdiag, rdiag, &bad, rowbuf);
+    chol64_blk(M0, bw, lane, w, CQR_RATIO, gdiag, rdiag, &bad);
     HQR_TS();
     if (tid == 0 && (bad || structural)) atomicExch(p.flag, 1);
     __syncthreads();
     if (bad || __hip_atomic_load(p.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
 
     if (p.pass == 1) {
-        inv_upper64(M1, M0, bw, tid, gdiag);
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            p.r1[idx] = M0[idx / NB][idx % NB];
-            p.r1inv[idx] = M1[idx / NB][idx % NB];
-        }
+        for (int idx = tid; idx < NB * NB; idx += 256) p.r1[idx] = M0[idx / NB][idx % NB];
+        inv_upper64_blk(M1, M0, bw, lane, w);
+        for (int idx = tid; idx < NB * NB; idx += 256) p.r1inv[idx] = M1[idx / NB][idx % NB];
         return;
     }
 
     // ---- pass 2: M0 = R2
-    inv_upper64(M1, M0, bw, tid, gdiag);                // M1 = R2^{-1}
-    HQR_TS();
     for (int idx = tid; idx < NB * NB; idx += 256) M2[idx / NB][idx % NB] = p.r1inv[idx];
-    __syncthreads();
+    inv_upper64_blk(M1, M0, bw, lane, w);                // M1 = R2^{-1}
+    HQR_TS();
     mm64(M3, M2, M1, lane, w);                          // M3 = R^{-1} = R1^{-1} R2^{-1}
     __syncthreads();
     for (int idx = tid; idx < NB * NB; idx += 256) M2[idx / NB][idx % NB] = p.r1[idx];
@@ -435,7 +559,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     __syncthreads();
     HQR_TS();
     // modified LU of Q_top - S (in place in M0)
-    lu_sign64(M0, bw, tid, sgn, rdiag, rowbuf);
+    lu_sign64_blk(M0, bw, lane, w, sgn, rdiag);
     HQR_TS();
     // R_house = S R: write the upper triangle of the panel's top block
     for (int idx = tid; idx < bw * bw; idx += 256) {
@@ -449,39 +573,25 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         upv[tid] = -tau * rkk;
     }
     __syncthreads();
-    // W^{-1} = R^{-1} U^{-1}, scaled by up per column
-    {
-        // M2 = U^{-1} from the upper part of M0 (diagonal = U_kk)
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            const int i = idx / NB, j = idx % NB;
-            M1[i][j] = (i <= j && i < bw && j < bw) ? M0[i][j] : ((i == j) ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        inv_upper64(M2, M1, NB, tid, gdiag);
-        HQR_TS();
-        mm64(M1, M3, M2, lane, w);                      // M1 = R^{-1} U^{-1}
-        __syncthreads();
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            const int i = idx / NB, j = idx % NB;
-            p.winv[idx] = (j < bw) ? M1[i][j] * upv[j] : 0.0;
-        }
-    }
-    // T_Y = -(U S) L^{-T};  T_V = T_Y / (up_i up_j)
+    // U^{-1} and L^{-1} from the LU in M0
+    inv_upper64_blk(M2, M0, bw, lane, w);
+    inv_unit_lower64_blk(M1, M0, bw, lane, w);
+    HQR_TS();
+    // W^{-1} = R^{-1} U^{-1} diag(up), straight to global
+    mm64_to_global(p.winv, M3, M2, upv, bw, lane, w);
     __syncthreads();
-    HQR_TS();
-    inv_unit_lower64(M2, M0, bw, tid);                  // M2 = L^{-1}
-    HQR_TS();
+    // T_Y = -(U S) L^{-T};  T_V = T_Y / (up_i up_j)
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, l = idx % NB;
-        M1[i][l] = (i <= l && l < bw) ? M0[i][l] * sgn[l] : 0.0; // U S
-        M3[l][i] = M2[i][l];                                     // L^{-T}
+        M2[i][l] = (i <= l && l < bw) ? M0[i][l] * sgn[l] : 0.0; // U S
+        M3[l][i] = M1[i][l];                                     // L^{-T}
     }
     __syncthreads();
-    mm64(M2, M1, M3, lane, w);
+    mm64(M1, M2, M3, lane, w);
     __syncthreads();
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, j = idx % NB;
-        p.T[idx] = (i <= j && j < bw) ? -M2[i][j] / (upv[i] * upv[j]) : 0.0;
+        p.T[idx] = (i <= j && j < bw) ? -M1[i][j] / (upv[i] * upv[j]) : 0.0;
     }
     // stored tails of the top block: L[i][j] * up_j (strict lower)
     for (int idx = tid; idx < bw * bw; idx += 256) {
