@@ -212,11 +212,11 @@ HQR_DEV f64x4 ld_blk(const double (*M)[LD65], int r0, int c0, int lane)
 // In-place upper Cholesky G = R^T R of the n x n block of G (R in the upper
 // part, zeros below, identity beyond n; G's entries outside the block must
 // be zero), by 16-column block steps.  In block step kb ONE wave computes
-// rows 16kb .. 16kb+15 of R (Crout order, lane t owning column 16kb + t:
-// R[i][c] = (G'[i][c] - sum_{l} R[l][i] R[l][c]) / R[i][i] over the block's
-// earlier rows l, the pivot R[i][i] taken from lane i by readlane, column i
-// of R read back from LDS as a broadcast); then all waves subtract
-// R_p^T R_p from the trailing upper blocks on MFMA.  gdiag gets G's original
+// rows 16kb .. 16kb+15 of R (lane t owning column 16kb + t, right-looking
+// within the block: the pivot from lane i by readlane, then the rank-1
+// update of the block's remaining rows with the other columns' entries by
+// readlane); then all waves subtract R_p^T R_p from the trailing upper
+// blocks on MFMA.  gdiag gets G's original
 // diagonal, rdiag R's; *bad is set when a pivot^2 falls below ratio * G_kk.
 // Starts and ends with a barrier.
 HQR_DEV void chol64_blk(double (*G)[LD65], int n, int lane, int w, double ratio, double *gdiag, double *rdiag,
@@ -231,25 +231,31 @@ HQR_DEV void chol64_blk(double (*G)[LD65], int n, int lane, int w, double ratio,
     for (int kb = 0; kb < 4; ++kb) {
         const int b0 = 16 * kb;
         if (w == 0) {
+            // lane t holds column c = b0 + t of the block row; right-looking
+            // within the block, other columns' entries by readlane
             const int c = b0 + lane;
             const bool act = c < NB;
-            double r[16];
+            double g[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) g[i] = act ? G[b0 + i][c] : 0.0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int gi = b0 + i;
-                double s = act ? G[gi][c] : 0.0;
-#pragma unroll
-                for (int l = 0; l < i; ++l) s = fma(-G[b0 + l][gi], r[l], s);
-                const double piv = readlane_f64(s, i);
+                const double piv = readlane_f64(g[i], i);
                 const double rii = (gi < n) ? sqrt(fmax(piv, 0.0)) : 1.0;
                 if (lane == 0 && gi < n && !(piv > ratio * gdiag[gi])) *bad = 1;
                 double v;
                 if (gi >= n) v = (c == gi) ? 1.0 : 0.0;
                 else if (lane < i) v = 0.0;
                 else if (lane == i) v = rii;
-                else v = (c < n) ? s / rii : 0.0;
-                r[i] = v;
-                if (act && lane >= i) G[gi][c] = v;
+                else v = (c < n) ? g[i] / rii : 0.0;
+#pragma unroll
+                for (int i2 = i + 1; i2 < 16; ++i2) g[i2] = fma(-readlane_f64(v, i2), v, g[i2]);
+                g[i] = v;
+            }
+            if (act) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) G[b0 + i][c] = g[i];
             }
         }
         __syncthreads();
@@ -287,9 +293,9 @@ HQR_DEV void chol64_blk(double (*G)[LD65], int n, int lane, int w, double ratio,
 // factorization without pivoting of M - S, s_k = -sgn(pivot k) (sgn(0) = +1)
 // chosen at step k; entries outside the block stay zero.  Block steps of 16:
 // ONE wave computes U's block row and L's block column (lane t owning column
-// 16kb + t of U and row 16kb + t of L, Doolittle order within the block, the
-// pivot by readlane, finished entries read back from LDS as broadcasts), then
-// all waves subtract L_p U_p from the trailing blocks on MFMA.  Starts and
+// 16kb + t of U and row 16kb + t of L, right-looking within the block with
+// the other lanes' entries by readlane), then all waves subtract L_p U_p
+// from the trailing blocks on MFMA.  Starts and
 // ends with a barrier.
 HQR_DEV void lu_sign64_blk(double (*M)[LD65], int n, int lane, int w, double *sgn, double *udiag)
 {
@@ -298,32 +304,43 @@ HQR_DEV void lu_sign64_blk(double (*M)[LD65], int n, int lane, int w, double *sg
     for (int kb = 0; kb < 4; ++kb) {
         const int b0 = 16 * kb;
         if (w == 0) {
+            // lane t holds column t over the block rows (cv) and row t over the
+            // block columns (rv); the diagonal block is in both copies, which
+            // receive identical updates; other lanes' entries by readlane
             const int t = b0 + lane;
             const bool act = t < NB;
-            double u[16], lr[16];
+            double cv[16], rv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                cv[i] = act ? M[b0 + i][t] : 0.0;
+                rv[i] = act ? M[t][b0 + i] : 0.0;
+            }
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int gi = b0 + i;
-                // column role: U[gi][t] = M'[gi][t] - sum_l L[gi][b0+l] U[b0+l][t]
-                double su = act ? M[gi][t] : 0.0;
-#pragma unroll
-                for (int l = 0; l < i; ++l) su = fma(-M[gi][b0 + l], u[l], su);
-                const double q = readlane_f64(su, i);
+                const double q = readlane_f64(cv[i], i);
                 const double sg = (q >= 0.0) ? -1.0 : 1.0;
                 const double ukk = q - sg;
-                const double uv = (lane > i) ? su : ((lane == i) ? ukk : 0.0);
-                u[i] = uv;
-                if (gi < n && act && lane >= i && t < n) M[gi][t] = uv;
-                // row role: L[t][gi] = (M'[t][gi] - sum_l L[t][b0+l] U[b0+l][gi]) / U_kk
-                double sl = act ? M[t][gi] : 0.0;
+                const double u = (lane > i) ? cv[i] : ((lane == i) ? ukk : 0.0);   // U[gi][t]
+                const double l = (lane > i) ? rv[i] / ukk : 0.0;                   // L[t][gi]
 #pragma unroll
-                for (int l = 0; l < i; ++l) sl = fma(-lr[l], M[b0 + l][gi], sl);
-                const double lv = (lane > i) ? sl / ukk : 0.0;
-                lr[i] = lv;
-                if (gi < n && act && lane > i && t < n) M[t][gi] = lv;
+                for (int i2 = i + 1; i2 < 16; ++i2) {
+                    cv[i2] = fma(-readlane_f64(l, i2), u, cv[i2]);
+                    rv[i2] = fma(-l, readlane_f64(u, i2), rv[i2]);
+                }
+                cv[i] = u;
+                rv[i] = l;
                 if (lane == 0 && gi < n) {
                     sgn[gi] = sg;
                     udiag[gi] = ukk;
+                }
+            }
+            if (act && t < n) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int gi = b0 + i;
+                    if (gi < n && lane >= i) M[gi][t] = cv[i];
+                    if (gi < n && lane > i) M[t][gi] = rv[i];
                 }
             }
         }
@@ -513,6 +530,19 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         ++tsi;                                                                   \
     } while (0)
     HQR_TS();
+    // pass 2 reads R1^{-1}, R1 and A's top block late: load them now, so the
+    // loads overlap the Cholesky factorization
+    double pf_r1inv[16], pf_r1[16], pf_at[16];
+    if (p.pass == 2) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int idx = tid + 256 * t;
+            const int c = idx / NB, r = idx % NB;
+            pf_r1inv[t] = p.r1inv[idx];
+            pf_r1[t] = p.r1[idx];
+            pf_at[t] = (r < bw && c < bw) ? HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) : 0.0;
+        }
+    }
 
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, j = idx % NB;
@@ -540,19 +570,28 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     }
 
     // ---- pass 2: M0 = R2
-    for (int idx = tid; idx < NB * NB; idx += 256) M2[idx / NB][idx % NB] = p.r1inv[idx];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int idx = tid + 256 * t;
+        M2[idx / NB][idx % NB] = pf_r1inv[t];
+    }
     inv_upper64_blk(M1, M0, bw, lane, w);                // M1 = R2^{-1}
     HQR_TS();
     mm64(M3, M2, M1, lane, w);                          // M3 = R^{-1} = R1^{-1} R2^{-1}
     __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += 256) M2[idx / NB][idx % NB] = p.r1[idx];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int idx = tid + 256 * t;
+        M2[idx / NB][idx % NB] = pf_r1[t];
+    }
     __syncthreads();
     mm64(M1, M0, M2, lane, w);                          // M1 = R = R2 R1
     __syncthreads();
     // Q_top = A_top R^{-1}
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int c = idx / NB, r = idx % NB;
-        M2[r][c] = (r < bw && c < bw) ? HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) : 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int idx = tid + 256 * t;
+        M2[idx % NB][idx / NB] = pf_at[t];
     }
     __syncthreads();
     mm64(M0, M2, M3, lane, w);                          // M0 = Q_top
