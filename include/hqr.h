@@ -11,7 +11,8 @@
  *     reflectors, without forming Q (Section 1);
  *   - qr_backsolve back-substitutes with R (abstract; Section 6 names the
  *     triangular solve as a kernel of the same solver);
- *   - qr_lsq_solve chains the three.
+ *   - qr_lsq_solve chains the three; qr_lsq_refine solves again with a
+ *     stored factorization and refines against the original matrix.
  *
  * Conventions shared by every entry point:
  *   - Matrices are FP64, column-major, leading dimension >= max(1, rows).
@@ -107,12 +108,31 @@ int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda,
  *     FP64 copy of A (same m x n, leading dimension lda_orig) used for the
  *     FP64 residuals of the refinement; resnorm is then ||b - A x||.
  *   info: device int (0, k+1 for a zero R[k][k], HQR_INFO_* flags);
- *   iters: device int or NULL, refinement steps taken (0 for FP64). */
+ *   iters: device int or NULL, refinement steps taken (0 for FP64).
+ *   The mixed form synchronizes `stream` with the host once per right-hand
+ *   side (to read the convergence record), and so does qr_lsq_refine. */
 int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
                  double *up, double *B, int64_t ldb, double *resnorm,
                  const hqr_opts *opt, const double *A_orig, int64_t lda_orig,
                  void *work, int64_t lwork, int *info, int *iters,
                  hipStream_t stream);
+
+/* Solve again with a stored factorization (qr_factor's output, from either
+ * precision, e.g. a previous mixed-precision qr_lsq_solve), then refine:
+ * B (m x nrhs) <- Q^T B, back-substitute, and correct x with the
+ * semi-normal equations using FP64 residuals of A_orig, the unmodified FP64
+ * A (r = b - A_orig x, A_orig^T r, R^T z = A_orig^T r, R dx = z), as the
+ * mixed form of qr_lsq_solve does (opt->tol, opt->max_iter; opt may be
+ * NULL).  x ends in B[0:n]; resnorm (device, nrhs doubles, or NULL) gets
+ * ||b - A_orig x||.  A and up are never modified.  Without convergence the
+ * problem is solved in FP64 from a copy of A_orig (a stream-ordered
+ * allocation of m*n doubles) and HQR_INFO_NOCONV is ORed into info; a zero
+ * R[k][k] gives info = k+1.  iters (device int or NULL): steps taken. */
+int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A,
+                  int64_t lda, const double *up, double *B, int64_t ldb,
+                  double *resnorm, const hqr_opts *opt, const double *A_orig,
+                  int64_t lda_orig, void *work, int64_t lwork, int *info,
+                  int *iters, hipStream_t stream);
 
 /* Many independent least-squares problems of uneven size in ONE persistent
  * launch (a batch of the per-iteration subproblems an SLSQP-like solver

@@ -586,15 +586,23 @@ struct TrsvArgs {
 
 constexpr int TRSV_MAXRHS = 8;
 
-// TRANS: solve R^T x = b instead (forward substitution; workgroup b owns
-// row block b and waits for the blocks above it).
-template <bool TRANS>
+// Workgroup b owns row block b (64 rows; for TRANS, R^T x = b by forward
+// substitution and the blocks above it).  Everything that does not depend on
+// other blocks is loaded before the first wait: the diagonal block (with the
+// reciprocals of its diagonal), the block's right-hand sides, and each
+// off-diagonal block of R one iteration ahead, in registers.  The remaining
+// critical path per block is: observe the predecessor's flag, read its x,
+// one 64 x 64 block product, a 64-step substitution with multiplies by the
+// precomputed reciprocals, publish.  NR: right-hand sides handled per pass
+// (1, or TRSV_MAXRHS for 2..8).
+template <bool TRANS, int NR>
 __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
 {
-    __shared__ double xs[64][TRSV_MAXRHS];
-    __shared__ double accs[64][TRSV_MAXRHS];
-    __shared__ double part[4][64][TRSV_MAXRHS];
+    __shared__ double xs[64][NR];
+    __shared__ double accs[64][NR];
+    __shared__ double part[4][64][NR];
     __shared__ double Rd[64][65];
+    __shared__ double rinv[64];
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
     if (*((volatile int *)p.info) != 0) return;
@@ -604,13 +612,39 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
     const int nr = (int)min<int64_t>(64, p.n - r0);
     const int nrhs = p.nrhs;
     if (tid == 0) bad = 0;
-    // accumulator: thread (row lane, group g) keeps partial sums for rhs c
-    double acc[TRSV_MAXRHS];
+    // independent of the other blocks: diagonal block, own right-hand sides
+    for (int idx = tid; idx < nr * nr; idx += 256) {
+        const int cc = idx / nr, r = idx - cc * nr;
+        Rd[r][cc] = HQR_AT(p.A, r0 + r, r0 + cc, p.lda);
+    }
+    for (int idx = tid; idx < nr * NR; idx += 256) {
+        const int c = idx / nr, r = idx - c * nr;
+        accs[r][c] = (c < nrhs) ? HQR_AT(p.B, r0 + r, c, p.ldb) : 0.0;
+    }
+    double acc[NR];
 #pragma unroll
-    for (int c = 0; c < TRSV_MAXRHS; ++c) acc[c] = 0.0;
-    __syncthreads();
-    for (int jj = 0; jj < (TRANS ? ib : nblk - 1 - ib); ++jj) {
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+    const int npred = TRANS ? ib : nblk - 1 - ib;
+    // off-diagonal block of iteration jj: thread (row lane, group g) takes
+    // columns g, g + 4, .., of the predecessor block
+    auto fetch = [&](int jj, double (&rv)[16]) {
         const int jb = TRANS ? jj : nblk - 1 - jj;
+        const int64_t c0 = (int64_t)jb * 64;
+        const int nc = (int)min<int64_t>(64, p.n - c0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int l = g + 4 * q;
+            rv[q] = (lane < nr && l < nc) ? (TRANS ? HQR_AT(p.A, c0 + l, r0 + lane, p.lda) : HQR_AT(p.A, r0 + lane, c0 + l, p.lda))
+                                          : 0.0;
+        }
+    };
+    double rv[16], rn[16];
+    if (npred > 0) fetch(0, rv);
+    __syncthreads();
+    if (tid < nr) rinv[tid] = 1.0 / Rd[tid][tid];
+    for (int jj = 0; jj < npred; ++jj) {
+        const int jb = TRANS ? jj : nblk - 1 - jj;
+        if (jj + 1 < npred) fetch(jj + 1, rn);
         if (tid == 0) {
             long s = 0;
             while (__hip_atomic_load(&p.flags[jb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != p.epoch) {
@@ -618,26 +652,26 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
                     bad = 1;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
             }
         }
         __syncthreads();
         if (bad) break;
         const int64_t c0 = (int64_t)jb * 64;
         const int nc = (int)min<int64_t>(64, p.n - c0);
-        for (int idx = tid; idx < 64 * TRSV_MAXRHS; idx += 256) {
-            const int r = idx / TRSV_MAXRHS, c = idx - r * TRSV_MAXRHS;
+        for (int idx = tid; idx < 64 * NR; idx += 256) {
+            const int r = idx / NR, c = idx - r * NR;
             xs[r][c] = (r < nc && c < nrhs) ? __hip_atomic_load(&p.B[(size_t)(c0 + r) + (size_t)c * p.ldb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
         }
         __syncthreads();
-        if (lane < nr) {
-#pragma unroll 4
-            for (int l = g; l < nc; l += 4) {
-                const double rv = TRANS ? HQR_AT(p.A, c0 + l, r0 + lane, p.lda) : HQR_AT(p.A, r0 + lane, c0 + l, p.lda);
 #pragma unroll
-                for (int c = 0; c < TRSV_MAXRHS; ++c) acc[c] += rv * xs[l][c];
-            }
+        for (int q = 0; q < 16; ++q) {
+            const int l = g + 4 * q;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = fma(rv[q], xs[l][c], acc[c]);
         }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) rv[q] = rn[q];
         __syncthreads();
     }
     if (bad) {
@@ -645,35 +679,23 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
         return;
     }
 #pragma unroll
-    for (int c = 0; c < TRSV_MAXRHS; ++c) part[g][lane][c] = acc[c];
-    __syncthreads();
-    // diagonal block (staged in LDS) on wave 0: lanes = rows
-    for (int idx = tid; idx < nr * nr; idx += 256) {
-        const int cc = idx / nr, r = idx - cc * nr;
-        Rd[r][cc] = HQR_AT(p.A, r0 + r, r0 + cc, p.lda);
-    }
-    for (int idx = tid; idx < nr * nrhs; idx += 256) {
-        const int c = idx / nr, r = idx - c * nr;
-        accs[r][c] = HQR_AT(p.B, r0 + r, c, p.ldb);
-    }
+    for (int c = 0; c < NR; ++c) part[g][lane][c] = acc[c];
     __syncthreads();
     if (g == 0) {
-        for (int c = 0; c < nrhs; ++c) {
+        for (int c = 0; c < nrhs && c < NR; ++c) {
             double t = 0.0;
             if (lane < nr)
                 t = accs[lane][c] - (((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c]);
             if (TRANS) {
                 for (int i = 0; i < nr; ++i) {
-                    const double ti = readlane_f64(t, i);
-                    const double xi = ti / Rd[i][i];
-                    if (lane > i && lane < nr) t -= Rd[i][lane] * xi;
+                    const double xi = readlane_f64(t, i) * rinv[i];
+                    if (lane > i && lane < nr) t = fma(-Rd[i][lane], xi, t);
                     if (lane == i) t = xi;
                 }
             } else {
                 for (int i = nr - 1; i >= 0; --i) {
-                    const double ti = readlane_f64(t, i);
-                    const double xi = ti / Rd[i][i];
-                    if (lane < i) t -= Rd[lane][i] * xi;
+                    const double xi = readlane_f64(t, i) * rinv[i];
+                    if (lane < i) t = fma(-Rd[lane][i], xi, t);
                     if (lane == i) t = xi;
                 }
             }

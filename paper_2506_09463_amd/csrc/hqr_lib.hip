@@ -700,10 +700,17 @@ static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int
         t.info = info;
         t.epoch = 1;
         t.spin_limit = 20000000L;
-        if (trans)
-            HQR_LAUNCH(K_TRSV, trsv_kernel<true>, dim3(pl.nblk), dim3(256), 0, s, t);
-        else
-            HQR_LAUNCH(K_TRSV, trsv_kernel<false>, dim3(pl.nblk), dim3(256), 0, s, t);
+        if (t.nrhs == 1) {
+            if (trans)
+                HQR_LAUNCH(K_TRSV, (trsv_kernel<true, 1>), dim3(pl.nblk), dim3(256), 0, s, t);
+            else
+                HQR_LAUNCH(K_TRSV, (trsv_kernel<false, 1>), dim3(pl.nblk), dim3(256), 0, s, t);
+        } else {
+            if (trans)
+                HQR_LAUNCH(K_TRSV, (trsv_kernel<true, TRSV_MAXRHS>), dim3(pl.nblk), dim3(256), 0, s, t);
+            else
+                HQR_LAUNCH(K_TRSV, (trsv_kernel<false, TRSV_MAXRHS>), dim3(pl.nblk), dim3(256), 0, s, t);
+        }
         HQR_CK(hipGetLastError());
     }
     return 0;
@@ -781,6 +788,68 @@ static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, 
 // max_iter steps is enqueued; the stream is synchronized once at the end to
 // read the convergence record and, without convergence, the FP64 path is
 // run on the restored inputs (info gets HQR_INFO_NOCONV).
+// Corrections of the semi-normal equations for every right-hand side:
+// x (in B[0:n]) += dx until converged (see csne_update_kernel), with FP64
+// residuals of A0 against the original right-hand sides in w.borig and
+// triangular solves with R (upper triangle of A).  Reports the largest
+// first-converged step and whether every column converged.
+static int mixed_refine(const Plan &pl, const Work &w, const double *A, int64_t lda, double *B, int64_t ldb,
+                        int64_t nrhs, double *resnorm, double tol, int max_iter, const double *A0, int64_t lda0,
+                        hipStream_t s, int *first, bool *converged)
+{
+    const int64_t m = pl.m, n = pl.n;
+    *first = 0;
+    *converged = true;
+    for (int64_t c = 0; c < nrhs; ++c) {
+        double *x = B + (size_t)c * ldb;
+        const double *b0 = w.borig + (size_t)c * m;
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, w.mstat, 0, (int64_t)4);
+        HQR_CK(hipGetLastError());
+        for (int it = 0; it < max_iter; ++it) {
+            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
+                       (const double *)x, w.rvec, m, n);
+            HQR_LAUNCH(K_REFINE, gemvt_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, A0, lda0,
+                       (const double *)w.rvec, w.gvec, m, n);
+            HQR_CK(hipGetLastError());
+            int rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, true);
+            if (rc) return rc;
+            rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, false);
+            if (rc) return rc;
+            HQR_LAUNCH(K_REFINE, csne_update_kernel, dim3(1), dim3(1024), 0, s, x, (const double *)w.gvec, n, tol,
+                       it, w.mstat, w.mstat_d);
+            HQR_CK(hipGetLastError());
+        }
+        if (resnorm) {
+            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
+                       (const double *)x, w.rvec, m, n);
+            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3(1), dim3(256), 0, s, (const double *)w.rvec,
+                       std::max<int64_t>(m, 1), (int64_t)0, m, resnorm + c);
+            HQR_CK(hipGetLastError());
+        }
+        int st[4] = {0, 0, 0, 0};
+        HQR_CK(hipMemcpyAsync(st, w.mstat, sizeof(st), hipMemcpyDeviceToHost, s));
+        HQR_CK(hipStreamSynchronize(s));
+        if (st[0] == 0 || st[1]) *converged = false;
+        *first = std::max(*first, st[0]);
+    }
+    return 0;
+}
+
+static int write_iters(int *iters, int v, hipStream_t s)
+{
+    if (!iters) return 0;
+    HQR_CK(hipMemcpyAsync(iters, &v, sizeof(int), hipMemcpyHostToDevice, s));
+    HQR_CK(hipStreamSynchronize(s));
+    return 0;
+}
+
+// Mixed precision: FP32 trailing contractions in the factorization, then
+// corrections of the semi-normal equations with FP64 residuals:
+//   r = b - A0 x,  g = A0^T r,  R^T z = g,  R dx = z,  x += dx
+// (A0 = the unmodified FP64 matrix, R = the factor's triangle).  A run of
+// max_iter steps is enqueued; the stream is synchronized once per right-hand
+// side to read the convergence record and, without convergence, the FP64
+// path is run on the restored inputs (info gets HQR_INFO_NOCONV).
 static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B,
                      int64_t ldb, double *resnorm, const hqr_opts *opt, const double *A0, int64_t lda0, void *work,
                      int64_t lwork, int *info, int *iters, hipStream_t s)
@@ -801,40 +870,10 @@ static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
     if (rc) return rc;
     rc = backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, s);
     if (rc) return rc;
-    int total_first = 0;
+    int first = 0;
     bool converged = true;
-    for (int64_t c = 0; c < nrhs; ++c) {
-        double *x = B + (size_t)c * ldb;
-        const double *b0 = w.borig + (size_t)c * m;
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, w.mstat, 0, (int64_t)4);
-        HQR_CK(hipGetLastError());
-        for (int it = 0; it < max_iter; ++it) {
-            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
-                       (const double *)x, w.rvec, m, n);
-            HQR_LAUNCH(K_REFINE, gemvt_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, A0, lda0,
-                       (const double *)w.rvec, w.gvec, m, n);
-            HQR_CK(hipGetLastError());
-            rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, true);
-            if (rc) return rc;
-            rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, false);
-            if (rc) return rc;
-            HQR_LAUNCH(K_REFINE, csne_update_kernel, dim3(1), dim3(1024), 0, s, x, (const double *)w.gvec, n, tol,
-                       it, w.mstat, w.mstat_d);
-            HQR_CK(hipGetLastError());
-        }
-        if (resnorm) {
-            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
-                       (const double *)x, w.rvec, m, n);
-            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3(1), dim3(256), 0, s, (const double *)w.rvec,
-                       std::max<int64_t>(m, 1), (int64_t)0, m, resnorm + c);
-            HQR_CK(hipGetLastError());
-        }
-        int st[4] = {0, 0, 0, 0};
-        HQR_CK(hipMemcpyAsync(st, w.mstat, sizeof(st), hipMemcpyDeviceToHost, s));
-        HQR_CK(hipStreamSynchronize(s));
-        if (st[0] == 0 || st[1]) converged = false;
-        total_first = std::max(total_first, st[0]);
-    }
+    rc = mixed_refine(pl, w, A, lda, B, ldb, nrhs, resnorm, tol, max_iter, A0, lda0, s, &first, &converged);
+    if (rc) return rc;
     int hinfo = 0;
     HQR_CK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
     HQR_CK(hipStreamSynchronize(s));
@@ -848,14 +887,10 @@ static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
         if (rc) return rc;
         hinfo = HQR_INFO_NOCONV;
         HQR_CK(hipMemcpyAsync(info, &hinfo, sizeof(int), hipMemcpyHostToDevice, s));
-        total_first = max_iter;
+        first = max_iter;
         HQR_CK(hipStreamSynchronize(s));
     }
-    if (iters) {
-        HQR_CK(hipMemcpyAsync(iters, &total_first, sizeof(int), hipMemcpyHostToDevice, s));
-        HQR_CK(hipStreamSynchronize(s));
-    }
-    return 0;
+    return write_iters(iters, first, s);
 }
 
 } // namespace hqr
@@ -1169,6 +1204,79 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
         HQR_CK(hipGetLastError());
     }
     return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, work, lwork, info, stream);
+}
+
+int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *up, double *B,
+                  int64_t ldb, double *resnorm, const hqr_opts *opt, const double *A_orig, int64_t lda_orig,
+                  void *work, int64_t lwork, int *info, int *iters, hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (nrhs < 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (ldb < std::max<int64_t>(1, m)) return -8;
+    if (!info) return -15;
+    if (n > 0 && !A) return -4;
+    if (n > 0 && !up) return -6;
+    if (nrhs > 0 && !B) return -7;
+    if (n > 0 && !A_orig) return -11;
+    if (lda_orig < std::max<int64_t>(1, m)) return -12;
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+    HQR_CK(hipGetLastError());
+    if (iters) {
+        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
+        HQR_CK(hipGetLastError());
+    }
+    if (n == 0 || nrhs == 0) return 0;
+    const double tol = (opt && opt->tol > 0.0) ? opt->tol : 1e-13;
+    const int max_iter = (opt && opt->max_iter >= 0) ? opt->max_iter : 10;
+    Plan pl = make_plan(m, n, nrhs, NB, true);
+    WorkGuard g;
+    Work w;
+    int rc = get_work(pl, work, lwork, stream, g, &w);
+    if (rc) return rc;
+    HQR_CK(hipMemcpy2DAsync(w.borig, sizeof(double) * m, B, sizeof(double) * ldb, sizeof(double) * m, nrhs,
+                            hipMemcpyDeviceToDevice, stream));
+    rc = qr_apply_qt(m, n, nrhs, A, lda, up, B, ldb, nullptr, 0, stream);
+    if (rc) return rc;
+    rc = backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, stream);
+    if (rc) return rc;
+    int first = 0;
+    bool converged = true;
+    rc = mixed_refine(pl, w, A, lda, B, ldb, nrhs, resnorm, tol, max_iter, A_orig, lda_orig, stream, &first,
+                      &converged);
+    if (rc) return rc;
+    int hinfo = 0;
+    HQR_CK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HQR_CK(hipStreamSynchronize(stream));
+    if (!converged && hinfo == 0) {
+        // FP64 solve from a copy of A_orig; the stored factorization is kept
+        double *A2 = nullptr;
+        if (hipMallocAsync((void **)&A2, sizeof(double) * (size_t)m * (size_t)n, stream) != hipSuccess)
+            return HQR_ENOMEM;
+        WorkGuard g2;
+        g2.ptr = A2;
+        g2.s = stream;
+        double *up2 = nullptr;
+        if (hipMallocAsync((void **)&up2, sizeof(double) * (size_t)n, stream) != hipSuccess) return HQR_ENOMEM;
+        WorkGuard g3;
+        g3.ptr = up2;
+        g3.s = stream;
+        HQR_CK(hipMemcpy2DAsync(A2, sizeof(double) * m, A_orig, sizeof(double) * lda_orig, sizeof(double) * m, n,
+                                hipMemcpyDeviceToDevice, stream));
+        HQR_CK(hipMemcpy2DAsync(B, sizeof(double) * ldb, w.borig, sizeof(double) * m, sizeof(double) * m, nrhs,
+                                hipMemcpyDeviceToDevice, stream));
+        rc = lsq_fp64(m, n, nrhs, A2, m, up2, B, ldb, resnorm, nullptr, 0, info, stream);
+        if (rc) return rc;
+        HQR_CK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, stream));
+        HQR_CK(hipStreamSynchronize(stream));
+        hinfo |= HQR_INFO_NOCONV;
+        HQR_CK(hipMemcpyAsync(info, &hinfo, sizeof(int), hipMemcpyHostToDevice, stream));
+        HQR_CK(hipStreamSynchronize(stream));
+        first = max_iter;
+    }
+    return write_iters(iters, first, stream);
 }
 
 int hqr_tune_set(int op, int64_t m_lo, int64_t m_hi, int64_t n_lo, int64_t n_hi, int precision, int choice)

@@ -28,7 +28,8 @@ HQR_TUNE_BATCHED = 1
 TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_backsolve",
-           "qr_lsq_solve", "hqr_batched_workspace_size", "qr_lsq_solve_batched", "qr_lsq_batched_mixed",
+           "qr_lsq_solve", "qr_lsq_refine", "hqr_batched_workspace_size", "qr_lsq_solve_batched",
+           "qr_lsq_batched_mixed",
            "hqr_tune_set", "hqr_tune_clear", "hqr_tune_variants", "hqr_tune_variant_name",
            "hqr_profile_begin", "hqr_profile_end", "hqr_profile_class",
            "hqr_status_string", "hqr_version")
@@ -63,7 +64,9 @@ def load(path: str = LIB_PATH):
     lib.qr_backsolve.argtypes = [i64, i64, vp, i64, vp, i64, ip, vp]
     lib.qr_lsq_solve.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp,
                                  ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
-    for fn in ("qr_factor", "qr_apply_qt", "qr_backsolve", "qr_lsq_solve"):
+    lib.qr_lsq_refine.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp,
+                                  ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
+    for fn in ("qr_factor", "qr_apply_qt", "qr_backsolve", "qr_lsq_solve", "qr_lsq_refine"):
         getattr(lib, fn).restype = ctypes.c_int
     lib.hqr_status_string.argtypes = [ctypes.c_int]
     lib.hqr_status_string.restype = ctypes.c_char_p
@@ -279,6 +282,30 @@ def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=H
                                             _ptr(resnorm), ctypes.byref(opts), _ptr(A_orig), lda_o,
                                             _ptr(work), lw, _ptr(info), _ptr(iters), _stream(stream)))
     return up, resnorm, info, iters
+
+
+def qr_lsq_refine(A, up, B, A_orig, resnorm=None, info=None, iters=None, tol=0.0, max_iter=-1, work=None,
+                  stream=None):
+    """Solve again with the stored factorization in (A, up) and refine against
+    A_orig (FP64 copy of the original matrix); B[0:n] <- x.  A, up are not
+    modified.  Returns (resnorm, info, iters)."""
+    torch = _torch()
+    lib = load()
+    m, n = A.shape
+    mb, nrhs = B.shape
+    if mb != m or tuple(A_orig.shape) != (m, n):
+        raise ValueError("B and A_orig must match A's rows (and A_orig A's shape)")
+    dev = A.device
+    if resnorm is None:
+        resnorm = torch.empty(max(nrhs, 1), dtype=torch.float64, device=dev)
+    info = _int_dev(info, dev)
+    iters = _int_dev(iters, dev)
+    opts = hqr_opts(HQR_PREC_MIXED, float(tol), int(max_iter))
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("qr_lsq_refine", lib.qr_lsq_refine(m, n, nrhs, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(B), _ld(B, "B"),
+                                              _ptr(resnorm), ctypes.byref(opts), _ptr(A_orig), _ld(A_orig, "A_orig"),
+                                              _ptr(work), lw, _ptr(info), _ptr(iters), _stream(stream)))
+    return resnorm, info, iters
 
 
 def profile_begin():

@@ -38,6 +38,7 @@ from typing import Callable, Dict, List, Optional
 import numpy as np
 
 GiB = 1 << 30
+MIXED_MIN_N = 513   # smallest n served by the mixed-precision path
 
 
 @dataclasses.dataclass
@@ -62,10 +63,24 @@ class Request:
     def nrhs(self) -> int:
         return self.B.shape[1]
 
+    @property
+    def mixed_path(self) -> bool:
+        """Served in mixed precision (FP32 trailing updates + FP64
+        refinement): mixed-flagged instances above the batched kernel's
+        range.  Smaller mixed-flagged instances are solved in FP64 by the
+        batched launch, which already meets the accuracy target and gains
+        nothing from FP32 at those sizes."""
+        return self.precision == "mixed" and self.n >= MIXED_MIN_N
+
+    def factor_bytes(self) -> int:
+        """Device bytes of the cached factorization: A's factor and up, plus
+        the FP64 copy of A that mixed-precision refinement reads."""
+        return 8 * (self.m * self.n + self.n) + (8 * self.m * self.n if self.mixed_path else 0)
+
     def bytes_needed(self, have_factor: bool) -> int:
         b = 8 * self.m * self.nrhs
         if not have_factor:
-            b += 8 * (self.m * self.n + self.n)
+            b += self.factor_bytes()
         return b
 
 
@@ -196,7 +211,7 @@ class Server:
                     self.ex.free_factor(entry.handle)
                     self._give(entry.bytes)
                     del self.cache[req.instance]
-                fbytes = 8 * (req.m * req.n + req.n)
+                fbytes = req.factor_bytes()
                 if not self._take(req.bytes_needed(False)):
                     keep.append(req)
                     continue
@@ -276,9 +291,11 @@ class GpuExecutor:
     """Runs batches through libhqr on `nstreams` torch streams.
 
     Instances with n <= ``batch_n_max`` go to one persistent batched launch
-    per batch; larger ones are solved one by one with the whole-GPU blocked
-    path (qr_lsq_solve, or qr_apply_qt + qr_backsolve for cached factors) on
-    the same stream, after the batched launch."""
+    per batch (FP64); larger ones are solved one by one with the whole-GPU
+    path on the same stream, after the batched launch: FP64 requests by
+    qr_lsq_solve (cached factors: qr_apply_qt + qr_backsolve), mixed ones by
+    the mixed-precision qr_lsq_solve, keeping an FP64 copy of A beside the
+    factor, and for cached factors qr_lsq_refine against that copy."""
 
     def __init__(self, nstreams: int = 2, batch_n_max: int = 512, device="cuda"):
         import torch
@@ -316,8 +333,9 @@ class GpuExecutor:
                     A = hqr.empty_colmajor(r.m, r.n, device=self.device)
                     A.copy_(self._host(r.A), non_blocking=True)
                     up = torch.empty(max(r.n, 1), dtype=torch.float64, device=self.device)
-                    e.handle = (A, up)
-                A, up = e.handle
+                    A0 = A.clone() if (r.mixed_path and r.n > self.batch_n_max) else None
+                    e.handle = (A, up, A0)
+                A, up, A0 = e.handle
                 B = hqr.empty_colmajor(r.m, r.nrhs, device=self.device)
                 B.copy_(self._host(r.B), non_blocking=True)
                 res = torch.empty(max(r.nrhs, 1), dtype=torch.float64, device=self.device)
@@ -329,15 +347,21 @@ class GpuExecutor:
                     small_fact.append(r.kind == "solve")
                     small_req.append(r)
                 else:
-                    large.append((r, A, up, B, res))
+                    large.append((r, A, up, A0, B, res))
             info = torch.zeros(max(len(small_req), 1), dtype=torch.int32, device=self.device)
             if small_req:
                 hqr.qr_lsq_solve_batched(small_A, small_B, ups=small_up, resnorms=small_res, info=info,
                                          stream=s, factored=small_fact)
             linfo = []
-            for r, A, up, B, res in large:
+            for r, A, up, A0, B, res in large:
                 li = torch.zeros(1, dtype=torch.int32, device=self.device)
-                if r.kind == "factor_solve":
+                if A0 is not None:
+                    if r.kind == "factor_solve":
+                        hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=li, precision=hqr.HQR_PREC_MIXED,
+                                         A_orig=A0, stream=s)
+                    else:
+                        hqr.qr_lsq_refine(A, up, B, A0, resnorm=res, info=li, stream=s)
+                elif r.kind == "factor_solve":
                     hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=li, stream=s)
                 else:
                     hqr.qr_apply_qt(A, up, B, stream=s)
@@ -346,7 +370,7 @@ class GpuExecutor:
             ev = torch.cuda.Event()
             ev.record(s)
         outs = {id(r): (B, res) for r, B, res in zip(small_req, small_B, small_res)}
-        for k, (r, A, up, B, res) in enumerate(large):
+        for k, (r, A, up, A0, B, res) in enumerate(large):
             outs[id(r)] = (B, res)
         return {"stream": si, "event": ev, "outs": outs, "small": small_req, "info": info,
                 "large": [(r, li) for (r, *_), li in zip(large, linfo)]}

@@ -54,6 +54,12 @@ def test_argument_validation_without_gpu(lib):
     assert lib.qr_factor(4, 3, None, 2, None, None, 0, ctypes.byref(info), None) == -4
     assert lib.qr_apply_qt(4, 3, -1, None, 4, None, None, 4, None, 0, None) == -3
     assert lib.qr_backsolve(3, 1, None, 2, None, 3, ctypes.byref(info), None) == -4
+    assert lib.qr_lsq_refine(3, 4, 1, None, 3, None, None, 3, None, None, None, 3, None, 0,
+                             ctypes.byref(info), None, None) == -2
+    assert lib.qr_lsq_refine(4, 3, 1, None, 2, None, None, 4, None, None, None, 4, None, 0,
+                             ctypes.byref(info), None, None) == -5
+    assert lib.qr_lsq_refine(4, 3, 1, None, 4, None, None, 4, None, None, None, 4, None, 0,
+                             None, None, None) == -15
     assert lib.hqr_status_string(-1002).decode().startswith("a HIP call")
     assert "gfx950" in lib.hqr_version().decode()
 

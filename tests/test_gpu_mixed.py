@@ -74,3 +74,57 @@ def test_mixed_fallback_when_refinement_cannot_converge(hqr, oracle_mod, m, n):
     xo = oracle_mod.lsq_solve(A, b)[0][:, 0]
     r = b - A @ xo
     assert np.linalg.norm(X[:, 0] - xo) / np.linalg.norm(xo) <= 2 * lsq_forward_bound(A, xo, r)
+
+
+@pytest.mark.parametrize("m,n,kappa", [(128, 64, 1e6), (700, 300, 1e5)])
+def test_refine_with_stored_mixed_factor(hqr, oracle_mod, m, n, kappa):
+    """A factor from a mixed solve is reused for new right-hand sides: each
+    refined solution is within 1e-10 of the extended-precision reference and
+    the stored factor is left bitwise unchanged."""
+    import torch
+    A, b, _ = workloads.conditioned(m, n, kappa, seed=19)
+    print("[case] refine", (m, n, kappa), flush=True)
+    dA, dA0 = to_dev(A), to_dev(A)
+    dB = to_dev(b.reshape(m, 1))
+    up, _, info, _ = hqr.qr_lsq_solve(dA, dB, precision=hqr.HQR_PREC_MIXED, A_orig=dA0)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    F, U = to_host(dA).copy(), to_host(up).copy()
+    rng = np.random.default_rng(20)
+    B2 = np.stack([A @ rng.standard_normal(n) + 1e-8 * rng.standard_normal(m), rng.standard_normal(m)], axis=1)
+    dB2 = to_dev(B2)
+    res, info2, it = hqr.qr_lsq_refine(dA, up, dB2, dA0)
+    torch.cuda.synchronize()
+    assert int(info2.item()) == 0 and 1 <= int(it.item()) <= 10
+    assert np.array_equal(to_host(dA), F) and np.array_equal(to_host(up), U)
+    X = to_host(dB2)[:n]
+    for c in range(2):
+        xref, _ = oracle_mod.lsq_reference(A, B2[:, c])
+        assert np.linalg.norm(X[:, c] - xref) / np.linalg.norm(xref) <= 1e-10
+        assert abs(to_host(res)[c] - np.linalg.norm(B2[:, c] - A @ X[:, c])) <= 1e-12 * max(1.0, np.linalg.norm(B2[:, c]))
+
+
+def test_refine_with_fp64_factor_and_fallback(hqr, oracle_mod):
+    """qr_lsq_refine also takes an FP64 factor; with no steps allowed it
+    solves in FP64 from A_orig, flags it, and keeps the factor."""
+    import torch
+    m, n = 300, 90
+    A, b, _ = workloads.conditioned(m, n, 1e4, seed=21)
+    dA, dA0 = to_dev(A), to_dev(A)
+    up, info = hqr.qr_factor(dA)
+    torch.cuda.synchronize()
+    F, U = to_host(dA).copy(), to_host(up).copy()
+    dB = to_dev(b.reshape(m, 1))
+    _, info2, _ = hqr.qr_lsq_refine(dA, up, dB, dA0)
+    torch.cuda.synchronize()
+    xref, _ = oracle_mod.lsq_reference(A, b)
+    assert int(info2.item()) == 0
+    assert np.linalg.norm(to_host(dB)[:n, 0] - xref) / np.linalg.norm(xref) <= 1e-10
+    dB = to_dev(b.reshape(m, 1))
+    _, info3, _ = hqr.qr_lsq_refine(dA, up, dB, dA0, max_iter=0)
+    torch.cuda.synchronize()
+    assert int(info3.item()) & hqr.HQR_INFO_NOCONV
+    assert np.array_equal(to_host(dA), F) and np.array_equal(to_host(up), U)
+    xo = oracle_mod.lsq_solve(A, b)[0][:, 0]
+    r = b - A @ xo
+    assert np.linalg.norm(to_host(dB)[:n, 0] - xo) / np.linalg.norm(xo) <= 2 * lsq_forward_bound(A, xo, r)

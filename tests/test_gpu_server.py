@@ -55,3 +55,26 @@ def test_served_mix_equals_alone(oracle_mod):
         for c in range(r.nrhs):
             rr = r.B[:, c] - A @ xo[:, c]
             assert np.linalg.norm(r.x[:, c] - xo[:, c]) / np.linalg.norm(xo[:, c]) <= 2 * lsq_forward_bound(A, xo[:, c], rr)
+
+
+def test_served_mixed_precision_requests(oracle_mod):
+    """Mixed-flagged instances above the batched range are served by the
+    mixed-precision path (their factor and the FP64 copy of A cached for the
+    later solve-only requests); every such result is within 1e-10 of the
+    extended-precision reference, and FP64 ones within the FP64 bound."""
+    import torch
+    from paper_2506_09463_amd.server import MIXED_MIN_N
+    reqs = make_stream(40, seed=8, solves_per_instance=3, nmax=900)
+    mats = {r.instance: r.A.copy() for r in reqs if r.kind == "factor_solve"}
+    mixed = [r for r in reqs if r.mixed_path]
+    assert mixed, "the seeded stream has mixed-path instances"
+    assert all(r.n >= MIXED_MIN_N for r in mixed)
+    print("[case] served mixed", len(reqs), len(mixed), flush=True)
+    srv = _serve(reqs)
+    assert len(srv.done) == len(reqs) and not srv.rejected
+    for r in mixed:
+        assert r.info == 0, r.rid
+        A = mats[r.instance]
+        for c in range(r.nrhs):
+            xref, _ = oracle_mod.lsq_reference(A, r.B[:, c])
+            assert np.linalg.norm(r.x[:, c] - xref) / np.linalg.norm(xref) <= 1e-10, (r.rid, c)
