@@ -112,6 +112,8 @@ static WgVariant make_wg(const char *name)
 static const WgVariant *wg_variants(int *count)
 {
     static const WgVariant v[] = {
+        make_wg<64, 2>("wg64x2"),   // m <= 128, one wave
+        make_wg<64, 4>("wg64x4"),   // m <= 256, one wave
         make_wg<128, 1>("wg128x1"), // m <= 128
         make_wg<256, 1>("wg256x1"), // m <= 256
         make_wg<128, 4>("wg128x4"), // m <= 512

@@ -58,7 +58,7 @@ def _shapes(maxrows):
             (97, 33, 5)]
 
 
-@pytest.mark.parametrize("vi", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("vi", [0, 1, 2, 3, 4, 5, 6])
 def test_single_each_variant(hqr, oracle_mod, vi):
     import torch
     vs = _variants(hqr)
@@ -79,7 +79,7 @@ def test_single_each_variant(hqr, oracle_mod, vi):
         _check_solve(oracle_mod, A, B, to_host(dA), to_host(up), to_host(dB), to_host(res), int(info.item()))
 
 
-@pytest.mark.parametrize("vi", [0, 4])
+@pytest.mark.parametrize("vi", [0, 6])
 def test_factor_and_apply_each_variant(hqr, oracle_mod, vi):
     import torch
     vs = _variants(hqr)
