@@ -39,10 +39,10 @@ PEAK_HBM_GBS = 8000.0
 # kernel sources they were taken on (SHA-256 over csrc/); otherwise the
 # roofline's traffic is null.
 HBM_TRAFFIC = {
-    "csrc_sha256": "9c39f7631a7ed9f7c63ad63d38e47f149bea5bc050ffbd521f6243182b025e89",
-    "per_launch_bytes": {"cqr_chol": [129477, 82176], "update": [79272085, 55855379], "vtx": [69597759, 8928377],
-                         "cqr_gram": [3366868, 1590024], "wsolve": [8590799, 521192], "trsv": [68576538, 34816],
-                         "cqr_finish": [3443620, 3129344], "gram_reduce": [1621357, 32784]},
+    "csrc_sha256": "de888dc25cbd8b1c0e2536447f81b56d48a2aa737f0679fc1da43afb15f6b5c6",
+    "per_launch_bytes": {"cqr_chol": [176396, 82176], "update": [79285651, 55855378], "vtx": [69598542, 8928377],
+                         "cqr_gram": [3369960, 1590024], "wsolve": [8590798, 521192], "trsv": [68611723, 34816],
+                         "cqr_finish": [3443603, 3129344], "gram_reduce": [1621357, 32784]},
 }
 
 
