@@ -441,6 +441,34 @@ __global__ void __launch_bounds__(256) wsolve_kernel(WArgs p)
     }
 }
 
+// Narrow form (at most 64 columns, many row splits): 4 columns per
+// workgroup, thread (row i, column c) sums its partials 16 at a time.
+constexpr int WSN_COLS = 4;
+__global__ void __launch_bounds__(256) wsolve_narrow_kernel(WArgs p)
+{
+    __shared__ double Ws[NB][WSN_COLS + 1];
+    __shared__ double Ts[NB][NB + 1];
+    const int tid = threadIdx.x;
+    const int i = tid / WSN_COLS, c = tid % WSN_COLS;
+    const int x = p.xoff + blockIdx.x * WSN_COLS + c;
+    const int xe = p.xoff + p.ncols;
+    for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx / NB][idx % NB] = p.T[idx];
+    double s = 0.0;
+    if (i < p.bw && x < xe) {
+        const double *src = p.wpart + (size_t)i * p.nxpad + x;
+        const size_t stride = (size_t)NB * p.nxpad;
+#pragma unroll 16
+        for (int q = 0; q < p.nsplit; ++q) s += src[q * stride];
+    }
+    Ws[i][c] = s;
+    __syncthreads();
+    if (x < xe) {
+        double t = 0.0;
+        for (int l = 0; l <= i && l < p.bw; ++l) t += Ts[l][i] * Ws[l][c];
+        p.wp[(size_t)i * p.nxpad + x] = (i < p.bw) ? t : 0.0;
+    }
+}
+
 // ---------------------------------------------------------- X <- X - V W'
 // grid: (ceil(rows/64), ceil(ncols/64)); 256 threads.  Tile 64 rows x 64
 // columns, computed transposed (D' = W'^T V^T) so each accumulator register
@@ -551,6 +579,71 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
                 }
             }
 #undef HQR_CCOL
+}
+
+// X <- X - V W' for at most 64 columns (the next panel's columns on the
+// critical path): grid ceil(rows / 64); wave w owns rows [64 bx + 16 w, +16)
+// and all columns (four 16-column MFMA tiles), so the 64-deep contraction is
+// spread over many waves instead of a few 64 x 64 tiles.  Same operand
+// layout as update_kernel (D' = -W'^T V^T).
+template <bool F32>
+__global__ void __launch_bounds__(256) update_narrow_kernel(UpdArgs p)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t rb = (int64_t)p.c0 + (int64_t)blockIdx.x * 64 + 16 * w;
+    const int ncols = p.ncA + p.nB;
+    if (rb >= p.m) return; // no barriers below
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t gi = rb + li;
+    const bool rok = gi < p.m;
+    const bool masked = rb < (int64_t)p.c0 + p.bw;
+#define HQR_NCOL(r) (F32 ? 4 * lk + (r) : 4 * (r) + lk)
+    f64x4 acc[4];
+    f32x4 acc32[4];
+    double *cptr[4][4];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+        acc32[tj] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * tj + HQR_NCOL(r);
+            cptr[tj][r] = (c < ncols) ? col_ptr(p, c) : nullptr;
+            acc[tj][r] = (!F32 && cptr[tj][r] && rok) ? cptr[tj][r][gi] : 0.0;
+        }
+    }
+    // every operand is loaded before the first MFMA (80 values per lane)
+    const double *wrow = p.wp + p.xoff + li;
+    double a[NB / 4][4], bv[NB / 4];
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+        const int k = 4 * k4 + lk;
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+            a[k4][tj] = (k < p.bw && 16 * tj + li < ncols) ? -wrow[(size_t)k * p.nxpad + 16 * tj] : 0.0;
+        double b = 0.0;
+        if (k < p.bw && rok) b = masked ? v_elem(p.A, p.lda, p.up, p.c0, gi, k) : HQR_AT(p.A, gi, p.c0 + k, p.lda);
+        bv[k4] = b;
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+        const double b = bv[k4];
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) {
+            if (F32)
+                acc32[tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(to_f32(a[k4][tj]), to_f32(b), acc32[tj], 0, 0, 0);
+            else
+                acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k4][tj], b, acc[tj], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (cptr[tj][r] && rok) {
+                if (F32) cptr[tj][r][gi] = cptr[tj][r][gi] + (double)acc32[tj][r];
+                else cptr[tj][r][gi] = acc[tj][r];
+            }
+#undef HQR_NCOL
 }
 
 // ------------------------------------------------------------ triangular

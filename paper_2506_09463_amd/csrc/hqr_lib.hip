@@ -397,7 +397,14 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     v.nx = vcols + ncA + nB;
     v.nxpad = pl.nxpad;
     const int ntiles = (v.nx + VTX_COLS - 1) / VTX_COLS;
-    const int nsplit = pick_nsplit(rows, ntiles, pl.nsplit_max);
+    // narrow updates (at most 64 columns, the next panel's on the critical
+    // path): more row splits with a compact partial layout (row stride 128),
+    // within the space the wide layout reserves
+    const bool narrow = (ncA + nB) <= 64 && v.nx <= VTX_COLS;
+    if (narrow) v.nxpad = VTX_COLS;
+    const int nsplit = narrow ? std::max(1, std::min<int>((int)std::min<int64_t>(64, rows / 128),
+                                                           pl.nsplit_max * pl.nxpad / VTX_COLS))
+                              : pick_nsplit(rows, ntiles, pl.nsplit_max);
     v.split_rows = rup((rows + nsplit - 1) / nsplit, KC);
     const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
     v.wpart = tb.wpart;
@@ -416,7 +423,7 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
         t.bw = bw;
         t.wpart = tb.wpart;
         t.nsplit = nsplit_eff;
-        t.nxpad = pl.nxpad;
+        t.nxpad = v.nxpad;
         t.T = tb.T;
         HQR_LAUNCH(K_TFACTOR, tfactor_kernel, dim3(1), dim3(256), 0, s, t);
         HQR_CK(hipGetLastError());
@@ -427,13 +434,16 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     WArgs wa;
     wa.wpart = tb.wpart;
     wa.nsplit = nsplit_eff;
-    wa.nxpad = pl.nxpad;
+    wa.nxpad = v.nxpad;
     wa.xoff = vcols;
     wa.ncols = ncols;
     wa.bw = bw;
     wa.T = tb.T;
     wa.wp = tb.wp;
-    HQR_LAUNCH(K_WSOLVE, wsolve_kernel, dim3((ncols + WS_COLS - 1) / WS_COLS), dim3(256), 0, s, wa);
+    if (narrow)
+        HQR_LAUNCH(K_WSOLVE, wsolve_narrow_kernel, dim3((ncols + WSN_COLS - 1) / WSN_COLS), dim3(256), 0, s, wa);
+    else
+        HQR_LAUNCH(K_WSOLVE, wsolve_kernel, dim3((ncols + WS_COLS - 1) / WS_COLS), dim3(256), 0, s, wa);
     HQR_CK(hipGetLastError());
 
     UpdArgs u;
@@ -450,12 +460,20 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     u.aoff = aoff;
     u.xoff = vcols;
     u.wp = tb.wp;
-    u.nxpad = pl.nxpad;
-    const dim3 ug((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols + UPD_TILE - 1) / UPD_TILE);
-    if (f32)
-        HQR_LAUNCH(K_UPDATE, update_kernel<true>, ug, dim3(256), 0, s, u);
-    else
-        HQR_LAUNCH(K_UPDATE, update_kernel<false>, ug, dim3(256), 0, s, u);
+    u.nxpad = v.nxpad;
+    if (narrow) {
+        const dim3 ug((unsigned)((rows + 63) / 64));
+        if (f32)
+            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<true>, ug, dim3(256), 0, s, u);
+        else
+            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<false>, ug, dim3(256), 0, s, u);
+    } else {
+        const dim3 ug((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols + UPD_TILE - 1) / UPD_TILE);
+        if (f32)
+            HQR_LAUNCH(K_UPDATE, update_kernel<true>, ug, dim3(256), 0, s, u);
+        else
+            HQR_LAUNCH(K_UPDATE, update_kernel<false>, ug, dim3(256), 0, s, u);
+    }
     HQR_CK(hipGetLastError());
     return 0;
 }
@@ -586,7 +604,9 @@ static SideStream *side_stream()
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
     SideStream &ss = g_side[dev];
     if (ss.device != dev) {
-        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) return nullptr; else if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) {
+            return nullptr;
+        }
         for (auto &e : ss.ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
         ss.device = dev;
