@@ -604,9 +604,7 @@ static SideStream *side_stream()
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
     SideStream &ss = g_side[dev];
     if (ss.device != dev) {
-        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) return nullptr; else if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) {
-            return nullptr;
-        }
+        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
         for (auto &e : ss.ev)
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
         ss.device = dev;
