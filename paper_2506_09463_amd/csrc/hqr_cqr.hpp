@@ -38,7 +38,7 @@
 
 namespace hqr {
 
-constexpr int CQR_ROWS = 128;          // rows per workgroup in the Gram kernels
+constexpr int CQR_ROWS = 64;           // rows per workgroup in the Gram kernels
 constexpr double CQR_RATIO = 1e-15;    // smallest accepted pivot^2 / G_kk
 constexpr int LD65 = NB + 1;
 
