@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
 #pragma unroll
             for (int q = 0; q < VPT; ++q) vreg[q] = (ok && vcol[q]) ? vcol[q][gi] : 0.0;
 #pragma unroll
-            for (int q = 0; q < XPT; ++q) xreg[q] = (ok && xcol[q]) ? xcol[q][gi] : 0.0;
+            for (int q = 0; q < XPT; ++q) xreg[q] = (ok && xcol[q]) ? __builtin_nontemporal_load(&xcol[q][gi]) : 0.0;
         }
     };
     if (r_begin < r_end) fetch(r_begin);
@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb + 16 * ti + li;
-                acc[tj][ti][r] = (!F32 && cptr[tj][r] && gi < p.m) ? cptr[tj][r][gi] : 0.0;
+                acc[tj][ti][r] = (!F32 && cptr[tj][r] && gi < p.m) ? __builtin_nontemporal_load(&cptr[tj][r][gi]) : 0.0;
             }
         }
 
@@ -574,8 +574,8 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb + 16 * ti + li;
                 if (cptr[tj][r] && gi < p.m) {
-                    if (F32) cptr[tj][r][gi] = cptr[tj][r][gi] + (double)acc32[tj][ti][r];
-                    else cptr[tj][r][gi] = acc[tj][ti][r];
+                    if (F32) __builtin_nontemporal_store(cptr[tj][r][gi] + (double)acc32[tj][ti][r], &cptr[tj][r][gi]);
+                    else __builtin_nontemporal_store(acc[tj][ti][r], &cptr[tj][r][gi]);
                 }
             }
 #undef HQR_CCOL
