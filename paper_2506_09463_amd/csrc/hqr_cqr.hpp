@@ -63,11 +63,6 @@ HQR_DEV void mm64(double (*out)[LD65], const double (*A)[LD65], const double (*B
         for (int r = 0; r < 4; ++r) out[16 * w + 4 * r + (lane >> 4)][16 * t + (lane & 15)] = acc[t][r];
 }
 
-
-
-
-
-
 // ------------------------------------------- 16 x 16 blocks on MFMA
 // FP64 MFMA 16x16x4 layouts: A[i][k] at lane i + 16k, B[k][j] at lane
 // j + 16k, D[i][j] at lane j + 16 (i % 4), register i / 4.  A product D
@@ -103,103 +98,6 @@ HQR_DEV void st_blk(double (*M)[LD65], int r0, int c0, f64x4 d, double scale, in
     for (int r = 0; r < 4; ++r) M[r0 + 4 * r + (lane >> 4)][c0 + (lane & 15)] = scale * d[r];
 }
 
-// X = U^{-1} for the upper-triangular n x n block of U (identity beyond n;
-// U's entries outside that block must be zero off the diagonal), by the 4
-// waves of the workgroup: wave w inverts diagonal block w (lane j < 16
-// solves for its column), then the blocks above the diagonal follow by their
-// distance from it, X_ij = -X_ii sum_{k=i+1..j} U_ik X_kj, as MFMA products.
-// Starts and ends with a barrier.
-HQR_DEV void inv_upper64_blk(double (*X)[LD65], const double (*U)[LD65], int n, int lane, int w)
-{
-    __syncthreads();
-    {
-        const int b0 = 16 * w, j = lane & 15;
-        double x[16];
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-            const int gi = b0 + i;
-            double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int l = i + 1; l < 16; ++l) s = fma(-U[gi][b0 + l], x[l], s);
-            x[i] = (i > j) ? 0.0 : ((gi < n) ? s / U[gi][gi] : ((i == j) ? 1.0 : 0.0));
-        }
-        if (lane < 16) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) X[b0 + i][b0 + j] = x[i];
-        }
-        for (int idx = lane; idx < 16 * b0; idx += 64) X[b0 + idx / b0][idx % b0] = 0.0;
-    }
-    __syncthreads();
-    if (w < 3) { // distance 1
-        const int i = w, j = w + 1;
-        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, U, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
-        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
-    }
-    __syncthreads();
-    if (w < 2) { // distance 2
-        const int i = w, j = w + 2;
-        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, U, 16 * i, 16 * (i + 1), X, 16 * (i + 1), 16 * j, lane);
-        t = mma_blk(t, U, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
-        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
-    }
-    __syncthreads();
-    if (w == 0) { // distance 3
-        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, U, 0, 16, X, 16, 48, lane);
-        t = mma_blk(t, U, 0, 32, X, 32, 48, lane);
-        t = mma_blk(t, U, 0, 48, X, 48, 48, lane);
-        st_blk(X, 0, 48, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 0, 0, t, lane), -1.0, lane);
-    }
-    __syncthreads();
-}
-
-// X = L^{-1} for the unit lower triangle whose strict lower entries are L's
-// (n x n block; L's entries outside it must be zero), same scheme: diagonal
-// blocks by forward substitution, then X_ij = -X_ii sum_{k=j..i-1} L_ik X_kj.
-// Starts and ends with a barrier.
-HQR_DEV void inv_unit_lower64_blk(double (*X)[LD65], const double (*L)[LD65], int n, int lane, int w)
-{
-    __syncthreads();
-    {
-        const int b0 = 16 * w, j = lane & 15;
-        double x[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int gi = b0 + i;
-            double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int l = 0; l < i; ++l) s = fma(-L[gi][b0 + l], x[l], s);
-            x[i] = (i < j) ? 0.0 : ((i == j) ? 1.0 : ((gi < n && b0 + j < n) ? s : 0.0));
-        }
-        if (lane < 16) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) X[b0 + i][b0 + j] = x[i];
-        }
-        const int c1 = b0 + 16, wid = NB - c1;
-        for (int idx = lane; idx < 16 * wid; idx += 64) X[b0 + idx / wid][c1 + idx % wid] = 0.0;
-    }
-    __syncthreads();
-    if (w < 3) { // distance 1: X_{j+1, j}
-        const int j = w, i = w + 1;
-        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, L, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
-        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
-    }
-    __syncthreads();
-    if (w < 2) { // distance 2: X_{j+2, j}
-        const int j = w, i = w + 2;
-        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, L, 16 * i, 16 * j, X, 16 * j, 16 * j, lane);
-        t = mma_blk(t, L, 16 * i, 16 * (j + 1), X, 16 * (j + 1), 16 * j, lane);
-        st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
-    }
-    __syncthreads();
-    if (w == 0) { // distance 3: X_{3, 0}
-        f64x4 t = mma_blk(f64x4{0.0, 0.0, 0.0, 0.0}, L, 48, 0, X, 0, 0, lane);
-        t = mma_blk(t, L, 48, 16, X, 16, 0, lane);
-        t = mma_blk(t, L, 48, 32, X, 32, 0, lane);
-        st_blk(X, 48, 0, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 48, 48, t, lane), -1.0, lane);
-    }
-    __syncthreads();
-}
-
 // 16 x 16 LDS block in D layout (to accumulate an MFMA update onto it)
 HQR_DEV f64x4 ld_blk(const double (*M)[LD65], int r0, int c0, int lane)
 {
@@ -209,54 +107,154 @@ HQR_DEV f64x4 ld_blk(const double (*M)[LD65], int r0, int c0, int lane)
     return d;
 }
 
-// In-place upper Cholesky G = R^T R of the n x n block of G (R in the upper
-// part, zeros below, identity beyond n; G's entries outside the block must
-// be zero), by 16-column block steps.  In block step kb ONE wave computes
-// rows 16kb .. 16kb+15 of R (lane t owning column 16kb + t, right-looking
-// within the block: the pivot from lane i by readlane, then the rank-1
-// update of the block's remaining rows with the other columns' entries by
-// readlane); then all waves subtract R_p^T R_p from the trailing upper
-// blocks on MFMA.  gdiag gets G's original
-// diagonal, rdiag R's; *bad is set when a pivot^2 falls below ratio * G_kk.
-// Starts and ends with a barrier.
-HQR_DEV void chol64_blk(double (*G)[LD65], int n, int lane, int w, double ratio, double *gdiag, double *rdiag,
-                        int *bad)
+// ------------------------------------------------- in-row broadcasts
+// The value that lane 16r + I holds, in every lane of the 16-lane row r
+// (DPP row_newbcast; one v_mov_b64_dpp for a double).
+template <int I> HQR_DEV double bc16c(double v)
+{
+    const long b = __builtin_bit_cast(long, v);
+    const long r = __builtin_amdgcn_mov_dpp(b, 0x150 + I, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, r);
+}
+
+// Pins v in a register at this point of the program: the compiler may not
+// move its computation past it (used to keep long update chains in order).
+HQR_DEV void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+// i must be a constant once the caller's loops are unrolled
+HQR_DEV double bc16(double v, int i)
+{
+    switch (i) {
+    case 0: return bc16c<0>(v);
+    case 1: return bc16c<1>(v);
+    case 2: return bc16c<2>(v);
+    case 3: return bc16c<3>(v);
+    case 4: return bc16c<4>(v);
+    case 5: return bc16c<5>(v);
+    case 6: return bc16c<6>(v);
+    case 7: return bc16c<7>(v);
+    case 8: return bc16c<8>(v);
+    case 9: return bc16c<9>(v);
+    case 10: return bc16c<10>(v);
+    case 11: return bc16c<11>(v);
+    case 12: return bc16c<12>(v);
+    case 13: return bc16c<13>(v);
+    case 14: return bc16c<14>(v);
+    default: return bc16c<15>(v);
+    }
+}
+
+// s = sqrt(d) and r = 1/sqrt(d): the hardware reciprocal square root refined
+// by two coupled Newton steps (Goldschmidt's iteration for s and 1/(2s)) and
+// a final residual correction of s.  d below 2^-900 is scaled by 2^1000
+// first; d <= 0 (or NaN) gives s = r = 1, the caller flags such pivots.
+HQR_DEV void pivot_sqrt(double d, double &s, double &r)
+{
+    const bool pos = d > 0.0;
+    const bool sc = pos && d < 0x1p-900;
+    const double x = pos ? (sc ? d * 0x1p+1000 : d) : 1.0;
+    const double y = __builtin_amdgcn_rsq(x);
+    double sv = x * y, h = 0.5 * y;
+    double e = fma(-sv, h, 0.5);
+    sv = fma(sv, e, sv);
+    h = fma(h, e, h);
+    e = fma(-sv, h, 0.5);
+    sv = fma(sv, e, sv);
+    h = fma(h, e, h);
+    sv = fma(h, fma(-sv, sv, x), sv);
+    s = sc ? sv * 0x1p-500 : sv;
+    r = sc ? (2.0 * h) * 0x1p+500 : 2.0 * h;
+}
+
+// 1/u from the hardware reciprocal and two Newton steps (|u| >= 1 here).
+HQR_DEV double recip_nr(double u)
+{
+    double y = __builtin_amdgcn_rcp(u);
+    double e = fma(-u, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-u, y, 1.0);
+    return fma(y, e, y);
+}
+
+// In-place upper Cholesky G = R^T R of the n x n leading block of G (R in the
+// upper triangle, zeros below, identity beyond n; G's entries outside the
+// block must be zero), right-looking by 16-column block steps.
+//
+// Block step kb: wave 0 factors block row kb in registers.  Lane t holds
+// column 16kb + t of the block row, and every 16-lane row also holds a copy
+// of the diagonal block (lane 16r + j: its column j), so the entries of the
+// current row of R that a rank-1 update needs are taken from the lane's own
+// row by DPP broadcast.  The same wave then inverts the diagonal block by back
+// substitution into X's diagonal block.  All waves then subtract
+// R_kb^T R_kb from the trailing upper blocks on MFMA.
+//
+// gdiag gets G's diagonal (1 beyond n), rdiag R's; *bad is set when a pivot
+// is not above ratio * G_kk.  Starts and ends with a barrier.
+HQR_DEV void chol64_dpp(double (*G)[LD65], double (*X)[LD65], int n, int lane, int w, double ratio,
+                        double *gdiag, double *rdiag, int *bad)
 {
     const int tid = 64 * w + lane;
     __syncthreads();
-    if (tid < NB) gdiag[tid] = (tid < n) ? G[tid][tid] : 1.0;
+    if (tid < NB) {
+        gdiag[tid] = (tid < n) ? G[tid][tid] : 1.0;
+        if (tid >= n) G[tid][tid] = 1.0;
+    }
     if (tid == 0) *bad = 0;
     __syncthreads();
 #pragma unroll 1
     for (int kb = 0; kb < 4; ++kb) {
         const int b0 = 16 * kb;
         if (w == 0) {
-            // lane t holds column c = b0 + t of the block row; right-looking
-            // within the block, other columns' entries by readlane
-            const int c = b0 + lane;
+            // opaque per block step: keeps the per-pivot lane masks from being
+            // hoisted out of the kb loop (they would occupy ~100 SGPRs)
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int jj = ln & 15, c = b0 + ln;
             const bool act = c < NB;
-            double g[16];
+            double g[16], p[16], acc[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) g[i] = act ? G[b0 + i][c] : 0.0;
+            for (int i = 0; i < 16; ++i) {
+                g[i] = G[b0 + i][b0 + jj];
+                p[i] = act ? G[b0 + i][c] : 0.0;
+                acc[i] = 0.0;
+            }
+            // lane i keeps pivot i and R_ii.  X = R_kk^{-1} is built along:
+            // lane j holds row j of X; acc[l] = sum_{i<l} X[j][i] R[i][l], and
+            // column i of X is -acc[i] / R_ii above the diagonal.
+            double my_d = 1.0, my_s = 0.0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int gi = b0 + i;
-                const double piv = readlane_f64(g[i], i);
-                const double rii = (gi < n) ? sqrt(fmax(piv, 0.0)) : 1.0;
-                if (lane == 0 && gi < n && !(piv > ratio * gdiag[gi])) *bad = 1;
-                double v;
-                if (gi >= n) v = (c == gi) ? 1.0 : 0.0;
-                else if (lane < i) v = 0.0;
-                else if (lane == i) v = rii;
-                else v = (c < n) ? g[i] / rii : 0.0;
+                const double d = bc16(g[i], i);
+                double s, r;
+                pivot_sqrt(d, s, r);
+                const double vg = (jj > i) ? g[i] * r : ((jj == i) ? s : 0.0);
+                const double vp = (c > gi) ? p[i] * r : ((c == gi) ? s : 0.0);
+                const double xi = (jj < i) ? -acc[i] * r : ((jj == i) ? r : 0.0);   // X[j][i]
+                g[i] = vg;
+                p[i] = vp;
+                my_d = (ln == i) ? d : my_d;
+                my_s = (ln == i) ? s : my_s;
+                X[b0 + jj][b0 + i] = xi;   // the four rows store the same value
 #pragma unroll
-                for (int i2 = i + 1; i2 < 16; ++i2) g[i2] = fma(-readlane_f64(v, i2), v, g[i2]);
-                g[i] = v;
+                for (int i2 = i + 1; i2 < 16; ++i2) {
+                    const double t = bc16(vg, i2);          // R[i][i2]
+                    g[i2] = fma(-t, vg, g[i2]);
+                    p[i2] = fma(-t, vp, p[i2]);
+                    acc[i2] = fma(xi, t, acc[i2]);
+                    pin(g[i2]);
+                    pin(p[i2]);
+                    pin(acc[i2]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (act) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) G[b0 + i][c] = g[i];
+                for (int i = 0; i < 16; ++i) G[b0 + i][c] = p[i];
             }
+            const bool badl = lane < 16 && b0 + lane < n && !(my_d > ratio * gdiag[b0 + lane]);
+            if (lane < 16) rdiag[b0 + lane] = my_s;
+            if (badl) *bad = 1;
         }
         __syncthreads();
         // trailing upper blocks (ib <= jb): G_ij -= R_p,i^T R_p,j, R_p = rows b0..b0+15
@@ -284,64 +282,98 @@ HQR_DEV void chol64_blk(double (*G)[LD65], int n, int lane, int w, double ratio,
         const int i = idx / NB, c = idx % NB;
         if (i > c) G[i][c] = 0.0;
     }
-    if (tid < NB) rdiag[tid] = G[tid][tid];
     __syncthreads();
 }
 
-// In place: M (n x n block; entries outside it zero) becomes L (strict
-// lower, unit diagonal implied) and U (upper, diagonal U_kk) of the LU
-// factorization without pivoting of M - S, s_k = -sgn(pivot k) (sgn(0) = +1)
-// chosen at step k; entries outside the block stay zero.  Block steps of 16:
-// ONE wave computes U's block row and L's block column (lane t owning column
-// 16kb + t of U and row 16kb + t of L, right-looking within the block with
-// the other lanes' entries by readlane), then all waves subtract L_p U_p
-// from the trailing blocks on MFMA.  Starts and
-// ends with a barrier.
-HQR_DEV void lu_sign64_blk(double (*M)[LD65], int n, int lane, int w, double *sgn, double *udiag)
+// In place: M (n x n leading block; entries outside it zero) becomes L
+// (strict lower, unit diagonal implied) and U (upper, diagonal U_kk) of the
+// LU factorization without pivoting of M - S, s_k = -sgn(pivot of step k)
+// (sgn(0) = +1); beyond n the factors continue as the identity (s_k = -1,
+// U_kk = 1).  Block step kb: wave 0 computes U's block row and L's block
+// column in registers (lane t: column 16kb + t of U and row 16kb + t of L;
+// every 16-lane row also holds the diagonal block, lane 16r + j its column j
+// and its row j, for DPP broadcasts), then inverts the diagonal blocks of U
+// and L into DU and DL (rows 16kb..16kb+15); all waves then subtract
+// L_kb U_kb from the trailing blocks on MFMA.  sgn and udiag get s_k and U_kk
+// for all 64 steps.  Starts and ends with a barrier.
+HQR_DEV void lu64_dpp(double (*M)[LD65], double (*DU)[17], double (*DL)[17], int lane, int w, double *sgn,
+                      double *udiag)
 {
     __syncthreads();
 #pragma unroll 1
     for (int kb = 0; kb < 4; ++kb) {
         const int b0 = 16 * kb;
         if (w == 0) {
-            // lane t holds column t over the block rows (cv) and row t over the
-            // block columns (rv); the diagonal block is in both copies, which
-            // receive identical updates; other lanes' entries by readlane
-            const int t = b0 + lane;
-            const bool act = t < NB;
-            double cv[16], rv[16];
+            // opaque per block step: keeps the per-pivot lane masks from being
+            // hoisted out of the kb loop (they would occupy ~100 SGPRs)
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int jj = ln & 15, c = b0 + ln;
+            const bool act = c < NB;
+            double cv[16], rv[16], dc[16], dr[16], au[16], al[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                cv[i] = act ? M[b0 + i][t] : 0.0;
-                rv[i] = act ? M[t][b0 + i] : 0.0;
+                cv[i] = act ? M[b0 + i][c] : 0.0;
+                rv[i] = act ? M[c][b0 + i] : 0.0;
+                dc[i] = M[b0 + i][b0 + jj];
+                dr[i] = M[b0 + jj][b0 + i];
+                au[i] = 0.0;
+                al[i] = 0.0;
             }
+            // U_kk^{-1} and L_kk^{-1} are built along: lane j holds row j of
+            // XU = U_kk^{-1} (au[l] = sum_{i<l} XU[j][i] U[i][l]) and column j
+            // of XL = L_kk^{-1} (al[l] = sum_{i<l} L[l][i] XL[i][j]).
+            double my_sg = 0.0, my_uk = 0.0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int gi = b0 + i;
-                const double q = readlane_f64(cv[i], i);
+                const double q = bc16(dc[i], i);
                 const double sg = (q >= 0.0) ? -1.0 : 1.0;
                 const double ukk = q - sg;
-                const double u = (lane > i) ? cv[i] : ((lane == i) ? ukk : 0.0);   // U[gi][t]
-                const double l = (lane > i) ? rv[i] / ukk : 0.0;                   // L[t][gi]
+                const double uinv = recip_nr(ukk);
+                const double ud = (jj > i) ? dc[i] : ((jj == i) ? ukk : 0.0);
+                const double ld = (jj > i) ? dr[i] * uinv : 0.0;
+                const double uc = (c > gi) ? cv[i] : ((c == gi) ? ukk : 0.0);
+                const double lc = (c > gi) ? rv[i] * uinv : 0.0;
+                const double xu = (jj < i) ? -au[i] * uinv : ((jj == i) ? uinv : 0.0);  // XU[j][i]
+                const double xl = (jj < i) ? -al[i] : ((jj == i) ? 1.0 : 0.0);          // XL[i][j]
+                dc[i] = ud;
+                dr[i] = ld;
+                cv[i] = uc;
+                rv[i] = lc;
+                my_sg = (ln == i) ? sg : my_sg;
+                my_uk = (ln == i) ? ukk : my_uk;
+                DU[b0 + jj][i] = xu;       // the four rows store the same values
+                DL[b0 + i][jj] = xl;
 #pragma unroll
                 for (int i2 = i + 1; i2 < 16; ++i2) {
-                    cv[i2] = fma(-readlane_f64(l, i2), u, cv[i2]);
-                    rv[i2] = fma(-l, readlane_f64(u, i2), rv[i2]);
+                    const double lb = bc16(ld, i2), ub = bc16(ud, i2);   // L[i2][i], U[i][i2]
+                    cv[i2] = fma(-lb, uc, cv[i2]);
+                    dc[i2] = fma(-lb, ud, dc[i2]);
+                    rv[i2] = fma(-lc, ub, rv[i2]);
+                    dr[i2] = fma(-ld, ub, dr[i2]);
+                    au[i2] = fma(xu, ub, au[i2]);
+                    al[i2] = fma(lb, xl, al[i2]);
+                    pin(cv[i2]);
+                    pin(dc[i2]);
+                    pin(rv[i2]);
+                    pin(dr[i2]);
+                    pin(au[i2]);
+                    pin(al[i2]);
                 }
-                cv[i] = u;
-                rv[i] = l;
-                if (lane == 0 && gi < n) {
-                    sgn[gi] = sg;
-                    udiag[gi] = ukk;
-                }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            if (act && t < n) {
+            if (act) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const int gi = b0 + i;
-                    if (gi < n && lane >= i) M[gi][t] = cv[i];
-                    if (gi < n && lane > i) M[t][gi] = rv[i];
+                    if (c >= gi) M[gi][c] = cv[i];
+                    if (c > gi) M[c][gi] = rv[i];
                 }
+            }
+            if (lane < 16) {
+                sgn[b0 + lane] = my_sg;
+                udiag[b0 + lane] = my_uk;
             }
         }
         __syncthreads();
@@ -362,31 +394,137 @@ HQR_DEV void lu_sign64_blk(double (*M)[LD65], int n, int lane, int w, double *sg
     }
 }
 
-// out (global, row-major 64 x 64) = (A * B) diag(cs) on columns < bw, zero
-// beyond; A, B in LDS; 256 threads, wave w computes row tile w.
-HQR_DEV void mm64_to_global(double *out, const double (*A)[LD65], const double (*B)[LD65], const double *cs,
-                            int bw, int lane, int w)
+// Off-diagonal blocks of triangular inverses whose diagonal blocks are
+// already in place, by distance from the diagonal on MFMA:
+//   upper U:      X_ij = -X_ii sum_{k=i+1..j} U_ik X_kj   (i < j)
+//   unit lower L: X_ij = -X_ii sum_{k=j..i-1} L_ik X_kj   (i > j)
+// One 16 x 16 block task: t = sum of the products, X_ij = -X_ii t.
+HQR_DEV void inv_upper_task(double (*X)[LD65], const double (*U)[LD65], int i, int j, int lane)
 {
-    f64x4 acc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int k0 = 0; k0 < NB; k0 += 4) {
-        const int kr = k0 + (lane >> 4);
-        const double a = A[16 * w + (lane & 15)][kr];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[kr][16 * t + (lane & 15)], acc[t], 0, 0, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int c = 16 * t + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) out[(16 * w + 4 * r + (lane >> 4)) * NB + c] = (c < bw) ? acc[t][r] * cs[c] : 0.0;
+    f64x4 t = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k = i + 1; k <= j; ++k) t = mma_blk(t, U, 16 * i, 16 * k, X, 16 * k, 16 * j, lane);
+    st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
+}
+
+HQR_DEV void inv_lower_task(double (*X)[LD65], const double (*L)[LD65], int i, int j, int lane)
+{
+    f64x4 t = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k = j; k < i; ++k) t = mma_blk(t, L, 16 * i, 16 * k, X, 16 * k, 16 * j, lane);
+    st_blk(X, 16 * i, 16 * j, mma_blk_reg(f64x4{0.0, 0.0, 0.0, 0.0}, X, 16 * i, 16 * i, t, lane), -1.0, lane);
+}
+
+// zero the blocks of X strictly below (lower = true: above) the diagonal
+HQR_DEV void zero_off_blocks(double (*X)[LD65], bool above, int tid)
+{
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int r = idx / NB, c = idx % NB;
+        if (above ? ((c >> 4) > (r >> 4)) : ((r >> 4) > (c >> 4))) X[r][c] = 0.0;
     }
 }
 
+// X = U^{-1} (64 x 64 upper U) given X's diagonal blocks.  Starts and ends
+// with a barrier.
+HQR_DEV void inv_upper_levels(double (*X)[LD65], const double (*U)[LD65], int lane, int w)
+{
+    __syncthreads();
+    zero_off_blocks(X, false, 64 * w + lane);
+    if (w < 3) inv_upper_task(X, U, w, w + 1, lane);
+    __syncthreads();
+    if (w < 2) inv_upper_task(X, U, w, w + 2, lane);
+    __syncthreads();
+    if (w == 0) inv_upper_task(X, U, 0, 3, lane);
+    __syncthreads();
+}
 
+// XU = U^{-1} and XL = L^{-1} for the U (upper) and L (strict lower, unit
+// diagonal) that share M, given the diagonal blocks of XU and XL.  Starts and
+// ends with a barrier.
+HQR_DEV void inv_lu_levels(double (*XU)[LD65], double (*XL)[LD65], const double (*M)[LD65], int lane, int w)
+{
+    __syncthreads();
+    zero_off_blocks(XU, false, 64 * w + lane);
+    zero_off_blocks(XL, true, 64 * w + lane);
+    for (int task = w; task < 6; task += 4) {
+        if (task < 3) inv_upper_task(XU, M, task, task + 1, lane);
+        else inv_lower_task(XL, M, task - 2, task - 3, lane);
+    }
+    __syncthreads();
+    if (w < 2) inv_upper_task(XU, M, w, w + 2, lane);
+    else inv_lower_task(XL, M, w, w - 2, lane);
+    __syncthreads();
+    if (w == 0) inv_upper_task(XU, M, 0, 3, lane);
+    else if (w == 1) inv_lower_task(XL, M, 3, 0, lane);
+    __syncthreads();
+}
 
+// Products of 64 x 64 operands given by element functions fa(r, c), fb(r, c),
+// into D-layout accumulators (acc[s][q] = C[16 bi + 4q + lane/16][16 bj +
+// lane%16] for the wave's block (bi, bj) of slot s).
+//
+// Upper x upper: the 10 blocks bi <= bj, each summed over k = bi..bj (20
+// block products), spread 5 per wave; uu_slot gives slot s of wave w as
+// 4 bi + bj, or -1.
+HQR_DEV int uu_slot(int w, int s)
+{
+    // w0: (0,3) (3,3)  w1: (0,2) (1,2)  w2: (1,3) (0,1)  w3: (2,3) (0,0) (1,1) (2,2)
+    const unsigned tab = (w == 0) ? 0xffff0f03u : (w == 1) ? 0xffff0602u : (w == 2) ? 0xffff0107u : 0x0a05000bu;
+    const int e = (int)((tab >> (8 * s)) & 0xffu);
+    return e == 0xff ? -1 : e;
+}
+
+template <class FA, class FB>
+HQR_DEV void mm_upper_upper(f64x4 (&acc)[4], FA fa, FB fb, int lane, int w)
+{
+    const int i16 = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const int e = uu_slot(w, s);
+        if (e < 0) continue;
+        const int bi = e >> 2, bj = e & 3;
+        for (int kb = bi; kb <= bj; ++kb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 16 * kb + 4 * q + kk;
+                acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(16 * bi + i16, k), fb(k, 16 * bj + i16), acc[s], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Full x upper: wave w computes block row w, block (w, bj) summed over
+// k = 0..bj (slot s = bj).
+template <class FA, class FB>
+HQR_DEV void mm_full_upper(f64x4 (&acc)[4], FA fa, FB fb, int lane, int w)
+{
+    const int i16 = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb <= s; ++kb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 16 * kb + 4 * q + kk;
+                acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(16 * w + i16, k), fb(k, 16 * s + i16), acc[s], 0, 0, 0);
+            }
+        }
+    }
+}
+
+// Visit the elements of the wave's upper x upper accumulators:
+// f(row, col, value).
+template <class F>
+HQR_DEV void for_uu(const f64x4 (&acc)[4], F f, int lane, int w)
+{
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int e = uu_slot(w, s);
+        if (e < 0) continue;
+        const int bi = e >> 2, bj = e & 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) f(16 * bi + 4 * q + (lane >> 4), 16 * bj + (lane & 15), acc[s][q]);
+    }
+}
 
 // ------------------------------------------------------------ Gram kernel
 struct CqrArgs {
@@ -399,6 +537,7 @@ struct CqrArgs {
     double *gpart;            // [ngroups][NB][NB]
     unsigned long long *mask; // [ngroups] bit k: column k nonzero below its pivot row
     const double *r1inv;      // [NB][NB] row-major (pass 2)
+    double *q1top;            // [NB][NB] (pass 2 out) top bw x bw block of A_p R1^{-1}
     int *flag;                // nonzero: this panel takes the exact path
 };
 
@@ -439,6 +578,11 @@ __global__ void __launch_bounds__(256) cqr_gram_kernel(CqrArgs p)
             mm64(Y, X, Ri, lane, w);
             __syncthreads();
             Z = Y;
+            if (blockIdx.x == 0 && r0 == r_begin)
+                for (int idx = tid; idx < NB * NB; idx += 256) {
+                    const int r = idx / NB, c = idx % NB;
+                    p.q1top[idx] = (r < p.bw && c < p.bw) ? Y[r][c] : 0.0;
+                }
         }
         // acc += Z^T Z : wave w owns output rows [16w, 16w+16)
 #pragma unroll 4
@@ -504,6 +648,7 @@ struct CholArgs {
     const unsigned long long *mask_all; // ORed zero-tail masks (pass 1)
     double *r1;         // [NB][NB]  (pass 1 out, pass 2 in)
     double *r1inv;      // [NB][NB]  (pass 1 out, pass 2 in)
+    const double *q1top; // [NB][NB] (pass 2 in) top bw x bw block of A_p R1^{-1}
     double *winv;       // [NB][NB]  (pass 2 out) R^{-1} U^{-1} diag(up)
     double *T;          // [NB][NB]  (pass 2 out) T for the stored vectors
     double *up;         // global up (pass 2 out)
@@ -512,13 +657,18 @@ struct CholArgs {
 };
 
 // One workgroup, 256 threads.
+//   pass 1: R1 = chol(G), R1^{-1}.
+//   pass 2: R2 = chol(G2), Q_top = Q1_top R2^{-1}, LU of Q_top - S, then
+//           R_house = S R2 R1, up, the stored tails of the top block, T_V
+//           and W^{-1} = R1^{-1} R2^{-1} U^{-1} diag(up).
 __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
 {
     __shared__ double M0[NB][LD65];
     __shared__ double M1[NB][LD65];
     __shared__ double M2[NB][LD65];
     __shared__ double M3[NB][LD65];
-    __shared__ double gdiag[NB], rdiag[NB], sgn[NB], upv[NB], rh[NB];
+    __shared__ double DU[NB][17], DL[NB][17];
+    __shared__ double gdiag[NB], rdiag[NB], sgn[NB], udiag[NB], upv[NB];
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int bw = p.bw;
@@ -530,23 +680,17 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         ++tsi;                                                                   \
     } while (0)
     HQR_TS();
-    // pass 2 reads R1^{-1}, R1 and A's top block late: load them now, so the
-    // loads overlap the Cholesky factorization
-    double pf_r1inv[16], pf_r1[16], pf_at[16];
-    if (p.pass == 2) {
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int idx = tid + 256 * t;
-            const int c = idx / NB, r = idx % NB;
-            pf_r1inv[t] = p.r1inv[idx];
-            pf_r1[t] = p.r1[idx];
-            pf_at[t] = (r < bw && c < bw) ? HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) : 0.0;
-        }
-    }
-
+    // G -> M0; pass 2 also stages Q1_top -> M2 and R1 -> M3 (idle until
+    // after the Cholesky factorization), all loads in flight together
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, j = idx % NB;
-        M0[i][j] = (i < bw && j < bw) ? p.G[idx] : 0.0;
+        const double gv = (i < bw && j < bw) ? p.G[idx] : 0.0;
+        if (p.pass == 2) {
+            const double qv = p.q1top[idx], rv = p.r1[idx];
+            M2[i][j] = qv;
+            M3[i][j] = rv;
+        }
+        M0[i][j] = gv;
     }
     int structural = 0;
     if (p.pass == 1 && tid == 0) {
@@ -554,88 +698,105 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         const unsigned long long need = (bw == 64) ? ~0ull : ((1ull << bw) - 1ull);
         structural = ((all & need) != need);
     }
-    __syncthreads();
     HQR_TS();
-    chol64_blk(M0, bw, lane, w, CQR_RATIO, gdiag, rdiag, &bad);
+    chol64_dpp(M0, M1, bw, lane, w, CQR_RATIO, gdiag, rdiag, &bad);
     HQR_TS();
     if (tid == 0 && (bad || structural)) atomicExch(p.flag, 1);
     __syncthreads();
     if (bad || __hip_atomic_load(p.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    inv_upper_levels(M1, M0, lane, w);                  // M1 = R^{-1} of this pass
+    HQR_TS();
 
     if (p.pass == 1) {
-        for (int idx = tid; idx < NB * NB; idx += 256) p.r1[idx] = M0[idx / NB][idx % NB];
-        inv_upper64_blk(M1, M0, bw, lane, w);
-        for (int idx = tid; idx < NB * NB; idx += 256) p.r1inv[idx] = M1[idx / NB][idx % NB];
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            p.r1[idx] = M0[idx / NB][idx % NB];
+            p.r1inv[idx] = M1[idx / NB][idx % NB];
+        }
         return;
     }
 
-    // ---- pass 2: M0 = R2
+    // ---- pass 2: M0 = R2, M1 = R2^{-1}, M2 = Q1_top, M3 = R1
+    {
+        f64x4 qacc[4];
+        mm_full_upper(qacc, [&](int r, int c) { return M2[r][c]; }, [&](int r, int c) { return M1[r][c]; }, lane, w);
+        __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int idx = tid + 256 * t;
-        M2[idx / NB][idx % NB] = pf_r1inv[t];
+        for (int s = 0; s < 4; ++s) st_blk(M2, 16 * w, 16 * s, qacc[s], 1.0, lane);  // M2 = Q_top
     }
-    inv_upper64_blk(M1, M0, bw, lane, w);                // M1 = R2^{-1}
     HQR_TS();
-    mm64(M3, M2, M1, lane, w);                          // M3 = R^{-1} = R1^{-1} R2^{-1}
-    __syncthreads();
+    // LU of Q_top - S in M2; diagonal blocks of U^{-1} -> DU, of L^{-1} -> DL
+    lu64_dpp(M2, DU, DL, lane, w, sgn, udiag);
+    HQR_TS();
+    // R1^{-1} is needed last: start its loads now
+    double pf_r1inv[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int idx = tid + 256 * t;
-        M2[idx / NB][idx % NB] = pf_r1[t];
-    }
-    __syncthreads();
-    mm64(M1, M0, M2, lane, w);                          // M1 = R = R2 R1
-    __syncthreads();
-    // Q_top = A_top R^{-1}
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int idx = tid + 256 * t;
-        M2[idx % NB][idx / NB] = pf_at[t];
-    }
-    __syncthreads();
-    mm64(M0, M2, M3, lane, w);                          // M0 = Q_top
-    __syncthreads();
-    HQR_TS();
-    // modified LU of Q_top - S (in place in M0)
-    lu_sign64_blk(M0, bw, lane, w, sgn, rdiag);
-    HQR_TS();
-    // R_house = S R: write the upper triangle of the panel's top block
-    for (int idx = tid; idx < bw * bw; idx += 256) {
-        const int c = idx / bw, r = idx % bw;
-        if (r <= c) HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) = sgn[r] * M1[r][c];
+    for (int t = 0; t < 16; ++t) pf_r1inv[t] = p.r1inv[tid + 256 * t];
+    // R = R2 R1; R_house = S R into the upper triangle of the panel's top block
+    {
+        f64x4 racc[4];
+        mm_upper_upper(racc, [&](int r, int c) { return M0[r][c]; }, [&](int r, int c) { return M3[r][c]; }, lane, w);
+        for_uu(racc, [&](int r, int c, double v) {
+            if (r <= c && c < bw) HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) = sgn[r] * v;
+        }, lane, w);
     }
     if (tid < bw) {
-        const double rkk = sgn[tid] * M1[tid][tid];
-        const double tau = -M0[tid][tid] * sgn[tid];      // = 1 + |pivot|
-        rh[tid] = rkk;
+        const double rkk = sgn[tid] * rdiag[tid] * M3[tid][tid];  // diag of S R2 R1
+        const double tau = -udiag[tid] * sgn[tid];                // = 1 + |pivot|
         upv[tid] = -tau * rkk;
     }
     __syncthreads();
-    // U^{-1} and L^{-1} from the LU in M0
-    inv_upper64_blk(M2, M0, bw, lane, w);
-    inv_unit_lower64_blk(M1, M0, bw, lane, w);
+    // diagonal blocks of U^{-1} -> M0, of L^{-1} -> M3; then the rest
+    for (int idx = tid; idx < NB * 16; idx += 256) {
+        const int r = idx >> 4, cc = idx & 15, c = 16 * (r >> 4) + cc;
+        M0[r][c] = DU[r][cc];
+        M3[r][c] = DL[r][cc];
+    }
+    inv_lu_levels(M0, M3, M2, lane, w);                 // M0 = U^{-1}, M3 = L^{-1}
     HQR_TS();
-    // W^{-1} = R^{-1} U^{-1} diag(up), straight to global
-    mm64_to_global(p.winv, M3, M2, upv, bw, lane, w);
+    // T_Y = -(U S) L^{-T}, T_V = T_Y / (up_i up_j) -> global; V1 = R2^{-1} U^{-1}
+    f64x4 vacc[4];
+    {
+        f64x4 tacc[4];
+        mm_upper_upper(tacc, [&](int r, int c) { return (c >= r && c < bw) ? M2[r][c] * sgn[c] : 0.0; },
+                       [&](int r, int c) { return M3[c][r]; }, lane, w);
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const int i = idx / NB, j = idx % NB;
+            if (!(i <= j && j < bw)) p.T[idx] = 0.0;
+        }
+        for_uu(tacc, [&](int r, int c, double v) {
+            if (r <= c && c < bw) p.T[r * NB + c] = -v / (upv[r] * upv[c]);
+        }, lane, w);
+    }
+    mm_upper_upper(vacc, [&](int r, int c) { return M1[r][c]; }, [&](int r, int c) { return M0[r][c]; }, lane, w);
     __syncthreads();
-    // T_Y = -(U S) L^{-T};  T_V = T_Y / (up_i up_j)
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx / NB, l = idx % NB;
-        M2[i][l] = (i <= l && l < bw) ? M0[i][l] * sgn[l] : 0.0; // U S
-        M3[l][i] = M1[i][l];                                     // L^{-T}
+    // M0 = V1 (its blocks below the diagonal are still U^{-1}'s zeros), M1 = R1^{-1}
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int e = uu_slot(w, s);
+        if (e >= 0) st_blk(M0, 16 * (e >> 2), 16 * (e & 3), vacc[s], 1.0, lane);
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int idx = tid + 256 * t;
+        M1[idx / NB][idx % NB] = pf_r1inv[t];
     }
     __syncthreads();
-    mm64(M1, M2, M3, lane, w);
-    __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx / NB, j = idx % NB;
-        p.T[idx] = (i <= j && j < bw) ? -M1[i][j] / (upv[i] * upv[j]) : 0.0;
+    // W^{-1} = R1^{-1} V1 diag(up) -> global (zero beyond bw and below the diagonal)
+    {
+        f64x4 wacc[4];
+        mm_upper_upper(wacc, [&](int r, int c) { return M1[r][c]; }, [&](int r, int c) { return M0[r][c]; }, lane, w);
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const int i = idx / NB, j = idx % NB;
+            if ((i >> 4) > (j >> 4) || j >= bw) p.winv[idx] = 0.0;
+        }
+        for_uu(wacc, [&](int r, int c, double v) {
+            if (c < bw) p.winv[r * NB + c] = v * upv[c];
+        }, lane, w);
     }
     // stored tails of the top block: L[i][j] * up_j (strict lower)
     for (int idx = tid; idx < bw * bw; idx += 256) {
         const int c = idx / bw, r = idx % bw;
-        if (r > c) HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) = M0[r][c] * upv[c];
+        if (r > c) HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) = M2[r][c] * upv[c];
     }
     if (tid < bw) p.up[p.c0 + tid] = upv[tid];
     HQR_TS();

@@ -287,7 +287,7 @@ struct Work {
     double *wpart2, *T2, *wp2;            // second set for the look-ahead stream
     int *flags;
     int *iscratch;
-    double *gpart, *r1, *r1inv, *winv, *G;
+    double *gpart, *r1, *r1inv, *winv, *G, *q1top;
     double *borig, *rvec, *gvec, *mstat_d;   // mixed precision: original B, residual, A^T r, ||dx||
     int *mstat;                              // mixed precision: [first converged step, stagnation, run]
     unsigned long long *mask, *mask_all;
@@ -326,9 +326,11 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *msd = take(sizeof(double) * 64);
     char *ms = take(sizeof(int) * 64);
     char *gg = take(sizeof(double) * NB * NB);
+    char *q1 = take(sizeof(double) * NB * NB);
     char *ma = take(sizeof(unsigned long long));
     if (w) {
         w->G = (double *)gg;
+        w->q1top = (double *)q1;
         w->borig = (double *)bo;
         w->rvec = (double *)rv;
         w->gvec = (double *)gv;
@@ -518,6 +520,7 @@ static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, doub
     g.gpart = w.gpart;
     g.mask = w.mask;
     g.r1inv = w.r1inv;
+    g.q1top = w.q1top;
     g.flag = flag;
     GredArgs gr;
     gr.gpart = w.gpart;
@@ -536,6 +539,7 @@ static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, doub
     c.mask_all = w.mask_all;
     c.r1 = w.r1;
     c.r1inv = w.r1inv;
+    c.q1top = w.q1top;
     c.winv = w.winv;
     c.T = Tout;
     c.up = up;
