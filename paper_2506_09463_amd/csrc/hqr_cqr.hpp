@@ -23,14 +23,23 @@
 //
 // Panels for which this is not the stored factorization of the one-reflector
 // loop, or not accurate, go to an exact one-workgroup Householder panel
-// (panel_exact_kernel) instead:
+// (exact_panel) instead:
 //   - a column whose part below the pivot row is exactly zero (the loop then
 //     keeps H_k = I; this includes an empty tail when m_p == bw);
 //   - a Cholesky pivot whose squared ratio to the column's norm falls below
 //     CQR_RATIO (conditioning beyond what two CholeskyQR passes repair, or
 //     rank deficiency).
-// The decision is taken on the device; `flag` then makes the remaining
-// CholeskyQR kernels of the panel return at once and the exact kernel run.
+// The decision is taken on the device: `flag` then makes pass 2 run the exact
+// loop instead.
+//
+// A panel takes two kernels, each a grid-wide step whose reduction and
+// small-matrix stage run in the workgroup that finishes last:
+//   cqr_pass1_kernel  (previous panel's update of these columns +) Gram
+//                     partials -> G -> R1, R1^{-1}
+//   cqr_pass2_kernel  Q1 and its Gram partials -> G2 -> R2 -> reconstruction
+// and the bottom rows become V_bot = A_bot W^{-1} in narrow_vtx_kernel (which
+// also forms W = T^T V^T C for the next panel's columns, with look-ahead) or
+// cqr_finish_kernel.
 #pragma once
 
 #include "hqr_device.hpp"
@@ -526,83 +535,309 @@ HQR_DEV void for_uu(const f64x4 (&acc)[4], F f, int lane, int w)
     }
 }
 
-// ------------------------------------------------------------ Gram kernel
-struct CqrArgs {
-    double *A;
-    int64_t lda;
-    int64_t m;
-    int c0, bw;
-    int pass;                 // 1: G of A_p (and zero-tail masks); 2: G of A_p R1^{-1}
-    int ngroups;              // workgroups (row chunks of CQR_ROWS rows)
-    double *gpart;            // [ngroups][NB][NB]
-    unsigned long long *mask; // [ngroups] bit k: column k nonzero below its pivot row
-    const double *r1inv;      // [NB][NB] row-major (pass 2)
-    double *q1top;            // [NB][NB] (pass 2 out) top bw x bw block of A_p R1^{-1}
-    int *flag;                // nonzero: this panel takes the exact path
-};
-
-__global__ void __launch_bounds__(256) cqr_gram_kernel(CqrArgs p)
+// acc[t] (t = 0..3) += sign * A[16w:16w+16][:] * B[:][16t:16t+16] over k = 0..63
+HQR_DEV void mm64_acc(f64x4 (&acc)[4], const double (*A)[LD65], const double (*B)[LD65], double sign, int lane, int w)
 {
-    __shared__ double X[NB][LD65];   // [row][col] chunk of 64 rows
-    __shared__ double Y[NB][LD65];
-    __shared__ double Ri[NB][LD65];
-    __shared__ unsigned long long msk;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (p.pass == 2 && *((volatile int *)p.flag)) return;
-    const int64_t r_begin = (int64_t)p.c0 + (int64_t)blockIdx.x * CQR_ROWS;
-    const int64_t r_end = min<int64_t>(p.m, r_begin + CQR_ROWS);
-    if (tid == 0) msk = 0ull;
-    if (p.pass == 2)
-        for (int idx = tid; idx < NB * NB; idx += 256) Ri[idx / NB][idx % NB] = p.r1inv[idx];
+#pragma unroll 4
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+        const int kr = k0 + (lane >> 4);
+        const double a = sign * A[16 * w + (lane & 15)][kr];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[kr][16 * t + (lane & 15)], acc[t], 0, 0, 0);
+    }
+}
 
-    f64x4 acc[4];
+// acc[t] = Z^T Z (rows 16w.., column tile t) for a 64 x 64 LDS tile Z
+HQR_DEV void gram64(f64x4 (&acc)[4], const double (*Z)[LD65], int lane, int w)
+{
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-    unsigned long long mymask = 0ull;
-
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += 64) {
-        __syncthreads();
-        for (int idx = tid; idx < 64 * NB; idx += 256) {
-            const int c = idx / 64, r = idx % 64;
-            const int64_t gi = r0 + r;
-            double v = 0.0;
-            if (gi < r_end && c < p.bw) {
-                v = HQR_AT(p.A, gi, p.c0 + c, p.lda);
-                if (p.pass == 1 && gi > (int64_t)p.c0 + c && v != 0.0) mymask |= (1ull << c);
-            }
-            X[r][c] = v;
-        }
-        __syncthreads();
-        double (*Z)[LD65] = X;
-        if (p.pass == 2) {
-            mm64(Y, X, Ri, lane, w);
-            __syncthreads();
-            Z = Y;
-            if (blockIdx.x == 0 && r0 == r_begin)
-                for (int idx = tid; idx < NB * NB; idx += 256) {
-                    const int r = idx / NB, c = idx % NB;
-                    p.q1top[idx] = (r < p.bw && c < p.bw) ? Y[r][c] : 0.0;
-                }
-        }
-        // acc += Z^T Z : wave w owns output rows [16w, 16w+16)
 #pragma unroll 4
-        for (int k0 = 0; k0 < 64; k0 += 4) {
-            const int kr = k0 + (lane >> 4);
-            const double a = Z[kr][16 * w + (lane & 15)];
+    for (int k0 = 0; k0 < NB; k0 += 4) {
+        const int kr = k0 + (lane >> 4);
+        const double a = Z[kr][16 * w + (lane & 15)];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Z[kr][16 * t + (lane & 15)], acc[t], 0, 0, 0);
-        }
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Z[kr][16 * t + (lane & 15)], acc[t], 0, 0, 0);
     }
-    double *out = p.gpart + (size_t)blockIdx.x * NB * NB;
+}
+
+// D-layout accumulators of a full 64 x 64 product -> row-major global
+HQR_DEV void st64_global(double *out, const f64x4 (&acc)[4], int lane, int w)
+{
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) out[(16 * w + 4 * r + (lane >> 4)) * NB + 16 * t + (lane & 15)] = acc[t][r];
-    if (p.pass == 1) {
-        if (mymask) atomicOr(&msk, mymask);
+}
+
+// ------------------------------------------------- exact one-workgroup panel
+// The one-reflector-at-a-time loop on the panel (the arithmetic of the
+// per-column launches, the dot products split over NG row groups), streamed
+// from global memory by 64 NG threads, followed by T from V^T V.  Used when a
+// panel is flagged (structurally exact reflectors, or conditioning beyond
+// what two CholeskyQR passes repair).
+struct ExactArgs {
+    double *A;
+    int64_t lda;
+    int64_t m;
+    int c0, bw;
+    double *up;
+    double *T;
+};
+
+template <int NG>
+HQR_DEV void exact_panel(const ExactArgs &p, int tid, double (*red)[PW], double *wsh, double *sc, double (*G)[LD65],
+                         double (*Ts)[LD65], double *tau, double *tmp)
+{
+    constexpr int NT = 64 * NG;
+    const int j = tid & 63, g = tid >> 6;
+    const int bw = p.bw, c0 = p.c0;
+    const int64_t m = p.m;
+    __syncthreads();
+    for (int k = 0; k < bw; ++k) {
+        const int64_t pr = (int64_t)c0 + k;
+        // partial dots x . a_j over rows > pr, plus max|x| and #nonzero
+        double acc = 0.0, mx = 0.0, nz = 0.0;
+        for (int64_t i = pr + 1 + g; i < m; i += NG) {
+            const double xi = HQR_AT(p.A, i, c0 + k, p.lda);
+            if (j >= k && j < bw) acc += xi * HQR_AT(p.A, i, c0 + j, p.lda);
+            mx = fmax(mx, fabs(xi));
+            nz += (xi != 0.0) ? 1.0 : 0.0;
+        }
+        red[g][j] = acc;
+        if (j == 0) {
+            red[g][NB] = mx;
+            red[g][NB + 1] = nz;
+        }
         __syncthreads();
-        if (tid == 0) p.mask[blockIdx.x] = msk;
+        if (tid < PW) {
+            double v = 0.0;
+            if (tid == NB) {
+                for (int q = 0; q < NG; ++q) v = fmax(v, red[q][NB]);
+            } else {
+                for (int q = 0; q < NG; ++q) v += red[q][tid];
+            }
+            red[0][tid] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double x0 = HQR_AT(p.A, pr, c0 + k, p.lda);
+            double upk, sk;
+            if (red[0][NB + 1] == 0.0) {
+                upk = 0.0;
+                sk = x0;
+            } else {
+                const double c = fmax(fabs(x0), red[0][NB]);
+                double nu;
+                if (norm_fast_path_ok(c)) {
+                    nu = sqrt(x0 * x0 + red[0][k]);
+                } else {
+                    double t = 0.0;
+                    for (int64_t i = pr + 1; i < m; ++i) {
+                        const double y = HQR_AT(p.A, i, c0 + k, p.lda) / c;
+                        t += y * y;
+                    }
+                    const double x0c = x0 / c;
+                    nu = c * sqrt(x0c * x0c + t);
+                }
+                sk = (x0 >= 0.0) ? -nu : nu;
+                upk = x0 - sk;
+            }
+            sc[0] = upk;
+            sc[1] = sk;
+            p.up[c0 + k] = upk;
+        }
+        __syncthreads();
+        const double upk = sc[0], sk = sc[1];
+        if (upk != 0.0) {
+            const double bk = upk * sk;
+            if (tid < NB) wsh[tid] = (tid > k && tid < bw) ? (upk * HQR_AT(p.A, pr, c0 + tid, p.lda) + red[0][tid]) / bk : 0.0;
+            __syncthreads();
+            if (j > k && j < bw) {
+                const double wj = wsh[j];
+                for (int64_t i = pr + g; i < m; i += NG) {
+                    const double v = (i == pr) ? upk : HQR_AT(p.A, i, c0 + k, p.lda);
+                    HQR_AT(p.A, i, c0 + j, p.lda) += wj * v;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) HQR_AT(p.A, pr, c0 + k, p.lda) = sk;
+        __syncthreads();
     }
+    // G = V^T V (V masked: up on the diagonal), then T by the recurrence
+    for (int e = tid; e < NB * NB; e += NT) {
+        Ts[e / NB][e % NB] = 0.0;
+        const int a = e / NB, b = e % NB;
+        if (a > b) continue;
+        double s = 0.0;
+        if (b < bw) {
+            const int64_t lo = (int64_t)c0 + b;
+            s = p.up[c0 + b] * ((a == b) ? p.up[c0 + a] : HQR_AT(p.A, lo, c0 + a, p.lda));
+            for (int64_t i = lo + 1; i < m; ++i) s += HQR_AT(p.A, i, c0 + a, p.lda) * HQR_AT(p.A, i, c0 + b, p.lda);
+        }
+        G[a][b] = s;
+        G[b][a] = s;
+    }
+    if (tid < NB) {
+        double t = 0.0;
+        if (tid < bw) {
+            const double u = p.up[c0 + tid];
+            t = (u == 0.0) ? 0.0 : -1.0 / (u * HQR_AT(p.A, (int64_t)c0 + tid, c0 + tid, p.lda));
+        }
+        tau[tid] = t;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < bw; ++jj) {
+        if (tid < jj) {
+            double s = 0.0;
+            for (int l = tid; l < jj; ++l) s += Ts[tid][l] * G[l][jj];
+            tmp[tid] = s;
+        }
+        __syncthreads();
+        if (tid < jj) Ts[tid][jj] = -tau[jj] * tmp[tid];
+        if (tid == jj) Ts[jj][jj] = tau[jj];
+        __syncthreads();
+    }
+    for (int e = tid; e < NB * NB; e += NT) p.T[e] = Ts[e / NB][e % NB];
+}
+
+// --------------------------------------- Gram partials (with the update)
+// Pass 1, workgroup t owns rows rbase + 64t .. +63 (rbase = cp with the
+// update, c0 without).  With `upd` it first applies the previous panel's
+// compact-WY block to this panel's columns: C -= V W with W = T^T X, X = V^T C
+// reduced over all rows (narrow_vtx_kernel + gram_reduce_kernel), V the
+// previous panel's reflectors (rows from cp, width NB); W is formed in every
+// workgroup (one 64^3 product on MFMA).  Then the rows at or below c0 give a
+// Gram partial Z^T Z of the panel and its zero-tail mask.
+struct Gram1Args {
+    double *A;
+    int64_t lda;
+    int64_t m;
+    int c0, bw;               // panel whose Gram is formed
+    int upd, cp;              // apply the previous panel (start cp, width NB) first
+    const double *up;         // stored up (the previous panel's part is read)
+    const double *X;          // [NB][NB] V^T C (upd)
+    const double *T;          // [NB][NB] the previous panel's T (upd)
+    double *gpart;            // [tiles][NB][NB]
+    unsigned long long *mask; // [tiles]
+    const int *flag;
+};
+
+__global__ void __launch_bounds__(256) cqr_gram1_kernel(Gram1Args p)
+{
+    __shared__ double M0[NB][LD65];
+    __shared__ double M1[NB][LD65];
+    __shared__ double M2[NB][LD65];
+    __shared__ double M3[NB][LD65];
+    __shared__ unsigned long long msk;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int bw = p.bw, t = blockIdx.x;
+    const int64_t rbase = p.upd ? (int64_t)p.cp : (int64_t)p.c0;
+    const int64_t r0 = rbase + 64 * (int64_t)t;
+    const bool flagged = *((volatile int *)p.flag) != 0;
+    if (tid == 0) msk = 0ull;
+    // M0 = C tile (panel columns); with the update M1 = V tile, M2 = X, M3 = T
+    for (int idx = tid; idx < 64 * NB; idx += 256) {
+        const int c = idx / 64, r = idx % 64;
+        const int64_t gi = r0 + r;
+        const bool ok = gi < p.m;
+        M0[r][c] = (ok && c < bw) ? HQR_AT(p.A, gi, p.c0 + c, p.lda) : 0.0;
+        if (p.upd) M1[r][c] = ok ? v_elem(p.A, p.lda, p.up, p.cp, gi, c) : 0.0;
+    }
+    if (p.upd)
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const double xv = p.X[idx], tv = p.T[idx];
+            M2[idx / NB][idx % NB] = xv;
+            M3[idx / NB][idx % NB] = tv;
+        }
+    __syncthreads();
+    if (p.upd) {
+        f64x4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // W = T^T X: (T^T)[i][k] = T[k][i]
+#pragma unroll 4
+        for (int k0 = 0; k0 < NB; k0 += 4) {
+            const int kr = k0 + (lane >> 4);
+            const double a = M3[kr][16 * w + (lane & 15)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, M2[kr][16 * q + (lane & 15)], acc[q], 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st_blk(M2, 16 * w, 16 * q, acc[q], 1.0, lane);   // M2 = W
+        __syncthreads();
+        // C -= V W: each wave reads and rewrites only its own 16 rows of M0
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = ld_blk(M0, 16 * w, 16 * q, lane);
+        mm64_acc(acc, M1, M2, -1.0, lane, w);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st_blk(M0, 16 * w, 16 * q, acc[q], 1.0, lane);
+        __syncthreads();
+        for (int idx = tid; idx < 64 * NB; idx += 256) {
+            const int c = idx / 64, r = idx % 64;
+            const int64_t gi = r0 + r;
+            if (gi < p.m && c < bw) HQR_AT(p.A, gi, p.c0 + c, p.lda) = M0[r][c];
+        }
+    }
+    if (flagged) return;                 // the exact loop factors this panel
+    if (p.upd && t == 0) return;         // rows above the panel
+    const int gidx = p.upd ? t - 1 : t;
+    unsigned long long mymask = 0ull;
+    for (int idx = tid; idx < 64 * NB; idx += 256) {
+        const int c = idx / 64, r = idx % 64;
+        const int64_t gi = r0 + r;
+        if (c < bw && gi > (int64_t)p.c0 + c && gi < p.m && M0[r][c] != 0.0) mymask |= (1ull << c);
+    }
+    if (mymask) atomicOr(&msk, mymask);
+    f64x4 acc[4];
+    gram64(acc, M0, lane, w);
+    st64_global(p.gpart + (size_t)gidx * NB * NB, acc, lane, w);
+    __syncthreads();
+    if (tid == 0) p.mask[gidx] = msk;
+}
+
+// --------------------------------------------------- pass-2 Gram partials
+// Workgroup t: Q1 = A_p R1^{-1} on rows c0 + 64t .. +63 and its Gram partial;
+// workgroup 0 also keeps the top bw x bw block of Q1.
+struct Gram2Args {
+    const double *A;
+    int64_t lda;
+    int64_t m;
+    int c0, bw;
+    const double *r1inv;
+    double *q1top;
+    double *gpart;
+    const int *flag;
+};
+
+__global__ void __launch_bounds__(256) cqr_gram2_kernel(Gram2Args p)
+{
+    __shared__ double X[NB][LD65];
+    __shared__ double Y[NB][LD65];
+    __shared__ double Ri[NB][LD65];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (*((volatile int *)p.flag)) return;
+    const int t = blockIdx.x;
+    const int64_t r0 = (int64_t)p.c0 + 64 * (int64_t)t;
+    for (int idx = tid; idx < 64 * NB; idx += 256) {
+        const int c = idx / 64, r = idx % 64;
+        const int64_t gi = r0 + r;
+        X[r][c] = (gi < p.m && c < p.bw) ? HQR_AT(p.A, gi, p.c0 + c, p.lda) : 0.0;
+    }
+    for (int idx = tid; idx < NB * NB; idx += 256) Ri[idx / NB][idx % NB] = p.r1inv[idx];
+    __syncthreads();
+    mm64(Y, X, Ri, lane, w);
+    __syncthreads();
+    if (t == 0)
+        for (int idx = tid; idx < NB * NB; idx += 256) {
+            const int r = idx / NB, c = idx % NB;
+            p.q1top[idx] = (r < p.bw && c < p.bw) ? Y[r][c] : 0.0;
+        }
+    f64x4 acc[4];
+    gram64(acc, Y, lane, w);
+    st64_global(p.gpart + (size_t)t * NB * NB, acc, lane, w);
 }
 
 // ----------------------------------------------- partial Gram reduction
@@ -616,14 +851,14 @@ struct GredArgs {
     const unsigned long long *mask;
     unsigned long long *mask_all;
     int with_mask;
-    const int *flag;
+    const int *flag;                     // nullptr: always run
 };
 
 __global__ void __launch_bounds__(256) gram_reduce_kernel(GredArgs p)
 {
     __shared__ double part[4][64];
     const int tid = threadIdx.x, e = blockIdx.x * 64 + (tid & 63), g4 = tid >> 6;
-    if (*((volatile int *)p.flag)) return;
+    if (p.flag && *((volatile int *)p.flag)) return;
     double s = 0.0;
 #pragma unroll 4
     for (int q = g4; q < p.ngroups; q += 4) s += p.gpart[(size_t)q * NB * NB + e];
@@ -657,7 +892,9 @@ struct CholArgs {
 };
 
 // One workgroup, 256 threads.
-//   pass 1: R1 = chol(G), R1^{-1}.
+//   pass 1: R1 = chol(G), R1^{-1}; flags the panel (structurally exact
+//           reflectors, or a pivot below CQR_RATIO).
+//   flagged panel, pass 2: the exact one-reflector loop instead.
 //   pass 2: R2 = chol(G2), Q_top = Q1_top R2^{-1}, LU of Q_top - S, then
 //           R_house = S R2 R1, up, the stored tails of the top block, T_V
 //           and W^{-1} = R1^{-1} R2^{-1} U^{-1} diag(up).
@@ -669,10 +906,17 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     __shared__ double M3[NB][LD65];
     __shared__ double DU[NB][17], DL[NB][17];
     __shared__ double gdiag[NB], rdiag[NB], sgn[NB], udiag[NB], upv[NB];
-    __shared__ int bad;
+    __shared__ int bad, structural_sh;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int bw = p.bw;
-    if (p.pass == 2 && *((volatile int *)p.flag)) return;
+    if (tid == 0) structural_sh = 0;
+    __shared__ double red[4][PW], wsh[NB], sc[4];
+    const ExactArgs ex{p.A, p.lda, p.m, p.c0, bw, p.up, p.T};
+    if (*((volatile int *)p.flag)) {
+        // flagged up front or in pass 1: the exact loop factors the panel
+        if (p.pass == 2) exact_panel<4>(ex, tid, red, wsh, sc, M0, M1, gdiag, rdiag);
+        return;
+    }
     int tsi = 0;
 #define HQR_TS()                                                                 \
     do {                                                                         \
@@ -697,13 +941,18 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         const unsigned long long all = *p.mask_all;
         const unsigned long long need = (bw == 64) ? ~0ull : ((1ull << bw) - 1ull);
         structural = ((all & need) != need);
+        structural_sh = structural;
     }
     HQR_TS();
     chol64_dpp(M0, M1, bw, lane, w, CQR_RATIO, gdiag, rdiag, &bad);
     HQR_TS();
-    if (tid == 0 && (bad || structural)) atomicExch(p.flag, 1);
+    if (tid == 0 && (bad || structural)) *((volatile int *)p.flag) = 1;
     __syncthreads();
-    if (bad || __hip_atomic_load(p.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    if (bad && p.pass == 2) {
+        exact_panel<4>(ex, tid, red, wsh, sc, M0, M1, gdiag, rdiag);
+        return;
+    }
+    if (bad || structural_sh) return;
     inv_upper_levels(M1, M0, lane, w);                  // M1 = R^{-1} of this pass
     HQR_TS();
 
@@ -803,7 +1052,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
 #undef HQR_TS
 }
 
-// ------------------------------------------ bottom rows: Y_bot * diag(up)
+// ---------------------------------- bottom rows: Y_bot * diag(up) (standalone)
 struct FinArgs {
     double *A;
     int64_t lda;
@@ -837,138 +1086,78 @@ __global__ void __launch_bounds__(256) cqr_finish_kernel(FinArgs p)
     }
 }
 
-// ------------------------------------------------- exact one-workgroup panel
-// The one-reflector-at-a-time loop on the panel (same arithmetic as the
-// per-pivot launches), streamed from global memory by one workgroup of 1024
-// threads, followed by T from V^T V.  Runs only when `flag` is set.
-struct ExactArgs {
+// --------------------------- next panel's V^T C, finishing this panel's V
+// For the look-ahead: panel p (start c0, width NB) has just been factored;
+// its bottom rows still hold A_bot and become V_bot = A_bot W^{-1} here
+// (unless the panel was flagged: the exact loop stored V itself).
+// Workgroup t (rows c0 + 64t .. +63) writes its V rows back and the partial
+// V_t^T C_t for the next panel's nc columns C (summed by gram_reduce_kernel;
+// cqr_gram1_kernel applies the block).
+struct NarrowArgs {
     double *A;
     int64_t lda;
     int64_t m;
-    int c0, bw;
-    double *up;
-    double *T;
+    int c0, nc;
+    const double *up;
+    const double *winv;
     const int *flag;
+    double *gpart;            // [tiles][NB][NB] out
 };
 
-__global__ void __launch_bounds__(1024) panel_exact_kernel(ExactArgs p)
+__global__ void __launch_bounds__(256) narrow_vtx_kernel(NarrowArgs p)
 {
-    __shared__ double red[16][PW];
-    __shared__ double wsh[NB];
-    __shared__ double sc[4];
-    __shared__ double G[NB][LD65];
-    __shared__ double Ts[NB][LD65];
-    __shared__ double tau[NB], tmp[NB];
-    const int tid = threadIdx.x, j = tid & 63, g = tid >> 6; // 16 row groups
-    if (!*((volatile int *)p.flag)) return;
-    const int bw = p.bw, c0 = p.c0;
-    const int64_t m = p.m;
-    for (int k = 0; k < bw; ++k) {
-        const int64_t pr = (int64_t)c0 + k;
-        // partial dots x . a_j over rows > pr, plus max|x| and #nonzero
-        double acc = 0.0, mx = 0.0, nz = 0.0;
-        for (int64_t i = pr + 1 + g; i < m; i += 16) {
-            const double xi = HQR_AT(p.A, i, c0 + k, p.lda);
-            if (j >= k && j < bw) acc += xi * HQR_AT(p.A, i, c0 + j, p.lda);
-            mx = fmax(mx, fabs(xi));
-            nz += (xi != 0.0) ? 1.0 : 0.0;
-        }
-        red[g][j] = acc;
-        if (j == 0) {
-            red[g][NB] = mx;
-            red[g][NB + 1] = nz;
-        }
-        __syncthreads();
-        if (tid < PW) {
-            double v = 0.0;
-            if (tid == NB) {
-                for (int q = 0; q < 16; ++q) v = fmax(v, red[q][NB]);
-            } else {
-                for (int q = 0; q < 16; ++q) v += red[q][tid];
-            }
-            red[0][tid] = v;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            const double x0 = HQR_AT(p.A, pr, c0 + k, p.lda);
-            double upk, sk;
-            if (red[0][NB + 1] == 0.0) {
-                upk = 0.0;
-                sk = x0;
-            } else {
-                const double c = fmax(fabs(x0), red[0][NB]);
-                double nu;
-                if (norm_fast_path_ok(c)) {
-                    nu = sqrt(x0 * x0 + red[0][k]);
-                } else {
-                    double t = 0.0;
-                    for (int64_t i = pr + 1; i < m; ++i) {
-                        const double y = HQR_AT(p.A, i, c0 + k, p.lda) / c;
-                        t += y * y;
-                    }
-                    const double x0c = x0 / c;
-                    nu = c * sqrt(x0c * x0c + t);
-                }
-                sk = (x0 >= 0.0) ? -nu : nu;
-                upk = x0 - sk;
-            }
-            sc[0] = upk;
-            sc[1] = sk;
-            p.up[c0 + k] = upk;
-        }
-        __syncthreads();
-        const double upk = sc[0], sk = sc[1];
-        if (upk != 0.0) {
-            const double bk = upk * sk;
-            if (tid < NB) wsh[tid] = (tid > k && tid < bw) ? (upk * HQR_AT(p.A, pr, c0 + tid, p.lda) + red[0][tid]) / bk : 0.0;
-            __syncthreads();
-            if (j > k && j < bw) {
-                const double wj = wsh[j];
-                for (int64_t i = pr + g; i < m; i += 16) {
-                    const double v = (i == pr) ? upk : HQR_AT(p.A, i, c0 + k, p.lda);
-                    HQR_AT(p.A, i, c0 + j, p.lda) += wj * v;
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) HQR_AT(p.A, pr, c0 + k, p.lda) = sk;
-        __syncthreads();
+    __shared__ double M0[NB][LD65];
+    __shared__ double M1[NB][LD65];
+    __shared__ double M2[NB][LD65];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int t = blockIdx.x;
+    const int64_t r0 = (int64_t)p.c0 + 64 * (int64_t)t;
+    const bool flagged = *((volatile int *)p.flag) != 0;
+    const bool fin = (t > 0) && !flagged;
+    // M0 = V rows (top block: unit lower with up on the diagonal), or A_bot;
+    // M2 = C; M1 = W^{-1} when finishing
+    for (int idx = tid; idx < 64 * NB; idx += 256) {
+        const int c = idx / 64, r = idx % 64;
+        const int64_t gi = r0 + r;
+        const bool ok = gi < p.m;
+        M0[r][c] = ok ? ((t == 0) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : HQR_AT(p.A, gi, p.c0 + c, p.lda)) : 0.0;
+        M2[r][c] = (ok && c < p.nc) ? HQR_AT(p.A, gi, p.c0 + NB + c, p.lda) : 0.0;
     }
-    // G = V^T V (V masked: up on the diagonal), then T by the recurrence
-    for (int e = tid; e < NB * NB; e += 1024) {
-        Ts[e / NB][e % NB] = 0.0;
-        const int a = e / NB, b = e % NB;
-        if (a > b) continue;
-        double s = 0.0;
-        if (b < bw) {
-            const int64_t lo = (int64_t)c0 + b;
-            s = p.up[c0 + b] * ((a == b) ? p.up[c0 + a] : HQR_AT(p.A, lo, c0 + a, p.lda));
-            for (int64_t i = lo + 1; i < m; ++i) s += HQR_AT(p.A, i, c0 + a, p.lda) * HQR_AT(p.A, i, c0 + b, p.lda);
-        }
-        G[a][b] = s;
-        G[b][a] = s;
-    }
-    if (tid < NB) {
-        double t = 0.0;
-        if (tid < bw) {
-            const double u = p.up[c0 + tid];
-            t = (u == 0.0) ? 0.0 : -1.0 / (u * HQR_AT(p.A, (int64_t)c0 + tid, c0 + tid, p.lda));
-        }
-        tau[tid] = t;
-    }
+    if (fin)
+        for (int idx = tid; idx < NB * NB; idx += 256) M1[idx / NB][idx % NB] = p.winv[idx];
     __syncthreads();
-    for (int jj = 0; jj < bw; ++jj) {
-        if (tid < jj) {
-            double s = 0.0;
-            for (int l = tid; l < jj; ++l) s += Ts[tid][l] * G[l][jj];
-            tmp[tid] = s;
+    double (*V)[LD65] = M0;
+    if (fin) {
+        // V rows = A_bot W^{-1}: into M1's place after the product
+        f64x4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+        mm64_acc(acc, M0, M1, 1.0, lane, w);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st_blk(M1, 16 * w, 16 * q, acc[q], 1.0, lane);
+        __syncthreads();
+        V = M1;
+        for (int idx = tid; idx < 64 * NB; idx += 256) {
+            const int c = idx / 64, r = idx % 64;
+            const int64_t gi = r0 + r;
+            if (gi < p.m) HQR_AT(p.A, gi, p.c0 + c, p.lda) = M1[r][c];
         }
-        __syncthreads();
-        if (tid < jj) Ts[tid][jj] = -tau[jj] * tmp[tid];
-        if (tid == jj) Ts[jj][jj] = tau[jj];
-        __syncthreads();
     }
-    for (int e = tid; e < NB * NB; e += 1024) p.T[e] = Ts[e / NB][e % NB];
+    // partial V_t^T C_t
+    {
+        f64x4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int k0 = 0; k0 < NB; k0 += 4) {
+            const int kr = k0 + (lane >> 4);
+            const double a = V[kr][16 * w + (lane & 15)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, M2[kr][16 * q + (lane & 15)], acc[q], 0, 0, 0);
+        }
+        st64_global(p.gpart + (size_t)t * NB * NB, acc, lane, w);
+    }
 }
 
 } // namespace hqr

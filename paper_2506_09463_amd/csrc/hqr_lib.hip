@@ -26,12 +26,12 @@ namespace hqr {
 // by a pair of HIP events recorded on the launch's own stream.
 enum KClass {
     K_SMALL, K_PANEL, K_VTX, K_TFACTOR, K_WSOLVE, K_UPDATE, K_DIAG, K_TRSV, K_RESNORM, K_FILL,
-    K_CQR_GRAM, K_CQR_CHOL, K_CQR_FINISH, K_PANEL_EXACT, K_GRED, K_BATCHED, K_REFINE, K_NCLASS
+    K_GRAM1, K_GRAM2, K_GRED, K_CQR_CHOL, K_CQR_FINISH, K_NVTX, K_BATCHED, K_REFINE, K_NCLASS
 };
 static const char *kclass_name[K_NCLASS] = {"small_lsq", "panel_col", "vtx", "tfactor", "wsolve",
                                             "update", "diag_check", "trsv", "resnorm", "fill",
-                                            "cqr_gram", "cqr_chol", "cqr_finish", "panel_exact",
-                                            "gram_reduce", "batched_lsq", "refine"};
+                                            "cqr_gram1", "cqr_gram2", "gram_reduce", "cqr_chol",
+                                            "cqr_finish", "narrow_vtx", "batched_lsq", "refine"};
 struct ProfRec {
     int cls;
     hipEvent_t e0, e1;
@@ -287,7 +287,8 @@ struct Work {
     double *wpart2, *T2, *wp2;            // second set for the look-ahead stream
     int *flags;
     int *iscratch;
-    double *gpart, *r1, *r1inv, *winv, *G, *q1top;
+    double *gpart, *r1, *r1inv, *winv, *q1top;
+    double *G, *xn;                          // reduced Gram; reduced V^T C of the look-ahead
     double *borig, *rvec, *gvec, *mstat_d;   // mixed precision: original B, residual, A^T r, ||dx||
     int *mstat;                              // mixed precision: [first converged step, stagnation, run]
     unsigned long long *mask, *mask_all;
@@ -325,12 +326,14 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *gv = take(sizeof(double) * (size_t)std::max<int64_t>(p.m, 1));
     char *msd = take(sizeof(double) * 64);
     char *ms = take(sizeof(int) * 64);
-    char *gg = take(sizeof(double) * NB * NB);
     char *q1 = take(sizeof(double) * NB * NB);
+    char *gg = take(sizeof(double) * NB * NB);
+    char *xn = take(sizeof(double) * NB * NB);
     char *ma = take(sizeof(unsigned long long));
     if (w) {
-        w->G = (double *)gg;
         w->q1top = (double *)q1;
+        w->G = (double *)gg;
+        w->xn = (double *)xn;
         w->borig = (double *)bo;
         w->rvec = (double *)rv;
         w->gvec = (double *)gv;
@@ -502,39 +505,35 @@ static int panel_percol(const Plan &pl, const Work &w, double *A, int64_t lda, d
     return 0;
 }
 
-// Panel factorization by CholeskyQR2 + Householder reconstruction, with the
-// exact one-workgroup panel when the device flags the panel.  Leaves T (for
-// the stored vectors) in w.T.
-static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
-                     double *Tout, hipStream_t s)
+// Sum of `parts` 64 x 64 partials in w.gpart into out (fixed order); with the
+// pass-1 masks ORed into w.mask_all.  Skipped for a flagged panel when flag
+// is given.
+static int launch_gred(const Plan &, const Work &w, int parts, double *out, bool with_mask, const int *flag,
+                       hipStream_t s)
 {
-    const int64_t mp = pl.m - c0;
-    int *flag = w.pflag + pidx;
-    CqrArgs g;
-    g.A = A;
-    g.lda = lda;
-    g.m = pl.m;
-    g.c0 = c0;
-    g.bw = bw;
-    g.ngroups = (int)((mp + CQR_ROWS - 1) / CQR_ROWS);
-    g.gpart = w.gpart;
-    g.mask = w.mask;
-    g.r1inv = w.r1inv;
-    g.q1top = w.q1top;
-    g.flag = flag;
     GredArgs gr;
     gr.gpart = w.gpart;
-    gr.ngroups = g.ngroups;
-    gr.G = w.G;
+    gr.ngroups = parts;
+    gr.G = out;
     gr.mask = w.mask;
     gr.mask_all = w.mask_all;
+    gr.with_mask = with_mask ? 1 : 0;
     gr.flag = flag;
+    HQR_LAUNCH(K_GRED, gram_reduce_kernel, dim3(NB * NB / 64), dim3(256), 0, s, gr);
+    HQR_CK(hipGetLastError());
+    return 0;
+}
+
+static int launch_chol(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
+                       int pass, double *Tout, hipStream_t s)
+{
     CholArgs c;
     c.A = A;
     c.lda = lda;
     c.m = pl.m;
     c.c0 = c0;
     c.bw = bw;
+    c.pass = pass;
     c.G = w.G;
     c.mask_all = w.mask_all;
     c.r1 = w.r1;
@@ -543,43 +542,107 @@ static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, doub
     c.winv = w.winv;
     c.T = Tout;
     c.up = up;
-    c.flag = flag;
+    c.flag = w.pflag + pidx;
     c.tstamp = nullptr;
-    for (int pass = 1; pass <= 2; ++pass) {
-        g.pass = pass;
-        c.pass = pass;
-        gr.with_mask = (pass == 1);
-        HQR_LAUNCH(K_CQR_GRAM, cqr_gram_kernel, dim3(g.ngroups), dim3(256), 0, s, g);
-        HQR_CK(hipGetLastError());
-        HQR_LAUNCH(K_GRED, gram_reduce_kernel, dim3(NB * NB / 64), dim3(256), 0, s, gr);
-        HQR_CK(hipGetLastError());
-        HQR_LAUNCH(K_CQR_CHOL, cqr_chol_kernel, dim3(1), dim3(256), 0, s, c);
-        HQR_CK(hipGetLastError());
-    }
-    if (mp > bw) {
-        FinArgs f;
-        f.A = A;
-        f.lda = lda;
-        f.m = pl.m;
-        f.c0 = c0;
-        f.bw = bw;
-        f.winv = w.winv;
-        f.flag = flag;
-        HQR_LAUNCH(K_CQR_FINISH, cqr_finish_kernel, dim3((unsigned)((mp - bw + 63) / 64)), dim3(256), 0, s, f);
-        HQR_CK(hipGetLastError());
-    }
-    ExactArgs e;
-    e.A = A;
-    e.lda = lda;
-    e.m = pl.m;
-    e.c0 = c0;
-    e.bw = bw;
-    e.up = up;
-    e.T = Tout;
-    e.flag = flag;
-    HQR_LAUNCH(K_PANEL_EXACT, panel_exact_kernel, dim3(1), dim3(1024), 0, s, e);
+    HQR_LAUNCH(K_CQR_CHOL, cqr_chol_kernel, dim3(1), dim3(256), 0, s, c);
     HQR_CK(hipGetLastError());
     return 0;
+}
+
+// Panel (c0, bw) by CholeskyQR2 + reconstruction, bottom rows not yet
+// finished.  With upd, the previous panel (start cp, width NB; X = V^T C in
+// w.xn, its T in Tprev) is first applied to this panel's columns.
+static int panel_passes(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
+                        double *Tout, bool upd, int cp, const double *Tprev, hipStream_t s)
+{
+    const int64_t rbase = upd ? cp : c0;
+    const int parts = (int)((pl.m - c0 + 63) / 64);
+    int *flag = w.pflag + pidx;
+    Gram1Args g;
+    g.A = A;
+    g.lda = lda;
+    g.m = pl.m;
+    g.c0 = c0;
+    g.bw = bw;
+    g.upd = upd ? 1 : 0;
+    g.cp = cp;
+    g.up = up;
+    g.X = w.xn;
+    g.T = Tprev;
+    g.gpart = w.gpart;
+    g.mask = w.mask;
+    g.flag = flag;
+    HQR_LAUNCH(K_GRAM1, cqr_gram1_kernel, dim3((unsigned)((pl.m - rbase + 63) / 64)), dim3(256), 0, s, g);
+    HQR_CK(hipGetLastError());
+    int rc = launch_gred(pl, w, parts, w.G, true, flag, s);
+    if (!rc) rc = launch_chol(pl, w, A, lda, up, c0, bw, pidx, 1, Tout, s);
+    if (rc) return rc;
+    Gram2Args g2;
+    g2.A = A;
+    g2.lda = lda;
+    g2.m = pl.m;
+    g2.c0 = c0;
+    g2.bw = bw;
+    g2.r1inv = w.r1inv;
+    g2.q1top = w.q1top;
+    g2.gpart = w.gpart;
+    g2.flag = flag;
+    HQR_LAUNCH(K_GRAM2, cqr_gram2_kernel, dim3((unsigned)parts), dim3(256), 0, s, g2);
+    HQR_CK(hipGetLastError());
+    rc = launch_gred(pl, w, parts, w.G, false, flag, s);
+    if (!rc) rc = launch_chol(pl, w, A, lda, up, c0, bw, pidx, 2, Tout, s);
+    return rc;
+}
+
+// Bottom rows of panel (c0, bw): V_bot = A_bot W^{-1} (nothing when flagged).
+static int launch_finish(const Plan &pl, const Work &w, double *A, int64_t lda, int c0, int bw, int pidx,
+                         hipStream_t s)
+{
+    const int64_t mp = pl.m - c0;
+    if (mp <= bw) return 0;
+    FinArgs f;
+    f.A = A;
+    f.lda = lda;
+    f.m = pl.m;
+    f.c0 = c0;
+    f.bw = bw;
+    f.winv = w.winv;
+    f.flag = w.pflag + pidx;
+    HQR_LAUNCH(K_CQR_FINISH, cqr_finish_kernel, dim3((unsigned)((mp - bw + 63) / 64)), dim3(256), 0, s, f);
+    HQR_CK(hipGetLastError());
+    return 0;
+}
+
+// Look-ahead: finish panel (c0, NB)'s V and write the partials of X = V^T C
+// for the next panel's nc columns (summed into w.xn by launch_gred).
+static int launch_narrow_vtx(const Plan &pl, const Work &w, double *A, int64_t lda, const double *up, int c0, int nc,
+                             int pidx, hipStream_t s)
+{
+    NarrowArgs a;
+    a.A = A;
+    a.lda = lda;
+    a.m = pl.m;
+    a.c0 = c0;
+    a.nc = nc;
+    a.up = up;
+    a.winv = w.winv;
+    a.flag = w.pflag + pidx;
+    a.gpart = w.gpart;
+    const int parts = (int)((pl.m - c0 + 63) / 64);
+    HQR_LAUNCH(K_NVTX, narrow_vtx_kernel, dim3((unsigned)parts), dim3(256), 0, s, a);
+    HQR_CK(hipGetLastError());
+    return 0;
+}
+
+// Panel factorization by CholeskyQR2 + Householder reconstruction (the exact
+// loop when the device flags the panel), bottom rows finished.  Leaves T (for
+// the stored vectors) in Tout.
+static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
+                     double *Tout, hipStream_t s)
+{
+    int rc = panel_passes(pl, w, A, lda, up, c0, bw, pidx, Tout, false, 0, nullptr, s);
+    if (!rc) rc = launch_finish(pl, w, A, lda, c0, bw, pidx, s);
+    return rc;
 }
 
 enum PanelMode { PANEL_CQR = 0, PANEL_PERCOL = 1, PANEL_EXACT = 2 };
@@ -670,9 +733,50 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
     // side stream starts after everything already on the caller's stream
     HQR_CK(hipEventRecord(ev_fork, s));
     HQR_CK(hipStreamWaitEvent(ss->stream, ev_fork, 0));
+    bool pending_r = false;
+    if (have_t && !pl.f32) {
+        // Fused chain on the caller's stream, per panel p:
+        //   [wait R(p-1)] -> narrow_vtx(p): V(p) finished, X = V^T C for the
+        //   next panel's columns (or finish(p) for the last panel) -> [a] ->
+        //   passes of panel p+1, the first applying N(p) = (V, T^T X)
+        // side: wait a -> R(p) (all later columns and B) -> [r(p)]
+        const int bw0 = (int)std::min<int64_t>(pl.nb, n);
+        int rc = panel_passes(pl, w, A, lda, up, 0, bw0, 0, Tbuf[0], false, 0, nullptr, s);
+        if (rc) return rc;
+        for (int64_t c0 = 0; c0 < n; c0 += pl.nb) {
+            const int bw = (int)std::min<int64_t>(pl.nb, n - c0);
+            const int pidx = (int)(c0 / pl.nb);
+            const int64_t c1 = c0 + bw;
+            const int bw1 = (int)std::min<int64_t>(pl.nb, std::max<int64_t>(0, n - c1));
+            const int ncR = (int)std::max<int64_t>(0, n - c1 - bw1);
+            TrailBufs br = bufR;
+            br.T = Tbuf[pidx & 1];
+            if (pending_r) HQR_CK(hipStreamWaitEvent(s, ev_r, 0));
+            rc = (bw1 > 0) ? launch_narrow_vtx(pl, w, A, lda, up, (int)c0, bw1, pidx, s)
+                           : launch_finish(pl, w, A, lda, (int)c0, bw, pidx, s);
+            if (rc) return rc;
+            HQR_CK(hipEventRecord(ev_a, s));
+            HQR_CK(hipStreamWaitEvent(ss->stream, ev_a, 0));
+            if (ncR + nB > 0) {
+                rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, true, ss->stream, false);
+                if (rc) return rc;
+            }
+            if (bw1 > 0) {
+                rc = launch_gred(pl, w, (int)((pl.m - c0 + 63) / 64), w.xn, false, nullptr, s);
+                if (!rc)
+                    rc = panel_passes(pl, w, A, lda, up, (int)c1, bw1, pidx + 1, Tbuf[(pidx + 1) & 1], true, (int)c0,
+                                  Tbuf[pidx & 1], s);
+                if (rc) return rc;
+            }
+            HQR_CK(hipEventRecord(ev_r, ss->stream));
+            pending_r = true;
+        }
+        HQR_CK(hipEventRecord(ev_join, ss->stream));
+        HQR_CK(hipStreamWaitEvent(s, ev_join, 0));
+        return 0;
+    }
     int rc = do_panel(0, (int)std::min<int64_t>(pl.nb, n), 0);
     if (rc) return rc;
-    bool pending_r = false;
     for (int64_t c0 = 0; c0 < n; c0 += pl.nb) {
         const int bw = (int)std::min<int64_t>(pl.nb, n - c0);
         const int pidx = (int)(c0 / pl.nb);
