@@ -205,6 +205,22 @@ HQR_DEV double v_elem(const double *A, int64_t lda, const double *up, int c0, in
     return HQR_AT(A, gi, c0 + c, lda);
 }
 
+// v_elem with both candidate loads issued unconditionally (no branch around
+// a load, so a tile's loads stay in flight together); gi and c must address
+// the matrix.
+HQR_DEV double v_elem_nb(const double *A, int64_t lda, const double *up, int c0, int64_t gi, int c)
+{
+    const double a = HQR_AT(A, gi, c0 + c, lda);
+    const double u = up[c0 + c];
+    const int64_t d = gi - c0;
+    return (d < c) ? 0.0 : ((d == c) ? u : a);
+}
+
+// Forces v to be materialized here (empty asm that reads and writes it): a
+// load feeding it cannot be sunk into a later conditional block, so a group
+// of loads issued before a group of pins waits once for all of them.
+HQR_DEV void pin_f64(double &v) { asm volatile("" : "+v"(v)); }
+
 HQR_DEV double x_elem(const VtxArgs &p, int64_t gi, int x)
 {
     if (gi >= p.m || x >= p.nx) return 0.0;
@@ -504,7 +520,7 @@ constexpr int UPD_TILE = 128;
 // F32: V and W' rounded to FP32, the product accumulated in FP32 by FP32
 // MFMA from zero, then subtracted from the FP64 trailing matrix.
 template <bool F32>
-__global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
+__global__ void __launch_bounds__(256, 2) update_kernel(UpdArgs p)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w & 1, wc = w >> 1;
@@ -515,9 +531,21 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
     const int li = lane & 15, lk = lane >> 4;
     const bool masked = rb < (int64_t)p.c0 + p.bw; // rows that meet the triangle of V
 
+    // Loads are unconditional: rows and columns are clamped into the matrix.
+    // A lane outside it only ever feeds accumulator entries that are never
+    // stored, except through k >= bw, which is zeroed after the loads.
+    int64_t gr[4];
+    bool rok[4];
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+        const int64_t gi = rb + 16 * ti + li;
+        rok[ti] = gi < p.m;
+        gr[ti] = rok[ti] ? gi : p.m - 1;
+    }
     f64x4 acc[4][4]; // [column tile][row tile]
     f32x4 acc32[4][4];
     double *cptr[4][4];
+    bool cok[4][4];
     // accumulator register r of lane (li, lk) holds column cb + 16 tj + ccol(r), row li
 #define HQR_CCOL(r) (F32 ? 4 * lk + (r) : 4 * (r) + lk)
 #pragma unroll
@@ -525,7 +553,8 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int c = cb + 16 * tj + HQR_CCOL(r);
-            cptr[tj][r] = (c < ncols) ? col_ptr(p, c) : nullptr;
+            cok[tj][r] = c < ncols;
+            cptr[tj][r] = col_ptr(p, cok[tj][r] ? c : 0);
         }
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
@@ -533,29 +562,46 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
         for (int ti = 0; ti < 4; ++ti) {
             acc32[tj][ti] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t gi = rb + 16 * ti + li;
-                acc[tj][ti][r] = (!F32 && cptr[tj][r] && gi < p.m) ? __builtin_nontemporal_load(&cptr[tj][r][gi]) : 0.0;
-            }
+            for (int r = 0; r < 4; ++r)
+                acc[tj][ti][r] = F32 ? 0.0 : __builtin_nontemporal_load(&cptr[tj][r][gr[ti]]);
         }
 
     const double *wrow = p.wp + p.xoff + cb + li;
-#pragma unroll 2
+    int wofs[4];
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) wofs[tj] = (cb + 16 * tj + li < ncols) ? 16 * tj : 0;
+    // raw operands of a k-step: W' row k, V column k and up_k (plain loads,
+    // no branch); the triangle of V and k >= bw are applied after the pins
+    double an[4], bn[4], un;
+    auto issue = [&](int k0) {
+        const int k = k0 + lk;
+        const int kc = (k < p.bw) ? k : 0;
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) an[tj] = wrow[(size_t)kc * p.nxpad + wofs[tj]];
+#pragma unroll
+        for (int ti = 0; ti < 4; ++ti) bn[ti] = HQR_AT(p.A, gr[ti], p.c0 + kc, p.lda);
+        un = p.up[p.c0 + kc];
+    };
+    issue(0);
+#pragma unroll 1
     for (int k0 = 0; k0 < NB; k0 += 4) {
         const int k = k0 + lk;
+        const bool kok = k < p.bw;
         double a[4], b[4];
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj) {
-            const int c = cb + 16 * tj + li;
-            a[tj] = (k < p.bw && c < ncols) ? -wrow[(size_t)k * p.nxpad + 16 * tj] : 0.0;
+        for (int q = 0; q < 4; ++q) {
+            pin_f64(an[q]);
+            pin_f64(bn[q]);
         }
+        pin_f64(un);
 #pragma unroll
-        for (int ti = 0; ti < 4; ++ti) {
-            const int64_t gi = rb + 16 * ti + li;
-            double v = 0.0;
-            if (k < p.bw && gi < p.m) v = masked ? v_elem(p.A, p.lda, p.up, p.c0, gi, k) : HQR_AT(p.A, gi, p.c0 + k, p.lda);
-            b[ti] = v;
+        for (int q = 0; q < 4; ++q) {
+            const int64_t d = rb + 16 * q + li - p.c0;   // row offset from the panel's first row
+            const double v = (masked && d <= k) ? ((d == k) ? un : 0.0) : bn[q];
+            a[q] = kok ? -an[q] : 0.0;
+            b[q] = kok ? v : 0.0;
         }
+        if (k0 + 4 < NB) issue(k0 + 4);
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
@@ -566,6 +612,15 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
                     acc[tj][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tj], b[ti], acc[tj][ti], 0, 0, 0);
             }
     }
+    if (F32) {
+        // C += the FP32 product: the old values are loaded together first
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[tj][ti][r] = __builtin_nontemporal_load(&cptr[tj][r][gr[ti]]);
+    }
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
@@ -573,8 +628,8 @@ __global__ void __launch_bounds__(256) update_kernel(UpdArgs p)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = rb + 16 * ti + li;
-                if (cptr[tj][r] && gi < p.m) {
-                    if (F32) __builtin_nontemporal_store(cptr[tj][r][gi] + (double)acc32[tj][ti][r], &cptr[tj][r][gi]);
+                if (cok[tj][r] && rok[ti]) {
+                    if (F32) __builtin_nontemporal_store(acc[tj][ti][r] + (double)acc32[tj][ti][r], &cptr[tj][r][gi]);
                     else __builtin_nontemporal_store(acc[tj][ti][r], &cptr[tj][r][gi]);
                 }
             }
@@ -596,33 +651,54 @@ __global__ void __launch_bounds__(256) update_narrow_kernel(UpdArgs p)
     const int li = lane & 15, lk = lane >> 4;
     const int64_t gi = rb + li;
     const bool rok = gi < p.m;
+    const int64_t gr = rok ? gi : p.m - 1;   // loads are unconditional (clamped, zeroed after)
     const bool masked = rb < (int64_t)p.c0 + p.bw;
 #define HQR_NCOL(r) (F32 ? 4 * lk + (r) : 4 * (r) + lk)
     f64x4 acc[4];
     f32x4 acc32[4];
     double *cptr[4][4];
+    bool cok[4][4];
 #pragma unroll
     for (int tj = 0; tj < 4; ++tj) {
         acc32[tj] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int c = 16 * tj + HQR_NCOL(r);
-            cptr[tj][r] = (c < ncols) ? col_ptr(p, c) : nullptr;
-            acc[tj][r] = (!F32 && cptr[tj][r] && rok) ? cptr[tj][r][gi] : 0.0;
+            cok[tj][r] = c < ncols;
+            cptr[tj][r] = col_ptr(p, cok[tj][r] ? c : 0);
+            const double v = cptr[tj][r][gr];
+            acc[tj][r] = (cok[tj][r] && rok) ? v : 0.0;
         }
     }
-    // every operand is loaded before the first MFMA (80 values per lane)
+    // every operand is loaded before the first MFMA (80 values per lane, plus
+    // up_k): plain loads first, all pinned, then the selects
     const double *wrow = p.wp + p.xoff + li;
-    double a[NB / 4][4], bv[NB / 4];
+    double a[NB / 4][4], bv[NB / 4], uv[NB / 4];
 #pragma unroll
     for (int k4 = 0; k4 < NB / 4; ++k4) {
         const int k = 4 * k4 + lk;
+        const int kc = (k < p.bw) ? k : 0;
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj)
-            a[k4][tj] = (k < p.bw && 16 * tj + li < ncols) ? -wrow[(size_t)k * p.nxpad + 16 * tj] : 0.0;
-        double b = 0.0;
-        if (k < p.bw && rok) b = masked ? v_elem(p.A, p.lda, p.up, p.c0, gi, k) : HQR_AT(p.A, gi, p.c0 + k, p.lda);
-        bv[k4] = b;
+        for (int tj = 0; tj < 4; ++tj) a[k4][tj] = wrow[(size_t)kc * p.nxpad + ((16 * tj + li < ncols) ? 16 * tj : 0)];
+        bv[k4] = HQR_AT(p.A, gr, p.c0 + kc, p.lda);
+        uv[k4] = p.up[p.c0 + kc];
+    }
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) pin_f64(a[k4][tj]);
+        pin_f64(bv[k4]);
+        pin_f64(uv[k4]);
+    }
+    const int64_t d = gi - p.c0;   // row offset from the panel's first row
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+        const int k = 4 * k4 + lk;
+        const bool kok = k < p.bw;
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) a[k4][tj] = (kok && 16 * tj + li < ncols) ? -a[k4][tj] : 0.0;
+        const double b = (masked && d <= k) ? ((d == k) ? uv[k4] : 0.0) : bv[k4];
+        bv[k4] = (kok && rok) ? b : 0.0;
     }
 #pragma unroll
     for (int k4 = 0; k4 < NB / 4; ++k4) {
@@ -639,8 +715,8 @@ __global__ void __launch_bounds__(256) update_narrow_kernel(UpdArgs p)
     for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            if (cptr[tj][r] && rok) {
-                if (F32) cptr[tj][r][gi] = cptr[tj][r][gi] + (double)acc32[tj][r];
+            if (cok[tj][r] && rok) {
+                if (F32) cptr[tj][r][gi] = acc[tj][r] + (double)acc32[tj][r];
                 else cptr[tj][r][gi] = acc[tj][r];
             }
 #undef HQR_NCOL

@@ -535,6 +535,56 @@ HQR_DEV void for_uu(const f64x4 (&acc)[4], F f, int lane, int w)
     }
 }
 
+// M[r][c] = A[r0 + r][c0 + c] (r < 64, c < NB), zero for rows >= m or
+// columns >= ncol.  256 threads; the loads are unconditional (clamped into
+// the matrix, zeroed afterwards), so all 16 of a thread are in flight
+// together instead of each waiting behind its own branch.
+HQR_DEV void load_tile(double (*M)[LD65], const double *A, int64_t lda, int64_t m, int64_t r0, int c0, int ncol,
+                       int tid)
+{
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * q, c = idx / 64, r = idx % 64;
+        const int64_t gi = r0 + r;
+        v[q] = HQR_AT(A, (gi < m) ? gi : m - 1, c0 + ((c < ncol) ? c : 0), lda);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pin_f64(v[q]);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * q, c = idx / 64, r = idx % 64;
+        M[r][c] = (r0 + r < m && c < ncol) ? v[q] : 0.0;
+    }
+}
+
+// M[r][c] = V[r0 + r][c] of the panel starting at cv (width NB; unit lower
+// triangle with up on the diagonal in its top block), zero for rows >= m.
+HQR_DEV void load_vtile(double (*M)[LD65], const double *A, int64_t lda, const double *up, int64_t m, int64_t r0,
+                        int cv, int tid)
+{
+    double v[16], u[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * q, c = idx / 64, r = idx % 64;
+        const int64_t gi = r0 + r;
+        v[q] = HQR_AT(A, (gi < m) ? gi : m - 1, cv + c, lda);
+        u[q] = up[cv + c];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        pin_f64(v[q]);
+        pin_f64(u[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int idx = tid + 256 * q, c = idx / 64, r = idx % 64;
+        const int64_t d = r0 + r - cv;   // row offset from the panel's first row
+        const double e = (d < c) ? 0.0 : ((d == c) ? u[q] : v[q]);
+        M[r][c] = (r0 + r < m) ? e : 0.0;
+    }
+}
+
 // acc[t] (t = 0..3) += sign * A[16w:16w+16][:] * B[:][16t:16t+16] over k = 0..63
 HQR_DEV void mm64_acc(f64x4 (&acc)[4], const double (*A)[LD65], const double (*B)[LD65], double sign, int lane, int w)
 {
@@ -738,13 +788,8 @@ __global__ void __launch_bounds__(256) cqr_gram1_kernel(Gram1Args p)
     const bool flagged = *((volatile int *)p.flag) != 0;
     if (tid == 0) msk = 0ull;
     // M0 = C tile (panel columns); with the update M1 = V tile, M2 = X, M3 = T
-    for (int idx = tid; idx < 64 * NB; idx += 256) {
-        const int c = idx / 64, r = idx % 64;
-        const int64_t gi = r0 + r;
-        const bool ok = gi < p.m;
-        M0[r][c] = (ok && c < bw) ? HQR_AT(p.A, gi, p.c0 + c, p.lda) : 0.0;
-        if (p.upd) M1[r][c] = ok ? v_elem(p.A, p.lda, p.up, p.cp, gi, c) : 0.0;
-    }
+    load_tile(M0, p.A, p.lda, p.m, r0, p.c0, bw, tid);
+    if (p.upd) load_vtile(M1, p.A, p.lda, p.up, p.m, r0, p.cp, tid);
     if (p.upd)
         for (int idx = tid; idx < NB * NB; idx += 256) {
             const double xv = p.X[idx], tv = p.T[idx];
@@ -821,11 +866,7 @@ __global__ void __launch_bounds__(256) cqr_gram2_kernel(Gram2Args p)
     if (*((volatile int *)p.flag)) return;
     const int t = blockIdx.x;
     const int64_t r0 = (int64_t)p.c0 + 64 * (int64_t)t;
-    for (int idx = tid; idx < 64 * NB; idx += 256) {
-        const int c = idx / 64, r = idx % 64;
-        const int64_t gi = r0 + r;
-        X[r][c] = (gi < p.m && c < p.bw) ? HQR_AT(p.A, gi, p.c0 + c, p.lda) : 0.0;
-    }
+    load_tile(X, p.A, p.lda, p.m, r0, p.c0, p.bw, tid);
     for (int idx = tid; idx < NB * NB; idx += 256) Ri[idx / NB][idx % NB] = p.r1inv[idx];
     __syncthreads();
     mm64(Y, X, Ri, lane, w);
@@ -928,7 +969,8 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     // after the Cholesky factorization), all loads in flight together
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int i = idx / NB, j = idx % NB;
-        const double gv = (i < bw && j < bw) ? p.G[idx] : 0.0;
+        const double gl = p.G[idx];
+        const double gv = (i < bw && j < bw) ? gl : 0.0;
         if (p.pass == 2) {
             const double qv = p.q1top[idx], rv = p.r1[idx];
             M2[i][j] = qv;
@@ -1071,11 +1113,7 @@ __global__ void __launch_bounds__(256) cqr_finish_kernel(FinArgs p)
     if (*((volatile int *)p.flag)) return;
     const int64_t r0 = (int64_t)p.c0 + p.bw + (int64_t)blockIdx.x * 64;
     for (int idx = tid; idx < NB * NB; idx += 256) Wi[idx / NB][idx % NB] = p.winv[idx];
-    for (int idx = tid; idx < 64 * NB; idx += 256) {
-        const int c = idx / 64, r = idx % 64;
-        const int64_t gi = r0 + r;
-        X[r][c] = (gi < p.m && c < p.bw) ? HQR_AT(p.A, gi, p.c0 + c, p.lda) : 0.0;
-    }
+    load_tile(X, p.A, p.lda, p.m, r0, p.c0, p.bw, tid);
     __syncthreads();
     mm64(Y, X, Wi, lane, w);
     __syncthreads();
@@ -1116,13 +1154,9 @@ __global__ void __launch_bounds__(256) narrow_vtx_kernel(NarrowArgs p)
     const bool fin = (t > 0) && !flagged;
     // M0 = V rows (top block: unit lower with up on the diagonal), or A_bot;
     // M2 = C; M1 = W^{-1} when finishing
-    for (int idx = tid; idx < 64 * NB; idx += 256) {
-        const int c = idx / 64, r = idx % 64;
-        const int64_t gi = r0 + r;
-        const bool ok = gi < p.m;
-        M0[r][c] = ok ? ((t == 0) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : HQR_AT(p.A, gi, p.c0 + c, p.lda)) : 0.0;
-        M2[r][c] = (ok && c < p.nc) ? HQR_AT(p.A, gi, p.c0 + NB + c, p.lda) : 0.0;
-    }
+    if (t == 0) load_vtile(M0, p.A, p.lda, p.up, p.m, r0, p.c0, tid);
+    else load_tile(M0, p.A, p.lda, p.m, r0, p.c0, NB, tid);
+    load_tile(M2, p.A, p.lda, p.m, r0, p.c0 + NB, p.nc, tid);
     if (fin)
         for (int idx = tid; idx < NB * NB; idx += 256) M1[idx / NB][idx % NB] = p.winv[idx];
     __syncthreads();
