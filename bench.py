@@ -62,22 +62,25 @@ def qr_flops(m, n):
 
 
 def class_work(m, n, nrhs, nb=64):
-    """Algorithmic work of each kernel class over one solve, per panel of
-    width bw at row offset c0 (m_p = m - c0 rows, ncols = trailing columns
-    plus right-hand sides).  Returns {class: (bound, amount, peak, unit)}:
+    """Algorithmic work of each kernel class over one solve with look-ahead,
+    per panel of width bw at row offset c0 (m_p = m - c0 rows; the next
+    panel has bw1 columns; ncR = later columns plus right-hand sides, the
+    side stream's share).  Returns {class: (bound, amount, peak, unit)}:
 
-      vtx         W = V^T [C | B] (T comes from the panel):
-                  2 m_p bw ncols flops                                 (FP64 MFMA)
-      update      C <- C - V W': reads and writes C, reads V and W':
-                  16 m_p ncols + 8 m_p bw + 8 bw ncols bytes (2 m_p bw ncols
-                  flops: 7.9 flop/B at bw = 64, under the FP64 ridge)  (HBM)
-      cqr_gram    Gram of the panel (pass 1), then Q1 = A_p R1^-1 and its
-                  Gram (pass 2): 2 m_p bw^2 + 4 m_p bw^2 flops         (FP64 MFMA)
-      cqr_finish  Y_bot = A_bot W^-1: 2 (m_p - bw) bw^2 flops          (FP64 MFMA)
-      gram_reduce sum of the per-workgroup Gram partials: reads
-                  ceil(m_p/128) bw^2 doubles, writes bw^2, per pass    (HBM)
-      wsolve      sum of split-K partials of W and W' = T^T W: reads
-                  nsplit bw ncols doubles, writes bw ncols             (HBM)
+      vtx         X = V^T [C | B] over the ncR columns:
+                  2 m_p bw ncR flops                                   (FP64 MFMA)
+      update      C <- C - V W' over the ncR columns: reads and writes C,
+                  reads V and W': 16 m_p ncR + 8 m_p bw + 8 bw ncR bytes (HBM)
+      wsolve      sum of the split-K partials of X and W' = T^T X: reads
+                  nsplit bw ncR doubles, writes bw ncR                 (HBM)
+      narrow_vtx  V_bot = A_bot W^-1 and X = V^T C for the next panel:
+                  2 (m_p - bw) bw^2 + 2 m_p bw bw1 flops               (FP64 MFMA)
+      cqr_gram1   next panel: W = T^T X per 64-row tile, C -= V W and the
+                  pass-1 Gram partials: 2 m_p bw bw1 + 2 (m_p - bw) bw1^2
+                  flops (+ 2 bw^3 per tile)                            (FP64 MFMA)
+      cqr_gram2   Q1 = A_p R1^-1 and its Gram: 4 m_p bw^2 flops        (FP64 MFMA)
+      gram_reduce sums of the per-tile 64 x 64 partials (X, G1, G2): reads
+                  ceil(m_p/64) bw^2 doubles, writes bw^2, three per panel (HBM)
       cqr_chol    64 x 64 Cholesky/inverse/LU work of one workgroup:
                   2/3 bw^3 flops (pass 1) + 14/3 bw^3 (pass 2)          (one CU)
       trsv        reads the n x n triangle once: 4 n^2 bytes            (HBM)
@@ -90,17 +93,24 @@ def class_work(m, n, nrhs, nb=64):
 
     for c0 in range(0, n, nb):
         bw = min(nb, n - c0)
+        bw1 = min(nb, max(0, n - c0 - bw))
         mp = m - c0
-        ncols = n - c0 - bw + nrhs
-        ngroups = -(-mp // 128)
-        ntiles = -(-ncols // 128)
+        ncR = max(0, n - c0 - bw - bw1) + nrhs
+        tiles = -(-mp // 64)
+        ntiles = -(-ncR // 128)
         nsplit = max(1, min(-(-512 // max(ntiles, 1)), max(1, mp // 256), 16))
-        add("vtx", "mfma", 2.0 * mp * bw * ncols)
-        add("update", "hbm", 16.0 * mp * ncols + 8.0 * mp * bw + 8.0 * bw * ncols)
-        add("cqr_gram", "mfma", 6.0 * mp * bw * bw)
-        add("cqr_finish", "mfma", 2.0 * max(mp - bw, 0) * bw * bw)
-        add("gram_reduce", "hbm", 2 * 8.0 * (ngroups + 1) * bw * bw)
-        add("wsolve", "hbm", 8.0 * (nsplit + 1) * bw * ncols)
+        add("vtx", "mfma", 2.0 * mp * bw * ncR)
+        add("update", "hbm", 16.0 * mp * ncR + 8.0 * mp * bw + 8.0 * bw * ncR)
+        add("wsolve", "hbm", 8.0 * (nsplit + 1) * bw * ncR)
+        if bw1 > 0:
+            add("narrow_vtx", "mfma", 2.0 * max(mp - bw, 0) * bw * bw + 2.0 * mp * bw * bw1)
+            add("cqr_gram1", "mfma", 2.0 * mp * bw * bw1 + 2.0 * max(mp - bw, 0) * bw1 * bw1 + 2.0 * bw ** 3 * tiles)
+        else:
+            add("cqr_finish", "mfma", 2.0 * max(mp - bw, 0) * bw * bw)
+        if c0 == 0:
+            add("cqr_gram1", "mfma", 2.0 * mp * bw * bw)
+        add("cqr_gram2", "mfma", 4.0 * mp * bw * bw)
+        add("gram_reduce", "hbm", 3 * 8.0 * (tiles + 1) * bw * bw)
         add("cqr_chol", "cu", (2.0 / 3.0 + 14.0 / 3.0) * bw ** 3)
     add("trsv", "hbm", 4.0 * n * n)
     peaks = {"mfma": (PEAK_F64_TFLOPS, "TFLOP/s", 1e12), "hbm": (PEAK_HBM_GBS, "GB/s", 1e9),

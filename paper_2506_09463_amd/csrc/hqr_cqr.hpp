@@ -900,16 +900,37 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(GredArgs p)
     __shared__ double part[4][64];
     const int tid = threadIdx.x, e = blockIdx.x * 64 + (tid & 63), g4 = tid >> 6;
     if (p.flag && *((volatile int *)p.flag)) return;
+    // thread (e, g4) sums partials q = g4, g4 + 4, ... in that order; 16
+    // loads at a time are issued before any is used (clamped, zeroed after)
     double s = 0.0;
-#pragma unroll 4
-    for (int q = g4; q < p.ngroups; q += 4) s += p.gpart[(size_t)q * NB * NB + e];
+    for (int q0 = g4; q0 < p.ngroups; q0 += 64) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = q0 + 4 * u;
+            v[u] = p.gpart[(size_t)((q < p.ngroups) ? q : g4) * NB * NB + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) pin_f64(v[u]);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += (q0 + 4 * u < p.ngroups) ? v[u] : 0.0;
+    }
     part[g4][tid & 63] = s;
     __syncthreads();
     if (tid < 64) p.G[e] = ((part[0][tid] + part[1][tid]) + part[2][tid]) + part[3][tid];
-    if (p.with_mask && blockIdx.x == 0 && tid == 64) {
+    if (p.with_mask && blockIdx.x == 0 && tid >= 64 && tid < 128) {
+        // OR of the masks: 64 lanes, strided loads all in flight, then a
+        // butterfly over the wave
+        const int l = tid - 64;
         unsigned long long all = 0ull;
-        for (int q = 0; q < p.ngroups; ++q) all |= p.mask[q];
-        *p.mask_all = all;
+        for (int q = l; q < p.ngroups; q += 64) all |= p.mask[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned lo = (unsigned)all, hi = (unsigned)(all >> 32);
+            all |= (unsigned long long)(unsigned)__shfl_xor((int)lo, off) |
+                   ((unsigned long long)(unsigned)__shfl_xor((int)hi, off) << 32);
+        }
+        if (l == 0) *p.mask_all = all;
     }
 }
 
