@@ -294,17 +294,110 @@ HQR_DEV void chol64_dpp(double (*G)[LD65], double (*X)[LD65], int n, int lane, i
     __syncthreads();
 }
 
+// One block step of the LU below, in one wave: LPART = false computes U's
+// block row (lane t: column 16kb + t) and U_kk^{-1}; LPART = true computes
+// L's block column (lane t: row 16kb + t) and L_kk^{-1}.  Both keep the
+// diagonal block (lane 16r + j: its column j in dc, its row j in dr, in
+// every 16-lane row for the DPP broadcasts) and take the same pivots.
+// ov: U[.][c] (block row) or L[c][.] (block column) of the block step
+template <bool LPART>
+HQR_DEV void lu64_load(const double (*M)[LD65], int b0, int lane, double (&ov)[16], double (&dc)[16],
+                       double (&dr)[16])
+{
+    const int jj = lane & 15, c = b0 + lane;
+    const bool act = c < NB;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        ov[i] = act ? (LPART ? M[c][b0 + i] : M[b0 + i][c]) : 0.0;
+        dc[i] = M[b0 + i][b0 + jj];
+        dr[i] = M[b0 + jj][b0 + i];
+    }
+}
+
+// The block step on the loaded values (after a barrier: the other wave's
+// writes to M cannot race with these reads).  ax: the running sums of
+// U_kk^{-1} (row j: ax[l] = sum_{i<l} XU[j][i] U[i][l]) or of L_kk^{-1}
+// (column j: ax[l] = sum_{i<l} L[l][i] XL[i][j]).
+template <bool LPART>
+HQR_DEV void lu64_block(double (*M)[LD65], double (*DX)[17], int b0, int lane, double *sgn, double *udiag,
+                        double (&ov)[16], double (&dc)[16], double (&dr)[16])
+{
+    // opaque per block step: keeps the per-pivot lane masks from being
+    // hoisted out of the caller's kb loop (they would occupy ~100 SGPRs)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int jj = ln & 15, c = b0 + ln;
+    const bool act = c < NB;
+    double ax[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ax[i] = 0.0;
+    double my_sg = 0.0, my_uk = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int gi = b0 + i;
+        const double q = bc16(dc[i], i);
+        const double sg = (q >= 0.0) ? -1.0 : 1.0;
+        const double ukk = q - sg;
+        const double uinv = recip_nr(ukk);
+        const double ud = (jj > i) ? dc[i] : ((jj == i) ? ukk : 0.0);
+        const double ld = (jj > i) ? dr[i] * uinv : 0.0;
+        // U[gi][c] or L[c][gi]
+        const double oc = LPART ? ((c > gi) ? ov[i] * uinv : 0.0) : ((c > gi) ? ov[i] : ((c == gi) ? ukk : 0.0));
+        // XU[j][i] or XL[i][j]
+        const double xv = LPART ? ((jj < i) ? -ax[i] : ((jj == i) ? 1.0 : 0.0))
+                                : ((jj < i) ? -ax[i] * uinv : ((jj == i) ? uinv : 0.0));
+        dc[i] = ud;
+        dr[i] = ld;
+        ov[i] = oc;
+        if (!LPART) {
+            my_sg = (ln == i) ? sg : my_sg;
+            my_uk = (ln == i) ? ukk : my_uk;
+            DX[b0 + jj][i] = xv;       // the four rows store the same value
+        } else {
+            DX[b0 + i][jj] = xv;
+        }
+#pragma unroll
+        for (int i2 = i + 1; i2 < 16; ++i2) {
+            const double lb = bc16(ld, i2), ub = bc16(ud, i2);   // L[i2][i], U[i][i2]
+            dc[i2] = fma(-lb, ud, dc[i2]);
+            dr[i2] = fma(-ld, ub, dr[i2]);
+            if (!LPART) {
+                ov[i2] = fma(-lb, oc, ov[i2]);
+                ax[i2] = fma(xv, ub, ax[i2]);
+            } else {
+                ov[i2] = fma(-oc, ub, ov[i2]);
+                ax[i2] = fma(lb, xv, ax[i2]);
+            }
+            pin(dc[i2]);
+            pin(dr[i2]);
+            pin(ov[i2]);
+            pin(ax[i2]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int gi = b0 + i;
+            if (!LPART && c >= gi) M[gi][c] = ov[i];
+            if (LPART && c > gi) M[c][gi] = ov[i];
+        }
+    }
+    if (!LPART && ln < 16) {
+        sgn[b0 + ln] = my_sg;
+        udiag[b0 + ln] = my_uk;
+    }
+}
+
 // In place: M (n x n leading block; entries outside it zero) becomes L
 // (strict lower, unit diagonal implied) and U (upper, diagonal U_kk) of the
 // LU factorization without pivoting of M - S, s_k = -sgn(pivot of step k)
 // (sgn(0) = +1); beyond n the factors continue as the identity (s_k = -1,
-// U_kk = 1).  Block step kb: wave 0 computes U's block row and L's block
-// column in registers (lane t: column 16kb + t of U and row 16kb + t of L;
-// every 16-lane row also holds the diagonal block, lane 16r + j its column j
-// and its row j, for DPP broadcasts), then inverts the diagonal blocks of U
-// and L into DU and DL (rows 16kb..16kb+15); all waves then subtract
-// L_kb U_kb from the trailing blocks on MFMA.  sgn and udiag get s_k and U_kk
-// for all 64 steps.  Starts and ends with a barrier.
+// U_kk = 1).  Block step kb: wave 0 computes U's block row and the diagonal
+// block of U^{-1} (into DU, rows 16kb..16kb+15), wave 1 L's block column and
+// the diagonal block of L^{-1} (into DL), both by lu64_block; all waves then
+// subtract L_kb U_kb from the trailing blocks on MFMA.  sgn and udiag get s_k
+// and U_kk for all 64 steps.  Starts and ends with a barrier.
 HQR_DEV void lu64_dpp(double (*M)[LD65], double (*DU)[17], double (*DL)[17], int lane, int w, double *sgn,
                       double *udiag)
 {
@@ -312,79 +405,12 @@ HQR_DEV void lu64_dpp(double (*M)[LD65], double (*DU)[17], double (*DL)[17], int
 #pragma unroll 1
     for (int kb = 0; kb < 4; ++kb) {
         const int b0 = 16 * kb;
-        if (w == 0) {
-            // opaque per block step: keeps the per-pivot lane masks from being
-            // hoisted out of the kb loop (they would occupy ~100 SGPRs)
-            int ln = lane;
-            asm volatile("" : "+v"(ln));
-            const int jj = ln & 15, c = b0 + ln;
-            const bool act = c < NB;
-            double cv[16], rv[16], dc[16], dr[16], au[16], al[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                cv[i] = act ? M[b0 + i][c] : 0.0;
-                rv[i] = act ? M[c][b0 + i] : 0.0;
-                dc[i] = M[b0 + i][b0 + jj];
-                dr[i] = M[b0 + jj][b0 + i];
-                au[i] = 0.0;
-                al[i] = 0.0;
-            }
-            // U_kk^{-1} and L_kk^{-1} are built along: lane j holds row j of
-            // XU = U_kk^{-1} (au[l] = sum_{i<l} XU[j][i] U[i][l]) and column j
-            // of XL = L_kk^{-1} (al[l] = sum_{i<l} L[l][i] XL[i][j]).
-            double my_sg = 0.0, my_uk = 0.0;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int gi = b0 + i;
-                const double q = bc16(dc[i], i);
-                const double sg = (q >= 0.0) ? -1.0 : 1.0;
-                const double ukk = q - sg;
-                const double uinv = recip_nr(ukk);
-                const double ud = (jj > i) ? dc[i] : ((jj == i) ? ukk : 0.0);
-                const double ld = (jj > i) ? dr[i] * uinv : 0.0;
-                const double uc = (c > gi) ? cv[i] : ((c == gi) ? ukk : 0.0);
-                const double lc = (c > gi) ? rv[i] * uinv : 0.0;
-                const double xu = (jj < i) ? -au[i] * uinv : ((jj == i) ? uinv : 0.0);  // XU[j][i]
-                const double xl = (jj < i) ? -al[i] : ((jj == i) ? 1.0 : 0.0);          // XL[i][j]
-                dc[i] = ud;
-                dr[i] = ld;
-                cv[i] = uc;
-                rv[i] = lc;
-                my_sg = (ln == i) ? sg : my_sg;
-                my_uk = (ln == i) ? ukk : my_uk;
-                DU[b0 + jj][i] = xu;       // the four rows store the same values
-                DL[b0 + i][jj] = xl;
-#pragma unroll
-                for (int i2 = i + 1; i2 < 16; ++i2) {
-                    const double lb = bc16(ld, i2), ub = bc16(ud, i2);   // L[i2][i], U[i][i2]
-                    cv[i2] = fma(-lb, uc, cv[i2]);
-                    dc[i2] = fma(-lb, ud, dc[i2]);
-                    rv[i2] = fma(-lc, ub, rv[i2]);
-                    dr[i2] = fma(-ld, ub, dr[i2]);
-                    au[i2] = fma(xu, ub, au[i2]);
-                    al[i2] = fma(lb, xl, al[i2]);
-                    pin(cv[i2]);
-                    pin(dc[i2]);
-                    pin(rv[i2]);
-                    pin(dr[i2]);
-                    pin(au[i2]);
-                    pin(al[i2]);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (act) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int gi = b0 + i;
-                    if (c >= gi) M[gi][c] = cv[i];
-                    if (c > gi) M[c][gi] = rv[i];
-                }
-            }
-            if (lane < 16) {
-                sgn[b0 + lane] = my_sg;
-                udiag[b0 + lane] = my_uk;
-            }
-        }
+        double ov[16], dc[16], dr[16];
+        if (w == 0) lu64_load<false>(M, b0, lane, ov, dc, dr);
+        else if (w == 1) lu64_load<true>(M, b0, lane, ov, dc, dr);
+        __syncthreads();
+        if (w == 0) lu64_block<false>(M, DU, b0, lane, sgn, udiag, ov, dc, dr);
+        else if (w == 1) lu64_block<true>(M, DL, b0, lane, sgn, udiag, ov, dc, dr);
         __syncthreads();
         // trailing blocks: M_ij -= L_p,i U_p,j over the block's 16 pivots
         const int rem = 3 - kb;
@@ -1039,10 +1065,6 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     // LU of Q_top - S in M2; diagonal blocks of U^{-1} -> DU, of L^{-1} -> DL
     lu64_dpp(M2, DU, DL, lane, w, sgn, udiag);
     HQR_TS();
-    // R1^{-1} is needed last: start its loads now
-    double pf_r1inv[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) pf_r1inv[t] = p.r1inv[tid + 256 * t];
     // R = R2 R1; R_house = S R into the upper triangle of the panel's top block
     {
         f64x4 racc[4];
@@ -1090,7 +1112,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int idx = tid + 256 * t;
-        M1[idx / NB][idx % NB] = pf_r1inv[t];
+        M1[idx / NB][idx % NB] = p.r1inv[idx];
     }
     __syncthreads();
     // W^{-1} = R1^{-1} V1 diag(up) -> global (zero beyond bw and below the diagonal)
