@@ -39,10 +39,12 @@ PEAK_HBM_GBS = 8000.0
 # kernel sources they were taken on (SHA-256 over csrc/); otherwise the
 # roofline's traffic is null.
 HBM_TRAFFIC = {
-    "csrc_sha256": "de888dc25cbd8b1c0e2536447f81b56d48a2aa737f0679fc1da43afb15f6b5c6",
-    "per_launch_bytes": {"cqr_chol": [176396, 82176], "update": [79285651, 55855378], "vtx": [69598542, 8928377],
-                         "cqr_gram": [3369960, 1590024], "wsolve": [8590798, 521192], "trsv": [68611723, 34816],
-                         "cqr_finish": [3443603, 3129344], "gram_reduce": [1621357, 32784]},
+    "csrc_sha256": "a20368ab4138c8e4d0d55e27e178d8cf119939d750ce8207a9f592b09577ba7f",
+    "per_launch_bytes": {"cqr_chol": [159805, 82176], "update": [145513366, 111204763],
+                         "vtx": [131437999, 16726016], "wsolve": [16891788, 1034240], "trsv": [68612243, 34816],
+                         "cqr_gram1": [7004228, 6294032], "cqr_gram2": [3523601, 3194880],
+                         "gram_reduce": [3218567, 32779], "narrow_vtx": [6762588, 6324224],
+                         "cqr_finish": [2426804, 2097152]},
 }
 
 

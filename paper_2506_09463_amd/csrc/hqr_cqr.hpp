@@ -988,6 +988,7 @@ struct CholArgs {
 //           and W^{-1} = R1^{-1} R2^{-1} U^{-1} diag(up).
 __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
 {
+    __builtin_amdgcn_s_setprio(3);   // single workgroup on the critical path: issue ahead of co-resident bulk waves
     __shared__ double M0[NB][LD65];
     __shared__ double M1[NB][LD65];
     __shared__ double M2[NB][LD65];
