@@ -77,12 +77,12 @@ def class_work(m, n, nrhs, nb=64):
                   nsplit bw ncR doubles, writes bw ncR                 (HBM)
       narrow_vtx  V_bot = A_bot W^-1 and X = V^T C for the next panel:
                   2 (m_p - bw) bw^2 + 2 m_p bw bw1 flops               (FP64 MFMA)
-      cqr_gram1   next panel: W = T^T X per 64-row tile, C -= V W and the
-                  pass-1 Gram partials: 2 m_p bw bw1 + 2 (m_p - bw) bw1^2
-                  flops (+ 2 bw^3 per tile)                            (FP64 MFMA)
+      cqr_gram1   next panel: C -= V W and the pass-1 Gram partials:
+                  2 m_p bw bw1 + 2 (m_p - bw) bw1^2 flops              (FP64 MFMA)
       cqr_gram2   Q1 = A_p R1^-1 and its Gram: 4 m_p bw^2 flops        (FP64 MFMA)
-      gram_reduce sums of the per-tile 64 x 64 partials (X, G1, G2): reads
-                  ceil(m_p/64) bw^2 doubles, writes bw^2, three per panel (HBM)
+      gram_reduce sums of the per-tile 64 x 64 partials (X, followed by
+                  W = T^T X in the same kernel; G1; G2): reads ceil(m_p/64)
+                  bw^2 doubles, writes bw^2, three per panel            (HBM)
       cqr_chol    64 x 64 Cholesky/inverse/LU work of one workgroup:
                   2/3 bw^3 flops (pass 1) + 14/3 bw^3 (pass 2)          (one CU)
       trsv        reads the n x n triangle once: 4 n^2 bytes            (HBM)
@@ -106,7 +106,7 @@ def class_work(m, n, nrhs, nb=64):
         add("wsolve", "hbm", 8.0 * (nsplit + 1) * bw * ncR)
         if bw1 > 0:
             add("narrow_vtx", "mfma", 2.0 * max(mp - bw, 0) * bw * bw + 2.0 * mp * bw * bw1)
-            add("cqr_gram1", "mfma", 2.0 * mp * bw * bw1 + 2.0 * max(mp - bw, 0) * bw1 * bw1 + 2.0 * bw ** 3 * tiles)
+            add("cqr_gram1", "mfma", 2.0 * mp * bw * bw1 + 2.0 * max(mp - bw, 0) * bw1 * bw1)
         else:
             add("cqr_finish", "mfma", 2.0 * max(mp - bw, 0) * bw * bw)
         if c0 == 0:

@@ -782,10 +782,9 @@ HQR_DEV void exact_panel(const ExactArgs &p, int tid, double (*red)[PW], double 
 // Pass 1, workgroup t owns rows rbase + 64t .. +63 (rbase = cp with the
 // update, c0 without).  With `upd` it first applies the previous panel's
 // compact-WY block to this panel's columns: C -= V W with W = T^T X, X = V^T C
-// reduced over all rows (narrow_vtx_kernel + gram_reduce_kernel), V the
-// previous panel's reflectors (rows from cp, width NB); W is formed in every
-// workgroup (one 64^3 product on MFMA).  Then the rows at or below c0 give a
-// Gram partial Z^T Z of the panel and its zero-tail mask.
+// reduced over all rows (narrow_vtx_kernel + xw_reduce_kernel), V the
+// previous panel's reflectors (rows from cp, width NB).  Then the rows at or
+// below c0 give a Gram partial Z^T Z of the panel and its zero-tail mask.
 struct Gram1Args {
     double *A;
     int64_t lda;
@@ -793,8 +792,7 @@ struct Gram1Args {
     int c0, bw;               // panel whose Gram is formed
     int upd, cp;              // apply the previous panel (start cp, width NB) first
     const double *up;         // stored up (the previous panel's part is read)
-    const double *X;          // [NB][NB] V^T C (upd)
-    const double *T;          // [NB][NB] the previous panel's T (upd)
+    const double *Wt;         // [NB][NB] W = T^T V^T C of the previous panel, transposed (upd)
     double *gpart;            // [tiles][NB][NB]
     unsigned long long *mask; // [tiles]
     const int *flag;
@@ -805,7 +803,6 @@ __global__ void __launch_bounds__(256) cqr_gram1_kernel(Gram1Args p)
     __shared__ double M0[NB][LD65];
     __shared__ double M1[NB][LD65];
     __shared__ double M2[NB][LD65];
-    __shared__ double M3[NB][LD65];
     __shared__ unsigned long long msk;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int bw = p.bw, t = blockIdx.x;
@@ -813,32 +810,15 @@ __global__ void __launch_bounds__(256) cqr_gram1_kernel(Gram1Args p)
     const int64_t r0 = rbase + 64 * (int64_t)t;
     const bool flagged = *((volatile int *)p.flag) != 0;
     if (tid == 0) msk = 0ull;
-    // M0 = C tile (panel columns); with the update M1 = V tile, M2 = X, M3 = T
+    // M0 = C tile (panel columns); with the update M1 = V tile, M2 = W
     load_tile(M0, p.A, p.lda, p.m, r0, p.c0, bw, tid);
-    if (p.upd) load_vtile(M1, p.A, p.lda, p.up, p.m, r0, p.cp, tid);
-    if (p.upd)
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            const double xv = p.X[idx], tv = p.T[idx];
-            M2[idx / NB][idx % NB] = xv;
-            M3[idx / NB][idx % NB] = tv;
-        }
+    if (p.upd) {
+        load_vtile(M1, p.A, p.lda, p.up, p.m, r0, p.cp, tid);
+        for (int idx = tid; idx < NB * NB; idx += 256) M2[idx % NB][idx / NB] = p.Wt[idx];
+    }
     __syncthreads();
     if (p.upd) {
         f64x4 acc[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-        // W = T^T X: (T^T)[i][k] = T[k][i]
-#pragma unroll 4
-        for (int k0 = 0; k0 < NB; k0 += 4) {
-            const int kr = k0 + (lane >> 4);
-            const double a = M3[kr][16 * w + (lane & 15)];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, M2[kr][16 * q + (lane & 15)], acc[q], 0, 0, 0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) st_blk(M2, 16 * w, 16 * q, acc[q], 1.0, lane);   // M2 = W
-        __syncthreads();
         // C -= V W: each wave reads and rewrites only its own 16 rows of M0
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = ld_blk(M0, 16 * w, 16 * q, lane);
@@ -1013,18 +993,31 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         ++tsi;                                                                   \
     } while (0)
     HQR_TS();
-    // G -> M0; pass 2 also stages Q1_top -> M2 and R1 -> M3 (idle until
-    // after the Cholesky factorization), all loads in flight together
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx / NB, j = idx % NB;
-        const double gl = p.G[idx];
-        const double gv = (i < bw && j < bw) ? gl : 0.0;
-        if (p.pass == 2) {
-            const double qv = p.q1top[idx], rv = p.r1[idx];
-            M2[i][j] = qv;
-            M3[i][j] = rv;
+    // G -> M0, Q1_top -> M2 and R1 -> M3 (the last two idle until after the
+    // Cholesky factorization; read in pass 1 too, where they are unused):
+    // all 48 loads of a thread are issued before the first is waited for
+    {
+        double gl[16], ql[16], rl[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int idx = tid + 256 * t;
+            gl[t] = p.G[idx];
+            ql[t] = p.q1top[idx];
+            rl[t] = p.r1[idx];
         }
-        M0[i][j] = gv;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            pin(gl[t]);
+            pin(ql[t]);
+            pin(rl[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int idx = tid + 256 * t, i = idx / NB, j = idx % NB;
+            M0[i][j] = (i < bw && j < bw) ? gl[t] : 0.0;
+            M2[i][j] = ql[t];
+            M3[i][j] = rl[t];
+        }
     }
     int structural = 0;
     if (p.pass == 1 && tid == 0) {
@@ -1088,6 +1081,11 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     }
     inv_lu_levels(M0, M3, M2, lane, w);                 // M0 = U^{-1}, M3 = L^{-1}
     HQR_TS();
+    // R1^{-1} is fetched now (into M1 once V1 no longer needs R2^{-1} there),
+    // so its latency overlaps the two products below
+    double r1i[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) r1i[t] = p.r1inv[tid + 256 * t];
     // T_Y = -(U S) L^{-T}, T_V = T_Y / (up_i up_j) -> global; V1 = R2^{-1} U^{-1}
     f64x4 vacc[4];
     {
@@ -1113,7 +1111,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int idx = tid + 256 * t;
-        M1[idx / NB][idx % NB] = p.r1inv[idx];
+        M1[idx / NB][idx % NB] = r1i[t];
     }
     __syncthreads();
     // W^{-1} = R1^{-1} V1 diag(up) -> global (zero beyond bw and below the diagonal)
@@ -1234,7 +1232,60 @@ __global__ void __launch_bounds__(256) narrow_vtx_kernel(NarrowArgs p)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, M2[kr][16 * q + (lane & 15)], acc[q], 0, 0, 0);
         }
-        st64_global(p.gpart + (size_t)t * NB * NB, acc, lane, w);
+        // stored transposed, [column j][reflector i], for xw_reduce_kernel
+        double *out = p.gpart + (size_t)t * NB * NB;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) out[(16 * q + (lane & 15)) * NB + 16 * w + 4 * r + (lane >> 4)] = acc[q][r];
+    }
+}
+
+// --------------------------------------------- W = T^T X for the look-ahead
+// Workgroup j: column j of X = sum of the transposed partials of
+// narrow_vtx_kernel (fixed order: thread (i, g4) sums q = g4, g4 + 4, ..;
+// the quarters added 0..3), then column j of W = T^T X (T upper triangular,
+// W[i][j] = sum_{l <= i} T[l][i] X[l][j]), stored transposed (Wt[j][i]).
+struct XwArgs {
+    const double *gpart;      // [parts][NB][NB], [q][j][i]
+    int parts;
+    const double *T;          // [NB][NB] row-major
+    double *Wt;               // [NB][NB] out, Wt[j][i] = W[i][j]
+};
+
+__global__ void __launch_bounds__(256) xw_reduce_kernel(XwArgs p)
+{
+    __shared__ double part[4][64];
+    __shared__ double xc[64];
+    const int tid = threadIdx.x, i = tid & 63, g4 = tid >> 6, j = blockIdx.x;
+    const size_t e = (size_t)j * NB + i;
+    double s = 0.0;
+    for (int q0 = g4; q0 < p.parts; q0 += 64) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int q = q0 + 4 * u;
+            v[u] = p.gpart[(size_t)((q < p.parts) ? q : g4) * NB * NB + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) pin_f64(v[u]);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += (q0 + 4 * u < p.parts) ? v[u] : 0.0;
+    }
+    part[g4][i] = s;
+    __syncthreads();
+    if (tid < 64) xc[i] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+    __syncthreads();
+    if (tid < 64) {
+        double tcol[NB];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) tcol[l] = p.T[l * NB + i];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) pin_f64(tcol[l]);
+        double wv = 0.0;
+#pragma unroll
+        for (int l = 0; l < NB; ++l) wv = (l <= i) ? fma(tcol[l], xc[l], wv) : wv;
+        p.Wt[e] = wv;
     }
 }
 

@@ -288,7 +288,7 @@ struct Work {
     int *flags;
     int *iscratch;
     double *gpart, *r1, *r1inv, *winv, *q1top;
-    double *G, *xn;                          // reduced Gram; reduced V^T C of the look-ahead
+    double *G, *xn;                          // reduced Gram; W = T^T V^T C of the look-ahead (transposed)
     double *borig, *rvec, *gvec, *mstat_d;   // mixed precision: original B, residual, A^T r, ||dx||
     int *mstat;                              // mixed precision: [first converged step, stagnation, run]
     unsigned long long *mask, *mask_all;
@@ -380,9 +380,12 @@ struct TrailBufs {
 // Apply the compact-WY block of panel (c0, bw) to trailing A columns
 // [c0+bw+aoff, c0+bw+aoff+ncA) and all nB columns of B.  With have_t the
 // panel's T is already in tb.T; otherwise it is formed from V^T V.
+// With ev_first: the first `first_cols` A columns (at most 64) are updated by
+// a launch of their own, ev_first is recorded on s after it, and the rest
+// follows (ev_first is recorded at the end when there is nothing to split).
 static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int64_t lda, double *B, int64_t ldb,
                              const double *up, int c0, int bw, int aoff, int ncA, int nB, bool have_t,
-                             hipStream_t s, bool f32 = false)
+                             hipStream_t s, bool f32 = false, int first_cols = 0, hipEvent_t ev_first = nullptr)
 {
     const int64_t rows = pl.m - c0;
     VtxArgs v;
@@ -435,7 +438,10 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     }
 
     const int ncols = ncA + nB;
-    if (ncols == 0) return 0;
+    if (ncols == 0) {
+        if (ev_first) HQR_CK(hipEventRecord(ev_first, s));
+        return 0;
+    }
     WArgs wa;
     wa.wpart = tb.wpart;
     wa.nsplit = nsplit_eff;
@@ -466,6 +472,23 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     u.xoff = vcols;
     u.wp = tb.wp;
     u.nxpad = v.nxpad;
+    const bool split = ev_first && !narrow && first_cols > 0 && first_cols <= NB && first_cols < ncA;
+    if (split) {
+        UpdArgs uf = u;
+        uf.ncA = first_cols;
+        uf.nB = 0;
+        const dim3 ug((unsigned)((rows + 63) / 64));
+        if (f32)
+            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<true>, ug, dim3(256), 0, s, uf);
+        else
+            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<false>, ug, dim3(256), 0, s, uf);
+        HQR_CK(hipGetLastError());
+        HQR_CK(hipEventRecord(ev_first, s));
+        u.ncA -= first_cols;
+        u.aoff += first_cols;
+        u.xoff += first_cols;
+    }
+    const int ncols_u = u.ncA + u.nB;
     if (narrow) {
         const dim3 ug((unsigned)((rows + 63) / 64));
         if (f32)
@@ -473,13 +496,14 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
         else
             HQR_LAUNCH(K_UPDATE, update_narrow_kernel<false>, ug, dim3(256), 0, s, u);
     } else {
-        const dim3 ug((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols + UPD_TILE - 1) / UPD_TILE);
+        const dim3 ug((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols_u + UPD_TILE - 1) / UPD_TILE);
         if (f32)
             HQR_LAUNCH(K_UPDATE, update_kernel<true>, ug, dim3(256), 0, s, u);
         else
             HQR_LAUNCH(K_UPDATE, update_kernel<false>, ug, dim3(256), 0, s, u);
     }
     HQR_CK(hipGetLastError());
+    if (ev_first && !split) HQR_CK(hipEventRecord(ev_first, s));
     return 0;
 }
 
@@ -550,10 +574,10 @@ static int launch_chol(const Plan &pl, const Work &w, double *A, int64_t lda, do
 }
 
 // Panel (c0, bw) by CholeskyQR2 + reconstruction, bottom rows not yet
-// finished.  With upd, the previous panel (start cp, width NB; X = V^T C in
-// w.xn, its T in Tprev) is first applied to this panel's columns.
+// finished.  With upd, the previous panel (start cp, width NB; W = T^T V^T C
+// transposed in w.xn) is first applied to this panel's columns.
 static int panel_passes(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
-                        double *Tout, bool upd, int cp, const double *Tprev, hipStream_t s)
+                        double *Tout, bool upd, int cp, hipStream_t s)
 {
     const int64_t rbase = upd ? cp : c0;
     const int parts = (int)((pl.m - c0 + 63) / 64);
@@ -567,8 +591,7 @@ static int panel_passes(const Plan &pl, const Work &w, double *A, int64_t lda, d
     g.upd = upd ? 1 : 0;
     g.cp = cp;
     g.up = up;
-    g.X = w.xn;
-    g.T = Tprev;
+    g.Wt = w.xn;
     g.gpart = w.gpart;
     g.mask = w.mask;
     g.flag = flag;
@@ -640,7 +663,7 @@ static int launch_narrow_vtx(const Plan &pl, const Work &w, double *A, int64_t l
 static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
                      double *Tout, hipStream_t s)
 {
-    int rc = panel_passes(pl, w, A, lda, up, c0, bw, pidx, Tout, false, 0, nullptr, s);
+    int rc = panel_passes(pl, w, A, lda, up, c0, bw, pidx, Tout, false, 0, s);
     if (!rc) rc = launch_finish(pl, w, A, lda, c0, bw, pidx, s);
     return rc;
 }
@@ -690,9 +713,12 @@ static bool lookahead_enabled()
 // With look-ahead (default), panel p+1 is factored on the caller's stream
 // while the rest of panel p's trailing update runs on a side stream:
 //   main: P(p) -> [a] -> N(p) (next panel's columns) -> P(p+1) -> wait r(p) -> N(p+1) -> ...
-//   side: wait a -> R(p) (all later columns and B) -> [r(p)]
-// N and R use separate W buffers; T alternates between two buffers by panel
-// parity (P(p+2) is issued after main has waited for R(p)).
+//   side: wait a -> R(p): V^T C and W for all later columns and B, the
+//         update of panel p+2's columns -> [r(p)] -> the update of the rest
+// r(p) marks all that N(p+1) reads, so N(p+1) and P(p+2) overlap the bulk
+// of R(p)'s update.  N and R use separate W buffers; T alternates between
+// two buffers by panel parity (P(p+2) is issued after main has waited for
+// r(p), which follows R(p)'s last read of T).
 static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, double *B, int64_t ldb,
                           int nB, hipStream_t s)
 {
@@ -741,7 +767,7 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
         //   passes of panel p+1, the first applying N(p) = (V, T^T X)
         // side: wait a -> R(p) (all later columns and B) -> [r(p)]
         const int bw0 = (int)std::min<int64_t>(pl.nb, n);
-        int rc = panel_passes(pl, w, A, lda, up, 0, bw0, 0, Tbuf[0], false, 0, nullptr, s);
+        int rc = panel_passes(pl, w, A, lda, up, 0, bw0, 0, Tbuf[0], false, 0, s);
         if (rc) return rc;
         for (int64_t c0 = 0; c0 < n; c0 += pl.nb) {
             const int bw = (int)std::min<int64_t>(pl.nb, n - c0);
@@ -757,18 +783,28 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
             if (rc) return rc;
             HQR_CK(hipEventRecord(ev_a, s));
             HQR_CK(hipStreamWaitEvent(ss->stream, ev_a, 0));
+            // R(p): the columns of panel p+2 first, then r(p) (all that
+            // narrow_vtx(p+1) reads), then the rest of the columns and B
             if (ncR + nB > 0) {
-                rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, true, ss->stream, false);
+                rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, true, ss->stream, false,
+                                       std::min(ncR, (int)pl.nb), ev_r);
                 if (rc) return rc;
+            } else {
+                HQR_CK(hipEventRecord(ev_r, ss->stream));
             }
             if (bw1 > 0) {
-                rc = launch_gred(pl, w, (int)((pl.m - c0 + 63) / 64), w.xn, false, nullptr, s);
+                XwArgs xa;
+                xa.gpart = w.gpart;
+                xa.parts = (int)((pl.m - c0 + 63) / 64);
+                xa.T = Tbuf[pidx & 1];
+                xa.Wt = w.xn;
+                HQR_LAUNCH(K_GRED, xw_reduce_kernel, dim3(NB), dim3(256), 0, s, xa);
+                HQR_CK(hipGetLastError());
                 if (!rc)
                     rc = panel_passes(pl, w, A, lda, up, (int)c1, bw1, pidx + 1, Tbuf[(pidx + 1) & 1], true, (int)c0,
-                                  Tbuf[pidx & 1], s);
+                                      s);
                 if (rc) return rc;
             }
-            HQR_CK(hipEventRecord(ev_r, ss->stream));
             pending_r = true;
         }
         HQR_CK(hipEventRecord(ev_join, ss->stream));
@@ -785,22 +821,27 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
         const int ncR = (int)std::max<int64_t>(0, n - c1 - bw1);
         TrailBufs bn = bufN, br = bufR;
         bn.T = br.T = Tbuf[pidx & 1];
-        // R(p) on the side stream: columns beyond the next panel, and B
+        // main: wait for r(p-1) (R(p-1) has updated the next panel's
+        // columns); issued before R(p) re-records ev_r
+        if (pending_r) HQR_CK(hipStreamWaitEvent(s, ev_r, 0));
+        // R(p) on the side stream: columns beyond the next panel, and B; the
+        // columns of panel p+2 first, then r(p), then the rest and B
         HQR_CK(hipEventRecord(ev_a, s));
         HQR_CK(hipStreamWaitEvent(ss->stream, ev_a, 0));
         if (ncR + nB > 0) {
-            rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, have_t, ss->stream, pl.f32);
+            rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, have_t, ss->stream, pl.f32,
+                                   std::min(ncR, (int)pl.nb), ev_r);
             if (rc) return rc;
+        } else {
+            HQR_CK(hipEventRecord(ev_r, ss->stream));
         }
-        // main: wait for R(p-1) (it updated this panel's next columns), then N(p), then P(p+1)
-        if (pending_r) HQR_CK(hipStreamWaitEvent(s, ev_r, 0));
+        // main: N(p), then P(p+1)
         if (bw1 > 0) {
             rc = apply_panel_block(pl, bn, A, lda, B, ldb, up, (int)c0, bw, 0, bw1, 0, have_t, s, pl.f32);
             if (rc) return rc;
             rc = do_panel(c1, bw1, pidx + 1);
             if (rc) return rc;
         }
-        HQR_CK(hipEventRecord(ev_r, ss->stream));
         pending_r = true;
     }
     // join: the caller's stream waits for the last side-stream work
