@@ -940,6 +940,66 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(GredArgs p)
     }
 }
 
+// ------------------------------------ Cholesky of a near-identity Gram matrix
+// For G = I + E with every |E_ij| <= CQR_SERIES_TAU, the upper factor is
+// R = I + X with X + X^T + X^T X = E.  Writing Phi(M) for the strict upper
+// part of a symmetric M plus half its diagonal, X0 = Phi(E) and
+// X1 = Phi(E - X0^T X0) satisfy ||X1 - X||_F <= 2 eps^3 (eps = ||E||_F <=
+// 64 tau), and R^{-1} = I - X1 + X1^2 up to eps^3: below 3e-22 for
+// tau = 2^-30, far under FP64 rounding.  Three block products on MFMA replace
+// the 64 sequential pivots.  The second CholeskyQR pass meets this bound
+// unless the panel's condition number exceeds about 1e3 (its Gram matrix is
+// then I + O(kappa^2 u)).
+constexpr double CQR_SERIES_TAU = 0x1p-30;
+
+// On entry (after a barrier) G holds I + E in full and X holds Phi(E).  On
+// exit G = R and X = R^{-1} (upper, zeros below), rdiag = diag(R); ends with
+// a barrier.
+HQR_DEV void chol_near_identity(double (*G)[LD65], double (*X)[LD65], double *rdiag, int lane, int w)
+{
+    const int i16 = lane & 15, kk = lane >> 4;
+    // P = X0^T X0 on the wave's upper blocks (w, s >= w): k-blocks 0..w
+    f64x4 acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+        if (s < w) continue;
+        for (int kb = 0; kb <= w; ++kb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 16 * kb + 4 * q + kk;
+                acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[k][16 * w + i16], X[k][16 * s + i16], acc[s], 0, 0, 0);
+            }
+        }
+    }
+    // X1 = Phi(E - P) on the wave's rows, kept in registers
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * w + 4 * q + kk, c = 16 * s + i16;
+            const double e = (G[r][c] - ((r == c) ? 1.0 : 0.0)) - acc[s][q];
+            acc[s][q] = (r > c) ? 0.0 : ((r == c) ? 0.5 * e : e);
+        }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 16 * w + 4 * q + kk, c = 16 * s + i16;
+            X[r][c] = acc[s][q];
+            G[r][c] = ((r == c) ? 1.0 : 0.0) + acc[s][q];
+            if (r == c) rdiag[r] = 1.0 + acc[s][q];
+        }
+    __syncthreads();
+    // X = I - X1 + X1^2 (X1^2 upper; the lower blocks keep X1's zeros)
+    f64x4 sq[4];
+    mm_upper_upper(sq, [&](int r, int c) { return X[r][c]; }, [&](int r, int c) { return X[r][c]; }, lane, w);
+    __syncthreads();
+    for_uu(sq, [&](int r, int c, double v) { X[r][c] = (((r == c) ? 1.0 : 0.0) - X[r][c]) + v; }, lane, w);
+    __syncthreads();
+}
+
 // --------------------------------------------------------- Cholesky kernel
 struct CholArgs {
     double *A;
@@ -975,10 +1035,14 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     __shared__ double M3[NB][LD65];
     __shared__ double DU[NB][17], DL[NB][17];
     __shared__ double gdiag[NB], rdiag[NB], sgn[NB], udiag[NB], upv[NB];
-    __shared__ int bad, structural_sh;
+    __shared__ int bad, structural_sh, nonid_sh;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int bw = p.bw;
-    if (tid == 0) structural_sh = 0;
+    if (tid == 0) {
+        structural_sh = 0;
+        nonid_sh = 0;
+        bad = 0;
+    }
     __shared__ double red[4][PW], wsh[NB], sc[4];
     const ExactArgs ex{p.A, p.lda, p.m, p.c0, bw, p.up, p.T};
     if (*((volatile int *)p.flag)) {
@@ -1011,13 +1075,21 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
             pin(ql[t]);
             pin(rl[t]);
         }
+        int far = 0;   // an entry of G - I beyond CQR_SERIES_TAU
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int idx = tid + 256 * t, i = idx / NB, j = idx % NB;
-            M0[i][j] = (i < bw && j < bw) ? gl[t] : 0.0;
+            const double g = (i < bw && j < bw) ? gl[t] : 0.0;
+            M0[i][j] = g;
             M2[i][j] = ql[t];
             M3[i][j] = rl[t];
+            if (p.pass == 2) {
+                const double e = g - ((i == j) ? 1.0 : 0.0);
+                far |= !(fabs(e) <= CQR_SERIES_TAU);
+                M1[i][j] = (i < j) ? e : ((i == j) ? 0.5 * e : 0.0);   // Phi(E)
+            }
         }
+        if (far) nonid_sh = 1;
     }
     int structural = 0;
     if (p.pass == 1 && tid == 0) {
@@ -1026,8 +1098,15 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         structural = ((all & need) != need);
         structural_sh = structural;
     }
+    __syncthreads();
+    // pass 2 of a full-width panel whose Gram matrix is within the series
+    // bound of the identity: no sequential pivots
+    const bool series = p.pass == 2 && bw == NB && !nonid_sh;
     HQR_TS();
-    chol64_dpp(M0, M1, bw, lane, w, CQR_RATIO, gdiag, rdiag, &bad);
+    if (series)
+        chol_near_identity(M0, M1, rdiag, lane, w);
+    else
+        chol64_dpp(M0, M1, bw, lane, w, CQR_RATIO, gdiag, rdiag, &bad);
     HQR_TS();
     if (tid == 0 && (bad || structural)) *((volatile int *)p.flag) = 1;
     __syncthreads();
@@ -1036,7 +1115,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         return;
     }
     if (bad || structural_sh) return;
-    inv_upper_levels(M1, M0, lane, w);                  // M1 = R^{-1} of this pass
+    if (!series) inv_upper_levels(M1, M0, lane, w);     // M1 = R^{-1} of this pass
     HQR_TS();
 
     if (p.pass == 1) {
@@ -1100,6 +1179,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
             if (r <= c && c < bw) p.T[r * NB + c] = -v / (upv[r] * upv[c]);
         }, lane, w);
     }
+    HQR_TS();
     mm_upper_upper(vacc, [&](int r, int c) { return M1[r][c]; }, [&](int r, int c) { return M0[r][c]; }, lane, w);
     __syncthreads();
     // M0 = V1 (its blocks below the diagonal are still U^{-1}'s zeros), M1 = R1^{-1}
@@ -1114,6 +1194,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         M1[idx / NB][idx % NB] = r1i[t];
     }
     __syncthreads();
+    HQR_TS();
     // W^{-1} = R1^{-1} V1 diag(up) -> global (zero beyond bw and below the diagonal)
     {
         f64x4 wacc[4];
@@ -1126,6 +1207,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
             if (c < bw) p.winv[r * NB + c] = v * upv[c];
         }, lane, w);
     }
+    HQR_TS();
     // stored tails of the top block: L[i][j] * up_j (strict lower)
     for (int idx = tid; idx < bw * bw; idx += 256) {
         const int c = idx / bw, r = idx % bw;

@@ -695,8 +695,11 @@ static SideStream *side_stream()
     SideStream &ss = g_side[dev];
     if (ss.device != dev) {
         if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        // the events only order the two streams of one device: no timing and
+        // no system-scope fence (kernel boundaries already release to the device)
         for (auto &e : ss.ev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
+                return nullptr;
         ss.device = dev;
     }
     return &ss;
