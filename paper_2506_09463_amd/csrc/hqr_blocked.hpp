@@ -196,18 +196,9 @@ struct VtxArgs {
     double *wpart;        // [nsplit][NB][nxpad]
 };
 
-// V element (global row gi >= c0, panel column c)
-HQR_DEV double v_elem(const double *A, int64_t lda, const double *up, int c0, int64_t gi, int c)
-{
-    const int64_t d = gi - c0;
-    if (d < c) return 0.0;
-    if (d == c) return up[c0 + c];
-    return HQR_AT(A, gi, c0 + c, lda);
-}
-
-// v_elem with both candidate loads issued unconditionally (no branch around
-// a load, so a tile's loads stay in flight together); gi and c must address
-// the matrix.
+// V element (global row gi >= c0, panel column c) with both candidate loads
+// issued unconditionally (no branch around a load, so a tile's loads stay in
+// flight together); gi and c must address the matrix.
 HQR_DEV double v_elem_nb(const double *A, int64_t lda, const double *up, int c0, int64_t gi, int c)
 {
     const double a = HQR_AT(A, gi, c0 + c, lda);
@@ -221,17 +212,6 @@ HQR_DEV double v_elem_nb(const double *A, int64_t lda, const double *up, int c0,
 // of loads issued before a group of pins waits once for all of them.
 HQR_DEV void pin_f64(double &v) { asm volatile("" : "+v"(v)); }
 
-HQR_DEV double x_elem(const VtxArgs &p, int64_t gi, int x)
-{
-    if (gi >= p.m || x >= p.nx) return 0.0;
-    if (p.with_v) {
-        if (x < p.bw) return v_elem(p.A, p.lda, p.up, p.c0, gi, x);
-        x -= p.bw;
-    }
-    if (x < p.ncA) return HQR_AT(p.A, gi, p.c0 + p.bw + p.aoff + x, p.lda);
-    return HQR_AT(p.B, gi, x - p.ncA, p.ldb);
-}
-
 // grid: (ceil(nx/128), nsplit); 256 threads.  Output tile: 64 reflectors x
 // 128 X columns over the rows of one split.  Wave w owns reflector rows
 // [16w, 16w+16) and all eight 16-column tiles.  Row chunks of KC rows are
@@ -240,9 +220,16 @@ HQR_DEV double x_elem(const VtxArgs &p, int64_t gi, int x)
 constexpr int VTX_COLS = 128;
 
 // F32: operands rounded to FP32, FP32 MFMA with FP32 accumulation (the
-// partial sums are stored widened to FP64).
-template <bool F32>
-__global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
+// partial sums are stored widened to FP64).  WITHV: the first bw X columns
+// are the panel's own V columns (the per-column panel mode forms V^T V there).
+//
+// Register budget: the prefetch loads are unconditional, with rows and
+// columns clamped into the matrix and column addresses formed at each fetch
+// (no per-thread pointer tables); the rows past the split, the columns past
+// nx and the triangle of V near the pivot rows are applied by selects when
+// the chunk is stored.  This keeps two waves per SIMD.
+template <bool F32, bool WITHV>
+__global__ void __launch_bounds__(256, 2) vtx_kernel(VtxArgs p)
 {
     __shared__ double Vs[KC][NB + 1];
     __shared__ double Xs[KC][VTX_COLS + 1];
@@ -259,62 +246,64 @@ __global__ void __launch_bounds__(256) vtx_kernel(VtxArgs p)
         acc32[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     }
 
-    // staging layout: thread t loads rows (t % KC) of columns t / KC + 8 q
+    // staging layout: thread t loads row t % KC of V columns t / KC + 8 q
+    // and of X columns x0 + t / KC + 8 q
     constexpr int VPT = KC * NB / 256;       // V elements per thread
     constexpr int XPT = KC * VTX_COLS / 256; // X elements per thread
     const int sr = tid % KC, sc = tid / KC;  // sc in [0, 8)
+    const int bwm = p.bw - 1;
+    double upq[VPT];                         // up of this thread's V columns
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) upq[q] = p.up[p.c0 + min(sc + 8 * q, bwm)];
     double vreg[VPT], xreg[XPT];
-    // column pointers (nullptr: zero column); a column flagged in vmask is a
-    // V column and is read through the triangle mask near the pivot rows
-    const double *vcol[VPT];
-    const double *xcol[XPT];
-    unsigned xvmask = 0u;
-#pragma unroll
-    for (int q = 0; q < VPT; ++q) {
-        const int c = sc + 8 * q;
-        vcol[q] = (c < p.bw) ? p.A + (size_t)(p.c0 + c) * p.lda : nullptr;
-    }
-#pragma unroll
-    for (int q = 0; q < XPT; ++q) {
-        int x = x0 + sc + 8 * q;
-        const double *ptr = nullptr;
-        if (x < p.nx) {
-            if (p.with_v && x < p.bw) {
-                ptr = p.A + (size_t)(p.c0 + x) * p.lda;
-                xvmask |= 1u << q;
-            } else {
-                if (p.with_v) x -= p.bw;
-                ptr = (x < p.ncA) ? p.A + (size_t)(p.c0 + p.bw + p.aoff + x) * p.lda : p.B + (size_t)(x - p.ncA) * p.ldb;
-            }
-        }
-        xcol[q] = ptr;
-    }
-    const int64_t tri_end = (int64_t)p.c0 + p.bw; // rows below need no mask
     auto fetch = [&](int64_t r0) {
-        const int64_t gi = r0 + sr;
-        const bool ok = gi < r_end;
-        if (r0 < tri_end) {
+        const int64_t gi0 = r0 + sr;
+        const int64_t gi = (gi0 < r_end) ? gi0 : r_end - 1;
 #pragma unroll
-            for (int q = 0; q < VPT; ++q) {
-                const int c = sc + 8 * q;
-                vreg[q] = (ok && vcol[q]) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : 0.0;
+        for (int q = 0; q < VPT; ++q) vreg[q] = HQR_AT(p.A, gi, p.c0 + min(sc + 8 * q, bwm), p.lda);
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+            const int x = min(x0 + sc + 8 * q, p.nx - 1);
+            const double *col;
+            if (WITHV && x < p.bw) {
+                col = p.A + (size_t)(p.c0 + x) * p.lda;
+            } else {
+                const int xa = WITHV ? x - p.bw : x;
+                col = (xa < p.ncA) ? p.A + (size_t)(p.c0 + p.bw + p.aoff + xa) * p.lda
+                                   : p.B + (size_t)(xa - p.ncA) * p.ldb;
             }
+            xreg[q] = __builtin_nontemporal_load(col + gi);
+        }
+    };
+    // waits for the chunk's loads, then zeroes what lies outside and applies
+    // the triangle of V (row offset d from the panel's first row)
+    auto finish = [&](int64_t r0) {
 #pragma unroll
-            for (int q = 0; q < XPT; ++q) {
-                const int c = x0 + sc + 8 * q;
-                double v = 0.0;
-                if (ok && xcol[q]) v = ((xvmask >> q) & 1u) ? v_elem(p.A, p.lda, p.up, p.c0, gi, c) : xcol[q][gi];
-                xreg[q] = v;
-            }
-        } else {
+        for (int q = 0; q < VPT; ++q) pin_f64(vreg[q]);
 #pragma unroll
-            for (int q = 0; q < VPT; ++q) vreg[q] = (ok && vcol[q]) ? vcol[q][gi] : 0.0;
+        for (int q = 0; q < XPT; ++q) pin_f64(xreg[q]);
+        const int64_t gi0 = r0 + sr;
+        const bool ok = gi0 < r_end;
+        const int64_t d = gi0 - p.c0;
 #pragma unroll
-            for (int q = 0; q < XPT; ++q) xreg[q] = (ok && xcol[q]) ? __builtin_nontemporal_load(&xcol[q][gi]) : 0.0;
+        for (int q = 0; q < VPT; ++q) {
+            const int c = sc + 8 * q;
+            const double v = (d < c) ? 0.0 : ((d == c) ? upq[q] : vreg[q]);
+            vreg[q] = (ok && c < p.bw) ? v : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < XPT; ++q) {
+            const int x = x0 + sc + 8 * q;
+            // WITHV: X column x < bw is V column x, held by this thread as
+            // vreg[q] (x < 64 only in tile 0, where x = sc + 8 q)
+            double v = xreg[q];
+            if (WITHV && q < VPT && x < p.bw) v = vreg[q < VPT ? q : 0];
+            xreg[q] = (ok && x < p.nx) ? v : 0.0;
         }
     };
     if (r_begin < r_end) fetch(r_begin);
     for (int64_t r0 = r_begin; r0 < r_end; r0 += KC) {
+        finish(r0);
 #pragma unroll
         for (int q = 0; q < VPT; ++q) Vs[sr][sc + 8 * q] = vreg[q];
 #pragma unroll

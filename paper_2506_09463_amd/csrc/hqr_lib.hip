@@ -416,10 +416,18 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     v.split_rows = rup((rows + nsplit - 1) / nsplit, KC);
     const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
     v.wpart = tb.wpart;
-    if (f32)
-        HQR_LAUNCH(K_VTX, vtx_kernel<true>, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
-    else
-        HQR_LAUNCH(K_VTX, vtx_kernel<false>, dim3(ntiles, nsplit_eff), dim3(256), 0, s, v);
+    const dim3 vg(ntiles, nsplit_eff);
+    if (v.with_v) {
+        if (f32)
+            HQR_LAUNCH(K_VTX, (vtx_kernel<true, true>), vg, dim3(256), 0, s, v);
+        else
+            HQR_LAUNCH(K_VTX, (vtx_kernel<false, true>), vg, dim3(256), 0, s, v);
+    } else {
+        if (f32)
+            HQR_LAUNCH(K_VTX, (vtx_kernel<true, false>), vg, dim3(256), 0, s, v);
+        else
+            HQR_LAUNCH(K_VTX, (vtx_kernel<false, false>), vg, dim3(256), 0, s, v);
+    }
     HQR_CK(hipGetLastError());
 
     if (!have_t) {
