@@ -37,14 +37,15 @@ PEAK_HBM_GBS = 8000.0
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled by the
 # same counters on a 1 GiB device copy (x2.0 and x1.0).  Valid only for the
 # kernel sources they were taken on (SHA-256 over csrc/); otherwise the
-# roofline's traffic is null.
+# roofline's traffic is null.  A class's figure averages over all its
+# launches (update: the 64-column launch for panel p+2 and the bulk launch;
+# gram_reduce: the two Gram reductions and the X/W reduction).
 HBM_TRAFFIC = {
-    "csrc_sha256": "a20368ab4138c8e4d0d55e27e178d8cf119939d750ce8207a9f592b09577ba7f",
-    "per_launch_bytes": {"cqr_chol": [159805, 82176], "update": [145513366, 111204763],
-                         "vtx": [131437999, 16726016], "wsolve": [16891788, 1034240], "trsv": [68612243, 34816],
-                         "cqr_gram1": [7004228, 6294032], "cqr_gram2": [3523601, 3194880],
-                         "gram_reduce": [3218567, 32779], "narrow_vtx": [6762588, 6324224],
-                         "cqr_finish": [2426804, 2097152]},
+    "csrc_sha256": "5e979bca1cbf21d66b3fe971cdb7eb12a2b3ace724731c36100b15da2c6ff804",
+    "per_launch_bytes": {"update": [73640712, 55165361], "cqr_chol": [198204, 82176], "vtx": [130910848, 16726016],
+                         "wsolve": [16364746, 1001984], "trsv": [68614779, 34816], "cqr_gram1": [6725994, 6294032],
+                         "cqr_gram2": [3516432, 3194880], "gram_reduce": [3316513, 32779],
+                         "narrow_vtx": [6760540, 6324224], "cqr_finish": [2426803, 2097152]},
 }
 
 
