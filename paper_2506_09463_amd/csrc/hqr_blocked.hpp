@@ -212,6 +212,27 @@ HQR_DEV double v_elem_nb(const double *A, int64_t lda, const double *up, int c0,
 // of loads issued before a group of pins waits once for all of them.
 HQR_DEV void pin_f64(double &v) { asm volatile("" : "+v"(v)); }
 
+// A 64 x 64 row-major matrix from global memory into LDS (transposed when
+// TRANS), by 256 threads: a thread's 16 loads are all issued before the first
+// is waited for (a plain copy loop waits on each load in turn).
+template <bool TRANS, int LD>
+HQR_DEV void ld64_lds(double (*M)[LD], const double *src, int tid)
+{
+    double v[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = src[tid + 256 * t];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pin_f64(v[t]);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int idx = tid + 256 * t;
+        if (TRANS)
+            M[idx % NB][idx / NB] = v[t];
+        else
+            M[idx / NB][idx % NB] = v[t];
+    }
+}
+
 // grid: (ceil(nx/128), nsplit); 256 threads.  Output tile: 64 reflectors x
 // 128 X columns over the rows of one split.  Wave w owns reflector rows
 // [16w, 16w+16) and all eight 16-column tiles.  Row chunks of KC rows are
@@ -417,7 +438,7 @@ __global__ void __launch_bounds__(256) wsolve_kernel(WArgs p)
     const int tid = threadIdx.x;
     const int xb = p.xoff + blockIdx.x * WS_COLS;
     const int xe = p.xoff + p.ncols;
-    for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx / NB][idx % NB] = p.T[idx];
+    ld64_lds<false>(Ts, p.T, tid);
     // 1024 partial sums: thread t reduces elements (i = t / 4 + 64 q?) -- four per thread
 #pragma unroll
     for (int e4 = 0; e4 < 4; ++e4) {
@@ -457,7 +478,7 @@ __global__ void __launch_bounds__(256) wsolve_narrow_kernel(WArgs p)
     const int i = tid / WSN_COLS, c = tid % WSN_COLS;
     const int x = p.xoff + blockIdx.x * WSN_COLS + c;
     const int xe = p.xoff + p.ncols;
-    for (int idx = tid; idx < NB * NB; idx += 256) Ts[idx / NB][idx % NB] = p.T[idx];
+    ld64_lds<false>(Ts, p.T, tid);
     double s = 0.0;
     if (i < p.bw && x < xe) {
         const double *src = p.wpart + (size_t)i * p.nxpad + x;

@@ -565,16 +565,19 @@ HQR_DEV void for_uu(const f64x4 (&acc)[4], F f, int lane, int w)
 // columns >= ncol.  256 threads; the loads are unconditional (clamped into
 // the matrix, zeroed afterwards), so all 16 of a thread are in flight
 // together instead of each waiting behind its own branch.
-HQR_DEV void load_tile(double (*M)[LD65], const double *A, int64_t lda, int64_t m, int64_t r0, int c0, int ncol,
-                       int tid)
+HQR_DEV void tile_issue(double (&v)[16], const double *A, int64_t lda, int64_t m, int64_t r0, int c0, int ncol,
+                        int tid)
 {
-    double v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int idx = tid + 256 * q, c = idx / 64, r = idx % 64;
         const int64_t gi = r0 + r;
         v[q] = HQR_AT(A, (gi < m) ? gi : m - 1, c0 + ((c < ncol) ? c : 0), lda);
     }
+}
+
+HQR_DEV void tile_store(double (*M)[LD65], double (&v)[16], int64_t m, int64_t r0, int ncol, int tid)
+{
 #pragma unroll
     for (int q = 0; q < 16; ++q) pin_f64(v[q]);
 #pragma unroll
@@ -586,10 +589,11 @@ HQR_DEV void load_tile(double (*M)[LD65], const double *A, int64_t lda, int64_t 
 
 // M[r][c] = V[r0 + r][c] of the panel starting at cv (width NB; unit lower
 // triangle with up on the diagonal in its top block), zero for rows >= m.
-HQR_DEV void load_vtile(double (*M)[LD65], const double *A, int64_t lda, const double *up, int64_t m, int64_t r0,
-                        int cv, int tid)
+// The issue half loads A's entries and up; the store half applies the
+// triangle.
+HQR_DEV void vtile_issue(double (&v)[16], double (&u)[16], const double *A, int64_t lda, const double *up, int64_t m,
+                         int64_t r0, int cv, int tid)
 {
-    double v[16], u[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int idx = tid + 256 * q, c = idx / 64, r = idx % 64;
@@ -597,6 +601,10 @@ HQR_DEV void load_vtile(double (*M)[LD65], const double *A, int64_t lda, const d
         v[q] = HQR_AT(A, (gi < m) ? gi : m - 1, cv + c, lda);
         u[q] = up[cv + c];
     }
+}
+
+HQR_DEV void vtile_store(double (*M)[LD65], double (&v)[16], double (&u)[16], int64_t m, int64_t r0, int cv, int tid)
+{
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         pin_f64(v[q]);
@@ -608,6 +616,29 @@ HQR_DEV void load_vtile(double (*M)[LD65], const double *A, int64_t lda, const d
         const int64_t d = r0 + r - cv;   // row offset from the panel's first row
         const double e = (d < c) ? 0.0 : ((d == c) ? u[q] : v[q]);
         M[r][c] = (r0 + r < m) ? e : 0.0;
+    }
+}
+
+// A 64 x 64 row-major matrix into LDS in two halves (transposed when TRANS),
+// so that its loads can be issued together with a tile's.
+HQR_DEV void mat64_issue(double (&v)[16], const double *src, int tid)
+{
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = src[tid + 256 * t];
+}
+
+template <bool TRANS>
+HQR_DEV void mat64_store(double (*M)[LD65], double (&v)[16], int tid)
+{
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pin_f64(v[t]);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int idx = tid + 256 * t;
+        if (TRANS)
+            M[idx % NB][idx / NB] = v[t];
+        else
+            M[idx / NB][idx % NB] = v[t];
     }
 }
 
@@ -810,11 +841,20 @@ __global__ void __launch_bounds__(256) cqr_gram1_kernel(Gram1Args p)
     const int64_t r0 = rbase + 64 * (int64_t)t;
     const bool flagged = *((volatile int *)p.flag) != 0;
     if (tid == 0) msk = 0ull;
-    // M0 = C tile (panel columns); with the update M1 = V tile, M2 = W
-    load_tile(M0, p.A, p.lda, p.m, r0, p.c0, bw, tid);
-    if (p.upd) {
-        load_vtile(M1, p.A, p.lda, p.up, p.m, r0, p.cp, tid);
-        for (int idx = tid; idx < NB * NB; idx += 256) M2[idx % NB][idx / NB] = p.Wt[idx];
+    // M0 = C tile (panel columns); with the update M1 = V tile, M2 = W; all
+    // loads are issued before the first wait
+    {
+        double cv[16], vv[16], uv[16], wv[16];
+        tile_issue(cv, p.A, p.lda, p.m, r0, p.c0, bw, tid);
+        if (p.upd) {
+            vtile_issue(vv, uv, p.A, p.lda, p.up, p.m, r0, p.cp, tid);
+            mat64_issue(wv, p.Wt, tid);
+        }
+        tile_store(M0, cv, p.m, r0, bw, tid);
+        if (p.upd) {
+            vtile_store(M1, vv, uv, p.m, r0, p.cp, tid);
+            mat64_store<true>(M2, wv, tid);
+        }
     }
     __syncthreads();
     if (p.upd) {
@@ -872,8 +912,13 @@ __global__ void __launch_bounds__(256) cqr_gram2_kernel(Gram2Args p)
     if (*((volatile int *)p.flag)) return;
     const int t = blockIdx.x;
     const int64_t r0 = (int64_t)p.c0 + 64 * (int64_t)t;
-    load_tile(X, p.A, p.lda, p.m, r0, p.c0, p.bw, tid);
-    for (int idx = tid; idx < NB * NB; idx += 256) Ri[idx / NB][idx % NB] = p.r1inv[idx];
+    {
+        double xv[16], rv[16];
+        tile_issue(xv, p.A, p.lda, p.m, r0, p.c0, p.bw, tid);
+        mat64_issue(rv, p.r1inv, tid);
+        tile_store(X, xv, p.m, r0, p.bw, tid);
+        mat64_store<false>(Ri, rv, tid);
+    }
     __syncthreads();
     mm64(Y, X, Ri, lane, w);
     __syncthreads();
@@ -1236,8 +1281,13 @@ __global__ void __launch_bounds__(256) cqr_finish_kernel(FinArgs p)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (*((volatile int *)p.flag)) return;
     const int64_t r0 = (int64_t)p.c0 + p.bw + (int64_t)blockIdx.x * 64;
-    for (int idx = tid; idx < NB * NB; idx += 256) Wi[idx / NB][idx % NB] = p.winv[idx];
-    load_tile(X, p.A, p.lda, p.m, r0, p.c0, p.bw, tid);
+    {
+        double wv[16], xv[16];
+        mat64_issue(wv, p.winv, tid);
+        tile_issue(xv, p.A, p.lda, p.m, r0, p.c0, p.bw, tid);
+        mat64_store<false>(Wi, wv, tid);
+        tile_store(X, xv, p.m, r0, p.bw, tid);
+    }
     __syncthreads();
     mm64(Y, X, Wi, lane, w);
     __syncthreads();
@@ -1278,11 +1328,22 @@ __global__ void __launch_bounds__(256) narrow_vtx_kernel(NarrowArgs p)
     const bool fin = (t > 0) && !flagged;
     // M0 = V rows (top block: unit lower with up on the diagonal), or A_bot;
     // M2 = C; M1 = W^{-1} when finishing
-    if (t == 0) load_vtile(M0, p.A, p.lda, p.up, p.m, r0, p.c0, tid);
-    else load_tile(M0, p.A, p.lda, p.m, r0, p.c0, NB, tid);
-    load_tile(M2, p.A, p.lda, p.m, r0, p.c0 + NB, p.nc, tid);
-    if (fin)
-        for (int idx = tid; idx < NB * NB; idx += 256) M1[idx / NB][idx % NB] = p.winv[idx];
+    {
+        // the V/A_bot tile and up are loaded alike (the triangle is applied
+        // when t == 0), W^{-1} always: every load is issued before the first wait
+        double av[16], uv[16], cv[16], wv[16];
+        vtile_issue(av, uv, p.A, p.lda, p.up, p.m, r0, p.c0, tid);
+        tile_issue(cv, p.A, p.lda, p.m, r0, p.c0 + NB, p.nc, tid);
+        mat64_issue(wv, p.winv, tid);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) pin_f64(wv[q]);   // keeps its loads out of the conditional store
+        if (t == 0)
+            vtile_store(M0, av, uv, p.m, r0, p.c0, tid);
+        else
+            tile_store(M0, av, p.m, r0, NB, tid);
+        tile_store(M2, cv, p.m, r0, p.nc, tid);
+        if (fin) mat64_store<false>(M1, wv, tid);
+    }
     __syncthreads();
     double (*V)[LD65] = M0;
     if (fin) {
