@@ -1388,7 +1388,9 @@ __global__ void __launch_bounds__(256) narrow_vtx_kernel(NarrowArgs p)
 // Workgroup j: column j of X = sum of the transposed partials of
 // narrow_vtx_kernel (fixed order: thread (i, g4) sums q = g4, g4 + 4, ..;
 // the quarters added 0..3), then column j of W = T^T X (T upper triangular,
-// W[i][j] = sum_{l <= i} T[l][i] X[l][j]), stored transposed (Wt[j][i]).
+// W[i][j] = sum_{l <= i} T[l][i] X[l][j]; thread (i, g4) takes l in
+// [16 g4, 16 g4 + 16), the quarters added 0..3), stored transposed
+// (Wt[j][i]).  Under 64 VGPRs, so it can start beside two bulk waves per SIMD.
 struct XwArgs {
     const double *gpart;      // [parts][NB][NB], [q][j][i]
     int parts;
@@ -1419,17 +1421,20 @@ __global__ void __launch_bounds__(256) xw_reduce_kernel(XwArgs p)
     __syncthreads();
     if (tid < 64) xc[i] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
     __syncthreads();
-    if (tid < 64) {
-        double tcol[NB];
+    double tl[16];
 #pragma unroll
-        for (int l = 0; l < NB; ++l) tcol[l] = p.T[l * NB + i];
+    for (int u = 0; u < 16; ++u) tl[u] = p.T[(16 * g4 + u) * NB + i];
 #pragma unroll
-        for (int l = 0; l < NB; ++l) pin_f64(tcol[l]);
-        double wv = 0.0;
+    for (int u = 0; u < 16; ++u) pin_f64(tl[u]);
+    double wv = 0.0;
 #pragma unroll
-        for (int l = 0; l < NB; ++l) wv = (l <= i) ? fma(tcol[l], xc[l], wv) : wv;
-        p.Wt[e] = wv;
+    for (int u = 0; u < 16; ++u) {
+        const int l = 16 * g4 + u;
+        wv = (l <= i) ? fma(tl[u], xc[l], wv) : wv;
     }
+    part[g4][i] = wv;
+    __syncthreads();
+    if (tid < 64) p.Wt[e] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
 }
 
 } // namespace hqr

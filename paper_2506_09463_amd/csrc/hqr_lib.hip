@@ -383,9 +383,12 @@ struct TrailBufs {
 // With ev_first: the first `first_cols` A columns (at most 64) are updated by
 // a launch of their own, ev_first is recorded on s after it, and the rest
 // follows (ev_first is recorded at the end when there is nothing to split).
+// vtx_wg_cap > 0 bounds the V^T C grid (fewer row splits), leaving CUs free
+// for work on another stream.
 static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int64_t lda, double *B, int64_t ldb,
                              const double *up, int c0, int bw, int aoff, int ncA, int nB, bool have_t,
-                             hipStream_t s, bool f32 = false, int first_cols = 0, hipEvent_t ev_first = nullptr)
+                             hipStream_t s, bool f32 = false, int first_cols = 0, hipEvent_t ev_first = nullptr,
+                             int vtx_wg_cap = 0)
 {
     const int64_t rows = pl.m - c0;
     VtxArgs v;
@@ -412,7 +415,9 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     if (narrow) v.nxpad = VTX_COLS;
     const int nsplit = narrow ? std::max(1, std::min<int>((int)std::min<int64_t>(64, rows / 128),
                                                            pl.nsplit_max * pl.nxpad / VTX_COLS))
-                              : pick_nsplit(rows, ntiles, pl.nsplit_max);
+                              : pick_nsplit(rows, ntiles,
+                                            vtx_wg_cap > 0 ? std::max(1, std::min(pl.nsplit_max, vtx_wg_cap / ntiles))
+                                                           : pl.nsplit_max);
     v.split_rows = rup((rows + nsplit - 1) / nsplit, KC);
     const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
     v.wpart = tb.wpart;
@@ -797,8 +802,10 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
             // R(p): the columns of panel p+2 first, then r(p) (all that
             // narrow_vtx(p+1) reads), then the rest of the columns and B
             if (ncR + nB > 0) {
+                // late panels, where the main chain is the longer one: V^T C
+                // on at most half the CUs so the chain's kernels find free ones
                 rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, true, ss->stream, false,
-                                       std::min(ncR, (int)pl.nb), ev_r);
+                                       std::min(ncR, (int)pl.nb), ev_r, (ncR + nB <= 2048) ? 128 : 0);
                 if (rc) return rc;
             } else {
                 HQR_CK(hipEventRecord(ev_r, ss->stream));
