@@ -861,21 +861,35 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
     for (int c = 0; c < NR; ++c) part[g][lane][c] = acc[c];
     __syncthreads();
     if (g == 0) {
+        // the substitution runs fully unrolled on registers: lane l holds its
+        // row (column when TRANS) of the diagonal block and 1/R_ll, so a step
+        // is two lane reads, a multiply and an FMA (no LDS access on the
+        // dependency chain)
+        double rowv[64];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) rowv[i] = TRANS ? Rd[i][lane] : Rd[lane][i];
+        const double rl = (lane < nr) ? rinv[lane] : 0.0;
         for (int c = 0; c < nrhs && c < NR; ++c) {
             double t = 0.0;
             if (lane < nr)
                 t = accs[lane][c] - (((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c]);
             if (TRANS) {
-                for (int i = 0; i < nr; ++i) {
-                    const double xi = readlane_f64(t, i) * rinv[i];
-                    if (lane > i && lane < nr) t = fma(-Rd[i][lane], xi, t);
-                    if (lane == i) t = xi;
+#pragma unroll
+                for (int i = 0; i < 64; ++i) {
+                    if (i < nr) {
+                        const double xi = readlane_f64(t, i) * readlane_f64(rl, i);
+                        if (lane > i && lane < nr) t = fma(-rowv[i], xi, t);
+                        if (lane == i) t = xi;
+                    }
                 }
             } else {
-                for (int i = nr - 1; i >= 0; --i) {
-                    const double xi = readlane_f64(t, i) * rinv[i];
-                    if (lane < i) t = fma(-Rd[lane][i], xi, t);
-                    if (lane == i) t = xi;
+#pragma unroll
+                for (int i = 63; i >= 0; --i) {
+                    if (i < nr) {
+                        const double xi = readlane_f64(t, i) * readlane_f64(rl, i);
+                        if (lane < i) t = fma(-rowv[i], xi, t);
+                        if (lane == i) t = xi;
+                    }
                 }
             }
             accs[lane][c] = t;
