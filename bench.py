@@ -41,11 +41,11 @@ PEAK_HBM_GBS = 8000.0
 # launches (update: the 64-column launch for panel p+2 and the bulk launch;
 # gram_reduce: the two Gram reductions and the X/W reduction).
 HBM_TRAFFIC = {
-    "csrc_sha256": "5e979bca1cbf21d66b3fe971cdb7eb12a2b3ace724731c36100b15da2c6ff804",
-    "per_launch_bytes": {"update": [73640712, 55165361], "cqr_chol": [198204, 82176], "vtx": [130910848, 16726016],
-                         "wsolve": [16364746, 1001984], "trsv": [68614779, 34816], "cqr_gram1": [6725994, 6294032],
-                         "cqr_gram2": [3516432, 3194880], "gram_reduce": [3316513, 32779],
-                         "narrow_vtx": [6760540, 6324224], "cqr_finish": [2426803, 2097152]},
+    "csrc_sha256": "5a2feed2b69037fc64b6868801cb8ee49c29a7575a31a878b490a4c338392aa0",
+    "per_launch_bytes": {"update": [73643102, 55164431], "cqr_chol": [195224, 82176], "vtx": [130921591, 15503360],
+                         "wsolve": [15216532, 1001984], "trsv": [68735751, 34816], "cqr_gram1": [6731404, 6294032],
+                         "cqr_gram2": [3531743, 3194880], "gram_reduce": [3295444, 32779],
+                         "narrow_vtx": [6770795, 6324224], "cqr_finish": [2447283, 2097152]},
 }
 
 

@@ -1079,7 +1079,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     __shared__ double M2[NB][LD65];
     __shared__ double M3[NB][LD65];
     __shared__ double DU[NB][17], DL[NB][17];
-    __shared__ double gdiag[NB], rdiag[NB], sgn[NB], udiag[NB], upv[NB];
+    __shared__ double gdiag[NB], rdiag[NB], sgn[NB], udiag[NB], upv[NB], rupv[NB];
     __shared__ int bad, structural_sh, nonid_sh;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int bw = p.bw;
@@ -1195,6 +1195,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
         const double rkk = sgn[tid] * rdiag[tid] * M3[tid][tid];  // diag of S R2 R1
         const double tau = -udiag[tid] * sgn[tid];                // = 1 + |pivot|
         upv[tid] = -tau * rkk;
+        rupv[tid] = 1.0 / upv[tid];   // nonzero: tau >= 1 and R_kk != 0 on this path
     }
     __syncthreads();
     // diagonal blocks of U^{-1} -> M0, of L^{-1} -> M3; then the rest
@@ -1221,7 +1222,7 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
             if (!(i <= j && j < bw)) p.T[idx] = 0.0;
         }
         for_uu(tacc, [&](int r, int c, double v) {
-            if (r <= c && c < bw) p.T[r * NB + c] = -v / (upv[r] * upv[c]);
+            if (r <= c && c < bw) p.T[r * NB + c] = -v * (rupv[r] * rupv[c]);
         }, lane, w);
     }
     HQR_TS();
@@ -1254,9 +1255,9 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     }
     HQR_TS();
     // stored tails of the top block: L[i][j] * up_j (strict lower)
-    for (int idx = tid; idx < bw * bw; idx += 256) {
-        const int c = idx / bw, r = idx % bw;
-        if (r > c) HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) = M2[r][c] * upv[c];
+    for (int idx = tid; idx < NB * NB; idx += 256) {
+        const int c = idx / NB, r = idx % NB;
+        if (r > c && r < bw) HQR_AT(p.A, (int64_t)p.c0 + r, p.c0 + c, p.lda) = M2[r][c] * upv[c];
     }
     if (tid < bw) p.up[p.c0 + tid] = upv[tid];
     HQR_TS();
