@@ -7,8 +7,9 @@
  *     reflector per column (Section 3, Alg. 2), keeping each reflector's
  *     leading component `up` and its tail below the diagonal (the pair
  *     (up, b) of Alg. 3, with b = up * R[k][k]);
- *   - qr_apply_qt applies Q^T to right-hand sides with those stored
- *     reflectors, without forming Q (Section 1);
+ *   - qr_apply_qt and qr_apply_q apply Q^T or Q to right-hand sides with
+ *     those stored reflectors, without forming Q (Section 1); qr_form_q
+ *     forms leading columns of Q explicitly;
  *   - qr_backsolve back-substitutes with R (abstract; Section 6 names the
  *     triangular solve as a kernel of the same solver);
  *   - qr_lsq_solve chains the three; qr_lsq_refine solves again with a
@@ -21,6 +22,12 @@
  *   - Calls are asynchronous on `stream` (0 = the null stream); outputs are
  *     valid after the stream is synchronized.  Calls never synchronize the
  *     host except where stated.
+ *   - Calls on different streams may run concurrently from different host
+ *     threads: the library keeps its per-stream state (the look-ahead's side
+ *     stream and events, the batched descriptor staging buffer) per caller
+ *     stream.  Calls on one stream from several host threads must be
+ *     serialized by the caller.  The tuning and profiling calls change
+ *     process-global state and are not thread-safe.
  *   - The caller owns every buffer.  `work`/`lwork` is an optional device
  *     workspace of at least hqr_workspace_size() bytes; with work == NULL the
  *     library takes a stream-ordered allocation (hipMallocAsync) and frees it
@@ -55,10 +62,12 @@ extern "C" {
 /* Device info codes (besides 0 and k+1 for a zero R[k][k]). */
 #define HQR_INFO_TIMEOUT (-2001) /* a bounded cross-workgroup wait expired;
                                      outputs are invalid                   */
-#define HQR_INFO_NOCONV  (1 << 29) /* mixed precision: refinement did not
-                                      converge; the FP64 fallback was used
-                                      and its result returned (OR-ed into
-                                      info together with any k+1)          */
+#define HQR_INFO_NOCONV  (1 << 29) /* refinement did not converge: the FP64
+                                      fallback was used and its result
+                                      returned (OR-ed into info together
+                                      with any k+1), or, with
+                                      HQR_OPT_NO_FALLBACK, x is the last
+                                      refinement iterate                   */
 
 /* Precision of the trailing-update contractions. */
 #define HQR_PREC_FP64  0 /* everything FP64                                  */
@@ -66,12 +75,23 @@ extern "C" {
                             accumulation, subtracted into FP64 storage;
                             reflector generation, R's diagonal, Q^T b and
                             the back-substitution stay FP64, then
-                            augmented-system refinement with FP64 residuals */
+                            refinement of the semi-normal equations with
+                            FP64 residuals of the original matrix          */
+
+/* hqr_opts.flags */
+#define HQR_OPT_NO_FALLBACK 1 /* refinement (mixed qr_lsq_solve, qr_lsq_refine):
+                                 never wait on the host; when some
+                                 right-hand side does not converge,
+                                 HQR_INFO_NOCONV is ORed into info on the
+                                 device and x is the last iterate (no FP64
+                                 fallback: the caller decides)           */
 
 typedef struct hqr_opts {
     int precision;   /* HQR_PREC_FP64 or HQR_PREC_MIXED                      */
-    double tol;      /* mixed: stop when ||dx|| <= tol * ||x|| (<= 0: 1e-13)  */
-    int max_iter;    /* mixed: refinement step limit (< 0: 10)                */
+    double tol;      /* refinement: converged when ||dx|| <= tol * ||x||
+                        (<= 0: 1e-13)                                        */
+    int max_iter;    /* refinement step limit (< 0: 10)                       */
+    int flags;       /* HQR_OPT_* bits (0: none)                              */
 } hqr_opts;
 
 /* Bytes of device workspace the calls below need for an m x n problem with
@@ -93,6 +113,24 @@ int qr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A,
                 int64_t lda, const double *up, double *B, int64_t ldb,
                 void *work, int64_t lwork, hipStream_t stream);
 
+/* B (m x nrhs, ldb >= max(1,m)) <- Q B = H_0 H_1 ... H_{n-1} B, using the
+ * output of qr_factor: the stored reflectors applied last to first (Section
+ * 1: SLSQP applies Q as well as Q^T from the stored reflectors, never forming
+ * Q).  Same arguments, workspace and errors as qr_apply_qt. */
+int qr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A,
+               int64_t lda, const double *up, double *B, int64_t ldb,
+               void *work, int64_t lwork, hipStream_t stream);
+
+/* Explicit Q: Q (m x k, 0 <= k <= m, ldq >= max(1,m), device) <- the leading
+ * k columns of Q = H_0 ... H_{n-1} from qr_factor's output (k = n: the thin
+ * Q with A = Q[:, 0:n] R; k = m: the full orthogonal Q).  Q is overwritten
+ * (its input is ignored).  Workspace: hqr_workspace_size(m, n, k, FP64)
+ * bytes, or NULL.  Returns 0 or -i (argument i invalid: m < 0, n outside
+ * [0, m], k outside [0, m], lda < m, ldq < m, null pointers). */
+int qr_form_q(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda,
+              const double *up, double *Q, int64_t ldq, void *work,
+              int64_t lwork, hipStream_t stream);
+
 /* B[0:n] (n x nrhs, ldb >= max(1,n)) <- R^{-1} B[0:n], R = upper triangle
  * of A (lda >= max(1,n)).  If some R[k][k] == 0, *info = smallest such k+1
  * and B is left unchanged; otherwise *info = 0. */
@@ -109,8 +147,18 @@ int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda,
  *     FP64 residuals of the refinement; resnorm is then ||b - A x||.
  *   info: device int (0, k+1 for a zero R[k][k], HQR_INFO_* flags);
  *   iters: device int or NULL, refinement steps taken (0 for FP64).
- *   The mixed form synchronizes `stream` with the host once per right-hand
- *   side (to read the convergence record), and so does qr_lsq_refine. */
+ *   Refinement (opt->tol, opt->max_iter) of every right-hand side: a column
+ *   is converged when ||dx|| <= tol ||x||, or when ||dx|| stops halving at or
+ *   below 1e-11 ||x|| (the rounding floor); corrections that stop halving
+ *   above that floor twice in a row, or max_iter steps without convergence,
+ *   mean no convergence.  A converged column's x is left as it is.
+ *   The mixed form synchronizes `stream` with the host once, after the
+ *   refinement, to read whether every column converged; without
+ *   convergence the problem is solved again by the FP64 path from the
+ *   restored inputs (A_orig, the original B) and HQR_INFO_NOCONV is ORed
+ *   into the info that solve reports.  With HQR_OPT_NO_FALLBACK in
+ *   opt->flags nothing waits on the host and there is no fallback (see
+ *   there).  qr_lsq_refine behaves the same way. */
 int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
                  double *up, double *B, int64_t ldb, double *resnorm,
                  const hqr_opts *opt, const double *A_orig, int64_t lda_orig,
@@ -124,10 +172,11 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
  * A (r = b - A_orig x, A_orig^T r, R^T z = A_orig^T r, R dx = z), as the
  * mixed form of qr_lsq_solve does (opt->tol, opt->max_iter; opt may be
  * NULL).  x ends in B[0:n]; resnorm (device, nrhs doubles, or NULL) gets
- * ||b - A_orig x||.  A and up are never modified.  Without convergence the
- * problem is solved in FP64 from a copy of A_orig (a stream-ordered
- * allocation of m*n doubles) and HQR_INFO_NOCONV is ORed into info; a zero
- * R[k][k] gives info = k+1.  iters (device int or NULL): steps taken. */
+ * ||b - A_orig x||.  A and up are never modified.  Convergence rule, host
+ * synchronization and HQR_OPT_NO_FALLBACK as for the mixed qr_lsq_solve;
+ * the FP64 fallback works on a copy of A_orig (a stream-ordered allocation
+ * of m*n doubles).  A zero R[k][k] gives info = k+1.  iters (device int or
+ * NULL): steps taken (max_iter without convergence). */
 int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A,
                   int64_t lda, const double *up, double *B, int64_t ldb,
                   double *resnorm, const hqr_opts *opt, const double *A_orig,

@@ -13,31 +13,12 @@
 // head passes the instance count.
 #pragma once
 
-#include "hqr_device.hpp"
+#include "hqr_args.hpp"
 
 namespace hqr {
 
-struct BatchDesc {
-    int64_t m, n, nrhs, lda, ldb;
-    double *A;
-    double *B;
-    double *up;
-    double *resnorm; // may be null
-    int64_t index;   // position in the caller's arrays (info slot)
-    int64_t factor;  // 1: factor A (B fused); 0: A, up hold a stored factorization
-};
 
-struct BatchArgs {
-    const BatchDesc *desc;
-    int count;
-    int *head;       // zero on entry
-    int *info;       // [count], caller order
-    int max_ntot;    // largest n + nrhs in the batch (<= BATCH_MAX_COLS)
-};
 
-constexpr int BATCH_MAX_ROWS = 4096;
-constexpr int BATCH_MAX_COLS = 2048;
-constexpr int BATCH_NW = 16;
 
 HQR_DEV double wave_sum(double v)
 {

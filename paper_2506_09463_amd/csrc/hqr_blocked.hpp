@@ -19,28 +19,14 @@
 // data, in the same order, by every workgroup.
 #pragma once
 
-#include "hqr_device.hpp"
+#include "hqr_args.hpp"
+
+#define HQR_HD __host__ __device__
+#include "hqr_refine_rule.hpp"
 
 namespace hqr {
 
-constexpr int NB = 64;          // panel width
-constexpr int PC_ROWS = 128;    // rows per workgroup in panel_col_kernel
-constexpr int PW = NB + 2;      // partial vector: dots, max|x|, #nonzero
-constexpr int KC = 32;          // rows per LDS chunk in vtc_kernel
 
-// ------------------------------------------------------------------ panel
-struct PanelArgs {
-    double *A;
-    int64_t lda;
-    int64_t m;        // rows of A
-    int c0;           // first column (and pivot row) of the panel
-    int bw;           // panel width (<= NB)
-    int k;            // launch index 0..bw
-    int nchunk;       // workgroups (row chunks of PC_ROWS rows from c0)
-    double *up;       // global up array (output for columns c0..c0+bw)
-    double *xbuf;     // [2][nchunk][PW] partials
-    double *pbuf;     // [2][NB] pivot rows
-};
 
 __global__ void __launch_bounds__(256) panel_col_kernel(PanelArgs p)
 {
@@ -176,25 +162,6 @@ __global__ void __launch_bounds__(256) panel_col_kernel(PanelArgs p)
     }
 }
 
-// ----------------------------------------------------- W = V^T X (partials)
-// X columns: [0, bw) = V itself (gives G = V^T V), then ncA trailing columns
-// of A starting at column c0+bw, then nB columns of B.
-struct VtxArgs {
-    const double *A;
-    int64_t lda;
-    const double *B;
-    int64_t ldb;
-    const double *up;
-    int64_t m;
-    int c0, bw;
-    int ncA, nB;          // trailing A columns, B columns
-    int aoff;             // first trailing A column is c0 + bw + aoff
-    int nx;               // bw + ncA + nB
-    int nxpad;            // row stride of the partial buffers
-    int64_t split_rows;   // rows per split (multiple of KC)
-    int with_v;           // include the bw V columns as X columns
-    double *wpart;        // [nsplit][NB][nxpad]
-};
 
 // V element (global row gi >= c0, panel column c) with both candidate loads
 // issued unconditionally (no branch around a load, so a tile's loads stay in
@@ -206,11 +173,6 @@ HQR_DEV double v_elem_nb(const double *A, int64_t lda, const double *up, int c0,
     const int64_t d = gi - c0;
     return (d < c) ? 0.0 : ((d == c) ? u : a);
 }
-
-// Forces v to be materialized here (empty asm that reads and writes it): a
-// load feeding it cannot be sunk into a later conditional block, so a group
-// of loads issued before a group of pins waits once for all of them.
-HQR_DEV void pin_f64(double &v) { asm volatile("" : "+v"(v)); }
 
 // A 64 x 64 row-major matrix from global memory into LDS (transposed when
 // TRANS), by 256 threads: a thread's 16 loads are all issued before the first
@@ -233,12 +195,6 @@ HQR_DEV void ld64_lds(double (*M)[LD], const double *src, int tid)
     }
 }
 
-// grid: (ceil(nx/128), nsplit); 256 threads.  Output tile: 64 reflectors x
-// 128 X columns over the rows of one split.  Wave w owns reflector rows
-// [16w, 16w+16) and all eight 16-column tiles.  Row chunks of KC rows are
-// staged in LDS ([row][col]); the next chunk is prefetched into registers
-// while the current one is multiplied.
-constexpr int VTX_COLS = 128;
 
 // F32: operands rounded to FP32, FP32 MFMA with FP32 accumulation (the
 // partial sums are stored widened to FP64).  WITHV: the first bw X columns
@@ -359,18 +315,6 @@ __global__ void __launch_bounds__(256, 2) vtx_kernel(VtxArgs p)
         }
 }
 
-// ------------------------------------------------- T from G = V^T V and tau
-// One workgroup.  tau_k = -1/(up_k R_kk) (0 for identity reflectors);
-// T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
-struct TArgs {
-    const double *A;
-    int64_t lda;
-    const double *up;
-    int c0, bw;
-    const double *wpart; // partials holding G in columns [0, bw)
-    int nsplit, nxpad;
-    double *T;           // [NB][NB] row-major T[i][j]
-};
 
 __global__ void __launch_bounds__(256) tfactor_kernel(TArgs p)
 {
@@ -417,19 +361,7 @@ __global__ void __launch_bounds__(256) tfactor_kernel(TArgs p)
     }
 }
 
-// ------------------------------------------------ W' = T^T (sum of partials)
-// grid: ceil(ncols/64) over the X columns that get updated (offset xoff).
-struct WArgs {
-    const double *wpart;
-    int nsplit, nxpad;
-    int xoff, ncols;      // updated X columns [xoff, xoff+ncols)
-    int bw;
-    const double *T;
-    double *wp;           // [NB][nxpad] row-major, same column indexing
-};
 
-// grid: ceil(ncols/WS_COLS); 256 threads, WS_COLS columns per workgroup.
-constexpr int WS_COLS = 16;
 
 __global__ void __launch_bounds__(256) wsolve_kernel(WArgs p)
 {
@@ -462,14 +394,15 @@ __global__ void __launch_bounds__(256) wsolve_kernel(WArgs p)
         const int x = xb + c;
         if (x >= xe) continue;
         double s = 0.0;
-        for (int l = 0; l <= i && l < p.bw; ++l) s += Ts[l][i] * Ws[l][c];
+        if (p.tmode == 0) {
+            for (int l = 0; l <= i && l < p.bw; ++l) s += Ts[l][i] * Ws[l][c];
+        } else {
+            for (int l = i; l < p.bw; ++l) s += Ts[i][l] * Ws[l][c];
+        }
         p.wp[(size_t)i * p.nxpad + x] = (i < p.bw) ? s : 0.0;
     }
 }
 
-// Narrow form (at most 64 columns, many row splits): 4 columns per
-// workgroup, thread (row i, column c) sums its partials 16 at a time.
-constexpr int WSN_COLS = 4;
 __global__ void __launch_bounds__(256) wsolve_narrow_kernel(WArgs p)
 {
     __shared__ double Ws[NB][WSN_COLS + 1];
@@ -490,29 +423,15 @@ __global__ void __launch_bounds__(256) wsolve_narrow_kernel(WArgs p)
     __syncthreads();
     if (x < xe) {
         double t = 0.0;
-        for (int l = 0; l <= i && l < p.bw; ++l) t += Ts[l][i] * Ws[l][c];
+        if (p.tmode == 0) {
+            for (int l = 0; l <= i && l < p.bw; ++l) t += Ts[l][i] * Ws[l][c];
+        } else {
+            for (int l = i; l < p.bw; ++l) t += Ts[i][l] * Ws[l][c];
+        }
         p.wp[(size_t)i * p.nxpad + x] = (i < p.bw) ? t : 0.0;
     }
 }
 
-// ---------------------------------------------------------- X <- X - V W'
-// grid: (ceil(rows/64), ceil(ncols/64)); 256 threads.  Tile 64 rows x 64
-// columns, computed transposed (D' = W'^T V^T) so each accumulator register
-// maps to 16 consecutive rows of one column.
-struct UpdArgs {
-    double *A;
-    int64_t lda;
-    double *B;
-    int64_t ldb;
-    const double *up;
-    int64_t m;
-    int c0, bw;
-    int ncA, nB;          // updated A columns start at c0+bw+aoff; then B columns
-    int aoff;
-    int xoff;             // X index of the first updated column in wp
-    const double *wp;     // [NB][nxpad]
-    int nxpad;
-};
 
 HQR_DEV double *col_ptr(const UpdArgs &p, int c)
 {
@@ -520,12 +439,6 @@ HQR_DEV double *col_ptr(const UpdArgs &p, int c)
     return p.B + (size_t)(c - p.ncA) * p.ldb;
 }
 
-// grid: (ceil(rows/128), ceil(ncols/128)); 256 threads.  Wave (wr, wc)
-// owns rows [128 bx + 64 wr, +64) x columns [128 by + 64 wc, +64) and keeps
-// that 64 x 64 block of X^T in 16 MFMA accumulators.  The fragments of W'
-// and V are read straight from global memory (L2): each fragment load is
-// four 128-byte segments.
-constexpr int UPD_TILE = 128;
 
 // F32: V and W' rounded to FP32, the product accumulated in FP32 by FP32
 // MFMA from zero, then subtracted from the FP64 trailing matrix.
@@ -745,25 +658,7 @@ __global__ void __launch_bounds__(256) diag_check_kernel(const double *A, int64_
     if (threadIdx.x == 0) *info = (first == 0x7fffffff) ? 0 : first;
 }
 
-// Blocked back-substitution R X = B[0:n].  Row blocks of 64; workgroup b
-// owns row block nblk-1-b, so every block it waits for belongs to a
-// workgroup dispatched before it.  A block is published by writing its x
-// values to B and then raising flags[block] (release); consumers acquire it.
-// The wait is bounded: on expiry the kernel records HQR_INFO_TIMEOUT.
-struct TrsvArgs {
-    const double *A;
-    int64_t lda;
-    double *B;
-    int64_t ldb;
-    int64_t n;
-    int nrhs;
-    int *flags;      // [nblk], zero on entry
-    int *info;       // read: nonzero -> nothing to do; written on timeout
-    int epoch;       // value a published flag holds
-    long spin_limit;
-};
 
-constexpr int TRSV_MAXRHS = 8;
 
 // Workgroup b owns row block b (64 rows; for TRANS, R^T x = b by forward
 // substitution and the blocks above it).  Everything that does not depend on
@@ -785,6 +680,7 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, g = tid >> 6;
     if (*((volatile int *)p.info) != 0) return;
+    if (p.active && *((volatile int *)p.active) == 0) return;
     const int nblk = (int)((p.n + 63) / 64);
     const int ib = TRANS ? (int)blockIdx.x : nblk - 1 - (int)blockIdx.x;
     const int64_t r0 = (int64_t)ib * 64;
@@ -942,65 +838,75 @@ __global__ void __launch_bounds__(256) resnorm_kernel(const double *B, int64_t l
     if (tid == 0) out[blockIdx.x] = gmx * sqrt(((ss[0] + ss[1]) + ss[2]) + ss[3]);
 }
 
-// r = b - A x  (FP64), one thread per row; x staged in LDS in chunks.
-__global__ void __launch_bounds__(256) resid_kernel(const double *A, int64_t lda, const double *b, const double *x,
-                                                    double *r, int64_t m, int64_t n)
+// ------------------------------------------------------------ refinement
+// r = b - A0 x for column blockIdx.y (FP64), one thread per row; x staged in
+// LDS in chunks.  Skipped for frozen columns unless `all`.
+__global__ void __launch_bounds__(256) resid_kernel(RefineArgs a, int all)
 {
     __shared__ double xs[1024];
+    const int c = blockIdx.y;
+    if (!all && (*((volatile int *)a.active) == 0 || a.stat[4 * c + 3])) return;
+    const double *x = a.X + (size_t)c * a.ldx;
+    const double *b = a.borig + (size_t)c * a.m;
+    double *r = a.rvec + (size_t)c * a.m;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double s = 0.0;
-    for (int64_t j0 = 0; j0 < n; j0 += 1024) {
-        const int64_t nj = min<int64_t>(1024, n - j0);
+    for (int64_t j0 = 0; j0 < a.n; j0 += 1024) {
+        const int64_t nj = min<int64_t>(1024, a.n - j0);
         __syncthreads();
         for (int64_t j = threadIdx.x; j < nj; j += 256) xs[j] = x[j0 + j];
         __syncthreads();
-        if (i < m)
-            for (int64_t j = 0; j < nj; ++j) s += HQR_AT(A, i, j0 + j, lda) * xs[j];
+        if (i < a.m)
+            for (int64_t j = 0; j < nj; ++j) s += HQR_AT(a.A0, i, j0 + j, a.lda0) * xs[j];
     }
-    if (i < m) r[i] = b[i] - s;
+    if (i < a.m) r[i] = b[i] - s;
 }
 
-// g = A^T r (FP64): one wave per column, lanes down the rows.
-__global__ void __launch_bounds__(256) gemvt_kernel(const double *A, int64_t lda, const double *r, double *g,
-                                                    int64_t m, int64_t n)
+// g = A0^T r for column blockIdx.y (FP64): one wave per column of A0, lanes
+// down the rows.
+__global__ void __launch_bounds__(256) gemvt_kernel(RefineArgs a)
 {
+    const int c = blockIdx.y;
+    if (*((volatile int *)a.active) == 0 || a.stat[4 * c + 3]) return;
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= n) return;
-    const double *aj = A + (size_t)j * lda;
+    if (j >= a.n) return;
+    const double *aj = a.A0 + (size_t)j * a.lda0;
+    const double *r = a.rvec + (size_t)c * a.m;
     double s = 0.0;
-    for (int64_t i = lane; i < m; i += 64) s += aj[i] * r[i];
+    for (int64_t i = lane; i < a.m; i += 64) s += aj[i] * r[i];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) g[j] = s;
+    if (lane == 0) a.gvec[(size_t)c * a.n + j] = s;
 }
 
-// One correction step of the semi-normal equations: x += dx.  Records in
-// stat[0] the first (1-based) step that converged: ||dx|| <= tol ||x||, or
-// ||dx|| stopped shrinking (more than half the previous ||dx||) at a level
-// below 1e-8 ||x|| (the corrections reached FP64 rounding).  stat[1] = 1
-// when the corrections stall above that level for two steps (failure).
-// st[0] keeps the previous ||dx||.  One workgroup.
-__global__ void __launch_bounds__(1024) csne_update_kernel(double *x, const double *dx, int64_t n, double tol,
-                                                           int step, int *stat, double *st)
+// One correction step for column blockIdx.x: x += dx, then the stopping rule
+// of hqr_refine_rule.hpp on ||dx|| and ||x||.  A column that converges or
+// fails is frozen (its x stays as it is) and leaves the active count.
+__global__ void __launch_bounds__(1024) csne_update_kernel(RefineArgs a, int step)
 {
     __shared__ double s1[16], s2[16];
+    const int c = blockIdx.x;
+    int *st = a.stat + 4 * c;
+    if (*((volatile int *)a.active) == 0 || st[3]) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double a = 0.0, b = 0.0;
-    for (int64_t j = tid; j < n; j += 1024) {
+    double *x = a.X + (size_t)c * a.ldx;
+    const double *dx = a.gvec + (size_t)c * a.n;
+    double sa = 0.0, sb = 0.0;
+    for (int64_t j = tid; j < a.n; j += 1024) {
         const double xn = x[j] + dx[j];
         x[j] = xn;
-        a += dx[j] * dx[j];
-        b += xn * xn;
+        sa += dx[j] * dx[j];
+        sb += xn * xn;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o);
-        b += __shfl_xor(b, o);
+        sa += __shfl_xor(sa, o);
+        sb += __shfl_xor(sb, o);
     }
     if (lane == 0) {
-        s1[w] = a;
-        s2[w] = b;
+        s1[w] = sa;
+        s2[w] = sb;
     }
     __syncthreads();
     if (tid == 0) {
@@ -1009,27 +915,58 @@ __global__ void __launch_bounds__(1024) csne_update_kernel(double *x, const doub
             da += s1[q];
             xb += s2[q];
         }
-        const double ndx = sqrt(da), nx = sqrt(xb);
-        if (step == 0) {
-            stat[1] = 0;
-            stat[2] = 0;
-        }
-        if (stat[0] == 0) {
-            if (ndx <= tol * nx) {
-                stat[0] = step + 1;
-            } else if (step > 0 && ndx > 0.5 * st[0]) {
-                if (ndx <= 1e-8 * nx) {
-                    stat[0] = step + 1;
-                } else {
-                    stat[2] += 1;
-                    if (stat[2] >= 2) stat[1] = 1;
-                }
-            } else {
-                stat[2] = 0;
-            }
-        }
-        st[0] = ndx;
+        RefineState rs{st[0], st[1], st[2], st[3], a.dxprev[c]};
+        refine_rule_step(rs, step, sqrt(da), sqrt(xb), a.tol, REFINE_STALL_FLOOR);
+        st[0] = rs.first;
+        st[1] = rs.failed;
+        st[2] = rs.stalls;
+        st[3] = rs.frozen;
+        a.dxprev[c] = rs.prev;
+        if (rs.frozen) atomicSub(a.active, 1);
     }
+}
+
+// Initial state of a refinement run: every column active.
+__global__ void refine_init_kernel(RefineArgs a)
+{
+    for (int i = threadIdx.x; i < 4 * a.nrhs; i += blockDim.x) a.stat[i] = 0;
+    for (int i = threadIdx.x; i < a.nrhs; i += blockDim.x) a.dxprev[i] = 0.0;
+    if (threadIdx.x == 0) *a.active = a.nrhs;
+}
+
+// Outcome of a refinement run: verdict[0] = 1 when every column converged;
+// iters = the largest first-converged step (max_iter when some column did
+// not converge); with or_info, HQR_INFO_NOCONV is ORed into *info when not
+// every column converged.  One thread.
+__global__ void refine_verdict_kernel(RefineArgs a, int *verdict, int *info, int *iters, int or_info)
+{
+    if (threadIdx.x != 0) return;
+    int conv = 1, it = 0;
+    for (int c = 0; c < a.nrhs; ++c) {
+        const int *st = a.stat + 4 * c;
+        if (st[0] == 0 || st[1]) conv = 0;
+        it = max(it, st[0]);
+    }
+    if (!conv) it = a.max_iter;
+    if (verdict) *verdict = conv;
+    if (iters) *iters = it;
+    if (or_info && !conv && info) *info |= HQR_INFO_NOCONV;
+}
+
+// Q (m x k, leading dimension ldq) <- the leading k columns of the m x m
+// identity; grid-stride over the k columns.
+__global__ void __launch_bounds__(256) eye_kernel(double *Q, int64_t ldq, int64_t m, int64_t k)
+{
+    for (int64_t j = blockIdx.x; j < k; j += gridDim.x) {
+        double *col = Q + (size_t)j * ldq;
+        for (int64_t i = threadIdx.x; i < m; i += 256) col[i] = (i == j) ? 1.0 : 0.0;
+    }
+}
+
+// *p |= v (one thread).
+__global__ void or_int_kernel(int *p, int v)
+{
+    if (threadIdx.x == 0) *p |= v;
 }
 
 __global__ void fill_int_kernel(int *p, int v, int64_t count)

@@ -42,14 +42,10 @@
 // cqr_finish_kernel.
 #pragma once
 
-#include "hqr_device.hpp"
-#include "hqr_blocked.hpp"
+#include "hqr_args.hpp"
 
 namespace hqr {
 
-constexpr int CQR_ROWS = 64;           // rows per workgroup in the Gram kernels
-constexpr double CQR_RATIO = 1e-15;    // smallest accepted pivot^2 / G_kk
-constexpr int LD65 = NB + 1;
 
 // ------------------------------------------------------------------ helpers
 // out = A * B for 64 x 64 LDS matrices (row-major, stride 65), FP64 MFMA.
@@ -809,25 +805,6 @@ HQR_DEV void exact_panel(const ExactArgs &p, int tid, double (*red)[PW], double 
     for (int e = tid; e < NB * NB; e += NT) p.T[e] = Ts[e / NB][e % NB];
 }
 
-// --------------------------------------- Gram partials (with the update)
-// Pass 1, workgroup t owns rows rbase + 64t .. +63 (rbase = cp with the
-// update, c0 without).  With `upd` it first applies the previous panel's
-// compact-WY block to this panel's columns: C -= V W with W = T^T X, X = V^T C
-// reduced over all rows (narrow_vtx_kernel + xw_reduce_kernel), V the
-// previous panel's reflectors (rows from cp, width NB).  Then the rows at or
-// below c0 give a Gram partial Z^T Z of the panel and its zero-tail mask.
-struct Gram1Args {
-    double *A;
-    int64_t lda;
-    int64_t m;
-    int c0, bw;               // panel whose Gram is formed
-    int upd, cp;              // apply the previous panel (start cp, width NB) first
-    const double *up;         // stored up (the previous panel's part is read)
-    const double *Wt;         // [NB][NB] W = T^T V^T C of the previous panel, transposed (upd)
-    double *gpart;            // [tiles][NB][NB]
-    unsigned long long *mask; // [tiles]
-    const int *flag;
-};
 
 __global__ void __launch_bounds__(256) cqr_gram1_kernel(Gram1Args p)
 {
@@ -889,19 +866,6 @@ __global__ void __launch_bounds__(256) cqr_gram1_kernel(Gram1Args p)
     if (tid == 0) p.mask[gidx] = msk;
 }
 
-// --------------------------------------------------- pass-2 Gram partials
-// Workgroup t: Q1 = A_p R1^{-1} on rows c0 + 64t .. +63 and its Gram partial;
-// workgroup 0 also keeps the top bw x bw block of Q1.
-struct Gram2Args {
-    const double *A;
-    int64_t lda;
-    int64_t m;
-    int c0, bw;
-    const double *r1inv;
-    double *q1top;
-    double *gpart;
-    const int *flag;
-};
 
 __global__ void __launch_bounds__(256) cqr_gram2_kernel(Gram2Args p)
 {
@@ -932,19 +896,6 @@ __global__ void __launch_bounds__(256) cqr_gram2_kernel(Gram2Args p)
     st64_global(p.gpart + (size_t)t * NB * NB, acc, lane, w);
 }
 
-// ----------------------------------------------- partial Gram reduction
-// G[e] = sum_q gpart[q][e] in a fixed order: 64 workgroups of 256 threads;
-// thread (entry e, quarter g4) sums q = g4, g4+4, ..; quarters added 0..3.
-// Workgroup 0 also ORs the zero-tail masks.
-struct GredArgs {
-    const double *gpart;
-    int ngroups;
-    double *G;
-    const unsigned long long *mask;
-    unsigned long long *mask_all;
-    int with_mask;
-    const int *flag;                     // nullptr: always run
-};
 
 __global__ void __launch_bounds__(256) gram_reduce_kernel(GredArgs p)
 {
@@ -1045,24 +996,6 @@ HQR_DEV void chol_near_identity(double (*G)[LD65], double (*X)[LD65], double *rd
     __syncthreads();
 }
 
-// --------------------------------------------------------- Cholesky kernel
-struct CholArgs {
-    double *A;
-    int64_t lda;
-    int64_t m;
-    int c0, bw;
-    int pass;
-    const double *G;                    // reduced Gram
-    const unsigned long long *mask_all; // ORed zero-tail masks (pass 1)
-    double *r1;         // [NB][NB]  (pass 1 out, pass 2 in)
-    double *r1inv;      // [NB][NB]  (pass 1 out, pass 2 in)
-    const double *q1top; // [NB][NB] (pass 2 in) top bw x bw block of A_p R1^{-1}
-    double *winv;       // [NB][NB]  (pass 2 out) R^{-1} U^{-1} diag(up)
-    double *T;          // [NB][NB]  (pass 2 out) T for the stored vectors
-    double *up;         // global up (pass 2 out)
-    int *flag;
-    long long *tstamp;  // optional per-phase timestamps (thread 0), may be null
-};
 
 // One workgroup, 256 threads.
 //   pass 1: R1 = chol(G), R1^{-1}; flags the panel (structurally exact
@@ -1264,15 +1197,6 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
 #undef HQR_TS
 }
 
-// ---------------------------------- bottom rows: Y_bot * diag(up) (standalone)
-struct FinArgs {
-    double *A;
-    int64_t lda;
-    int64_t m;
-    int c0, bw;
-    const double *winv;
-    const int *flag;
-};
 
 __global__ void __launch_bounds__(256) cqr_finish_kernel(FinArgs p)
 {
@@ -1299,23 +1223,6 @@ __global__ void __launch_bounds__(256) cqr_finish_kernel(FinArgs p)
     }
 }
 
-// --------------------------- next panel's V^T C, finishing this panel's V
-// For the look-ahead: panel p (start c0, width NB) has just been factored;
-// its bottom rows still hold A_bot and become V_bot = A_bot W^{-1} here
-// (unless the panel was flagged: the exact loop stored V itself).
-// Workgroup t (rows c0 + 64t .. +63) writes its V rows back and the partial
-// V_t^T C_t for the next panel's nc columns C (summed by gram_reduce_kernel;
-// cqr_gram1_kernel applies the block).
-struct NarrowArgs {
-    double *A;
-    int64_t lda;
-    int64_t m;
-    int c0, nc;
-    const double *up;
-    const double *winv;
-    const int *flag;
-    double *gpart;            // [tiles][NB][NB] out
-};
 
 __global__ void __launch_bounds__(256) narrow_vtx_kernel(NarrowArgs p)
 {
@@ -1385,19 +1292,6 @@ __global__ void __launch_bounds__(256) narrow_vtx_kernel(NarrowArgs p)
     }
 }
 
-// --------------------------------------------- W = T^T X for the look-ahead
-// Workgroup j: column j of X = sum of the transposed partials of
-// narrow_vtx_kernel (fixed order: thread (i, g4) sums q = g4, g4 + 4, ..;
-// the quarters added 0..3), then column j of W = T^T X (T upper triangular,
-// W[i][j] = sum_{l <= i} T[l][i] X[l][j]; thread (i, g4) takes l in
-// [16 g4, 16 g4 + 16), the quarters added 0..3), stored transposed
-// (Wt[j][i]).  Under 64 VGPRs, so it can start beside two bulk waves per SIMD.
-struct XwArgs {
-    const double *gpart;      // [parts][NB][NB], [q][j][i]
-    int parts;
-    const double *T;          // [NB][NB] row-major
-    double *Wt;               // [NB][NB] out, Wt[j][i] = W[i][j]
-};
 
 __global__ void __launch_bounds__(256) xw_reduce_kernel(XwArgs p)
 {

@@ -31,3 +31,8 @@ HQR_DEV bool norm_fast_path_ok(double c)
 
 // Round-to-nearest fp64 -> fp32 conversion.
 HQR_DEV float to_f32(double x) { return (float)x; }
+
+// Forces v to be materialized here (empty asm that reads and writes it): a
+// load feeding it cannot be sunk into a later conditional block, so a group
+// of loads issued before a group of pins waits once for all of them.
+HQR_DEV void pin_f64(double &v) { asm volatile("" : "+v"(v)); }

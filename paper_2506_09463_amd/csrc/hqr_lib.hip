@@ -1,5 +1,6 @@
 // hqr_lib.hip -- libhqr: the C ABI declared in include/hqr.h and its host
-// dispatch.  One translation unit: the kernels live in the included headers.
+// dispatch.  The kernels live in their own translation units (k_*.hip), each
+// exporting launch functions declared in hqr_args.hpp.
 #include "hqr.h"
 
 #include <hip/hip_runtime.h>
@@ -8,26 +9,17 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
-
-#include "hqr_device.hpp"
-#include "hqr_small.hpp"
-#include "hqr_blocked.hpp"
-#include "hqr_cqr.hpp"
-#include "hqr_batched.hpp"
-#include "hqr_wg.hpp"
-
+#include <mutex>
 #include <numeric>
 #include <vector>
+
+#include "hqr_args.hpp"
 
 namespace hqr {
 
 // ------------------------------------------------------------- profiling
 // Optional per-kernel-class timing: while active, every launch is bracketed
 // by a pair of HIP events recorded on the launch's own stream.
-enum KClass {
-    K_SMALL, K_PANEL, K_VTX, K_TFACTOR, K_WSOLVE, K_UPDATE, K_DIAG, K_TRSV, K_RESNORM, K_FILL,
-    K_GRAM1, K_GRAM2, K_GRED, K_CQR_CHOL, K_CQR_FINISH, K_NVTX, K_BATCHED, K_REFINE, K_NCLASS
-};
 static const char *kclass_name[K_NCLASS] = {"small_lsq", "panel_col", "vtx", "tfactor", "wsolve",
                                             "update", "diag_check", "trsv", "resnorm", "fill",
                                             "cqr_gram1", "cqr_gram2", "gram_reduce", "cqr_chol",
@@ -59,7 +51,7 @@ static hipEvent_t prof_event()
     return g_prof.pool[g_prof.pool_used++];
 }
 
-static hipEvent_t prof_begin(hipStream_t s)
+hipEvent_t prof_begin(hipStream_t s)
 {
     if (!g_prof.on) return nullptr;
     hipEvent_t e = prof_event();
@@ -67,7 +59,7 @@ static hipEvent_t prof_begin(hipStream_t s)
     return e;
 }
 
-static void prof_end(int cls, hipEvent_t e0, hipStream_t s)
+void prof_end(int cls, hipEvent_t e0, hipStream_t s)
 {
     if (!g_prof.on || !e0) return;
     hipEvent_t e1 = prof_event();
@@ -83,47 +75,8 @@ static void prof_end(int cls, hipEvent_t e0, hipStream_t s)
     g_prof.recs[g_prof.n++] = ProfRec{cls, e0, e1};
 }
 
-#define HQR_LAUNCH(cls, kern, grid, block, shmem, stream, ...)                     \
-    do {                                                                           \
-        hipEvent_t e0_ = prof_begin(stream);                                       \
-        hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);         \
-        prof_end(cls, e0_, stream);                                                \
-    } while (0)
 
 // ------------------------------------------------- one-workgroup variants
-typedef void (*wg_batched_fn)(const WgDesc *, int, int *, int *);
-typedef void (*wg_single_fn)(WgDesc, int *);
-struct WgVariant {
-    const char *name;
-    int nt, qm, per_cu;
-    wg_batched_fn batched;
-    wg_single_fn single;
-    int64_t max_rows, max_x;
-};
-
-template <int NT, int QM>
-static WgVariant make_wg(const char *name)
-{
-    const int per_cu = (int)std::max<size_t>(1, (160 * 1024) / sizeof(WgShared<NT, QM>));
-    return WgVariant{name, NT, QM, std::min(per_cu, 2), wg_batched_kernel<NT, QM>, wg_single_kernel<NT, QM>,
-                     wg_max_rows<NT, QM>(), wg_max_x<NT, QM>()};
-}
-
-static const WgVariant *wg_variants(int *count)
-{
-    static const WgVariant v[] = {
-        make_wg<64, 2>("wg64x2"),   // m <= 128, one wave
-        make_wg<64, 4>("wg64x4"),   // m <= 256, one wave
-        make_wg<128, 1>("wg128x1"), // m <= 128
-        make_wg<256, 1>("wg256x1"), // m <= 256
-        make_wg<128, 4>("wg128x4"), // m <= 512
-        make_wg<256, 2>("wg256x2"), // m <= 512
-        make_wg<256, 4>("wg256x4"), // m <= 1024
-    };
-    *count = (int)(sizeof(v) / sizeof(v[0]));
-    return v;
-}
-
 static bool wg_fits(const WgVariant &v, int64_t m, int64_t n, int64_t nrhs)
 {
     return m <= v.max_rows && n * nrhs <= v.max_x;
@@ -196,58 +149,7 @@ static const WgVariant *pick_wg_batched(int64_t mmax, int64_t nmax)
 
 static int launch_wg_single(const WgVariant *v, const WgDesc &d, int *info, hipStream_t s)
 {
-    HQR_LAUNCH(K_SMALL, v->single, dim3(1), dim3(v->nt), 0, s, d, info);
-    return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
-}
-
-// ------------------------------------------------------------- small path
-typedef void (*small_fn)(SmallArgs);
-struct SmallCfg {
-    int nw, rw, q;
-    small_fn fn;
-    size_t static_lds;
-};
-
-template <int NW, int RW, int Q>
-static SmallCfg make_small()
-{
-    const size_t st = sizeof(double) * (2 * NW * (Q * 64 + 2) + 2 * Q * 64 + NW + Q * 64 + 2 * NW * RW) + 16;
-    return SmallCfg{NW, RW, Q, small_lsq_kernel<NW, RW, Q>, st};
-}
-
-static const SmallCfg *small_configs(int *count)
-{
-    static SmallCfg cfgs[] = {
-        make_small<4, 16, 1>(),  // m <= 64,  n+nrhs <= 64
-        make_small<8, 16, 2>(),  // m <= 128, n+nrhs <= 128
-        make_small<16, 16, 2>(), // m <= 256, n+nrhs <= 128
-    };
-    *count = (int)(sizeof(cfgs) / sizeof(cfgs[0]));
-    return cfgs;
-}
-
-static constexpr size_t LDS_LIMIT = 160 * 1024;
-
-static const SmallCfg *pick_small(int64_t m, int64_t n, int64_t nrhs)
-{
-    if (m > 256 || n + nrhs > 128 || n == 0) return nullptr;
-    int cnt = 0;
-    const SmallCfg *c = small_configs(&cnt);
-    for (int i = 0; i < cnt; ++i) {
-        if (m > (int64_t)c[i].nw * c[i].rw || n + nrhs > 64 * c[i].q) continue;
-        if (c[i].static_lds + small_dyn_lds((int)m, (int)n, (int)nrhs) > LDS_LIMIT) continue;
-        return &c[i];
-    }
-    return nullptr;
-}
-
-static hipError_t launch_small(const SmallCfg *cfg, SmallArgs a, hipStream_t s)
-{
-    a.ldl = small_ldl(a.m);
-    const size_t dyn = small_dyn_lds(a.m, a.n, a.nrhs);
-    (void)hipFuncSetAttribute((const void *)cfg->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-    HQR_LAUNCH(K_SMALL, cfg->fn, dim3(1), dim3(cfg->nw * 64), dyn, s, a);
-    return hipGetLastError();
+    return k_wg_single(v, s, d, info) == hipSuccess ? 0 : HQR_EDEVICE;
 }
 
 // ------------------------------------------------------------ large path
@@ -289,8 +191,8 @@ struct Work {
     int *iscratch;
     double *gpart, *r1, *r1inv, *winv, *q1top;
     double *G, *xn;                          // reduced Gram; W = T^T V^T C of the look-ahead (transposed)
-    double *borig, *rvec, *gvec, *mstat_d;   // mixed precision: original B, residual, A^T r, ||dx||
-    int *mstat;                              // mixed precision: [first converged step, stagnation, run]
+    double *borig, *rvec, *gvec, *mstat_d;   // refinement: original B, residuals, A^T r, previous ||dx||
+    int *mstat;                              // refinement: [nrhs][4] column states, active count, verdict
     unsigned long long *mask, *mask_all;
     int *pflag;
 };
@@ -322,10 +224,11 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *mk = take(sizeof(unsigned long long) * (size_t)p.ngroups);
     char *pf = take(sizeof(int) * (size_t)std::max(p.npanels, 1));
     char *bo = take(sizeof(double) * (size_t)p.m * (size_t)std::max<int64_t>(p.nrhs, 1));
-    char *rv = take(sizeof(double) * (size_t)std::max<int64_t>(p.m, 1));
-    char *gv = take(sizeof(double) * (size_t)std::max<int64_t>(p.m, 1));
-    char *msd = take(sizeof(double) * 64);
-    char *ms = take(sizeof(int) * 64);
+    const size_t nr = (size_t)std::max<int64_t>(p.nrhs, 1);
+    char *rv = take(sizeof(double) * (size_t)std::max<int64_t>(p.m, 1) * nr);
+    char *gv = take(sizeof(double) * (size_t)std::max<int64_t>(p.n, 1) * nr);
+    char *msd = take(sizeof(double) * nr);
+    char *ms = take(sizeof(int) * (4 * nr + 2));
     char *q1 = take(sizeof(double) * NB * NB);
     char *gg = take(sizeof(double) * NB * NB);
     char *xn = take(sizeof(double) * NB * NB);
@@ -388,7 +291,7 @@ struct TrailBufs {
 static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int64_t lda, double *B, int64_t ldb,
                              const double *up, int c0, int bw, int aoff, int ncA, int nB, bool have_t,
                              hipStream_t s, bool f32 = false, int first_cols = 0, hipEvent_t ev_first = nullptr,
-                             int vtx_wg_cap = 0)
+                             int vtx_wg_cap = 0, bool apply_q = false)
 {
     const int64_t rows = pl.m - c0;
     VtxArgs v;
@@ -422,18 +325,7 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     const int nsplit_eff = (int)((rows + v.split_rows - 1) / v.split_rows);
     v.wpart = tb.wpart;
     const dim3 vg(ntiles, nsplit_eff);
-    if (v.with_v) {
-        if (f32)
-            HQR_LAUNCH(K_VTX, (vtx_kernel<true, true>), vg, dim3(256), 0, s, v);
-        else
-            HQR_LAUNCH(K_VTX, (vtx_kernel<false, true>), vg, dim3(256), 0, s, v);
-    } else {
-        if (f32)
-            HQR_LAUNCH(K_VTX, (vtx_kernel<true, false>), vg, dim3(256), 0, s, v);
-        else
-            HQR_LAUNCH(K_VTX, (vtx_kernel<false, false>), vg, dim3(256), 0, s, v);
-    }
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_vtx(f32, v.with_v != 0, vg, s, v));
 
     if (!have_t) {
         TArgs t;
@@ -446,8 +338,7 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
         t.nsplit = nsplit_eff;
         t.nxpad = v.nxpad;
         t.T = tb.T;
-        HQR_LAUNCH(K_TFACTOR, tfactor_kernel, dim3(1), dim3(256), 0, s, t);
-        HQR_CK(hipGetLastError());
+        HQR_CK(k_tfactor(s, t));
     }
 
     const int ncols = ncA + nB;
@@ -464,11 +355,9 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     wa.bw = bw;
     wa.T = tb.T;
     wa.wp = tb.wp;
-    if (narrow)
-        HQR_LAUNCH(K_WSOLVE, wsolve_narrow_kernel, dim3((ncols + WSN_COLS - 1) / WSN_COLS), dim3(256), 0, s, wa);
-    else
-        HQR_LAUNCH(K_WSOLVE, wsolve_kernel, dim3((ncols + WS_COLS - 1) / WS_COLS), dim3(256), 0, s, wa);
-    HQR_CK(hipGetLastError());
+    wa.tmode = apply_q ? 1 : 0;
+    HQR_CK(k_wsolve(narrow, dim3(narrow ? (ncols + WSN_COLS - 1) / WSN_COLS : (ncols + WS_COLS - 1) / WS_COLS), s,
+                    wa));
 
     UpdArgs u;
     u.A = A;
@@ -491,11 +380,7 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
         uf.ncA = first_cols;
         uf.nB = 0;
         const dim3 ug((unsigned)((rows + 63) / 64));
-        if (f32)
-            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<true>, ug, dim3(256), 0, s, uf);
-        else
-            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<false>, ug, dim3(256), 0, s, uf);
-        HQR_CK(hipGetLastError());
+        HQR_CK(k_update(true, f32, ug, s, uf));
         HQR_CK(hipEventRecord(ev_first, s));
         u.ncA -= first_cols;
         u.aoff += first_cols;
@@ -504,16 +389,10 @@ static int apply_panel_block(const Plan &pl, const TrailBufs &tb, double *A, int
     const int ncols_u = u.ncA + u.nB;
     if (narrow) {
         const dim3 ug((unsigned)((rows + 63) / 64));
-        if (f32)
-            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<true>, ug, dim3(256), 0, s, u);
-        else
-            HQR_LAUNCH(K_UPDATE, update_narrow_kernel<false>, ug, dim3(256), 0, s, u);
+        HQR_CK(k_update(true, f32, ug, s, u));
     } else {
         const dim3 ug((unsigned)((rows + UPD_TILE - 1) / UPD_TILE), (ncols_u + UPD_TILE - 1) / UPD_TILE);
-        if (f32)
-            HQR_LAUNCH(K_UPDATE, update_kernel<true>, ug, dim3(256), 0, s, u);
-        else
-            HQR_LAUNCH(K_UPDATE, update_kernel<false>, ug, dim3(256), 0, s, u);
+        HQR_CK(k_update(false, f32, ug, s, u));
     }
     HQR_CK(hipGetLastError());
     if (ev_first && !split) HQR_CK(hipEventRecord(ev_first, s));
@@ -536,8 +415,7 @@ static int panel_percol(const Plan &pl, const Work &w, double *A, int64_t lda, d
     pa.pbuf = w.pbuf;
     for (int k = 0; k <= bw; ++k) {
         pa.k = k;
-        HQR_LAUNCH(K_PANEL, panel_col_kernel, dim3(pa.nchunk), dim3(256), 0, s, pa);
-        HQR_CK(hipGetLastError());
+        HQR_CK(k_panel_col(dim3(pa.nchunk), s, pa));
     }
     return 0;
 }
@@ -556,8 +434,7 @@ static int launch_gred(const Plan &, const Work &w, int parts, double *out, bool
     gr.mask_all = w.mask_all;
     gr.with_mask = with_mask ? 1 : 0;
     gr.flag = flag;
-    HQR_LAUNCH(K_GRED, gram_reduce_kernel, dim3(NB * NB / 64), dim3(256), 0, s, gr);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_gram_reduce(s, gr));
     return 0;
 }
 
@@ -581,8 +458,7 @@ static int launch_chol(const Plan &pl, const Work &w, double *A, int64_t lda, do
     c.up = up;
     c.flag = w.pflag + pidx;
     c.tstamp = nullptr;
-    HQR_LAUNCH(K_CQR_CHOL, cqr_chol_kernel, dim3(1), dim3(256), 0, s, c);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_cqr_chol(s, c));
     return 0;
 }
 
@@ -608,8 +484,7 @@ static int panel_passes(const Plan &pl, const Work &w, double *A, int64_t lda, d
     g.gpart = w.gpart;
     g.mask = w.mask;
     g.flag = flag;
-    HQR_LAUNCH(K_GRAM1, cqr_gram1_kernel, dim3((unsigned)((pl.m - rbase + 63) / 64)), dim3(256), 0, s, g);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_cqr_gram1(dim3((unsigned)((pl.m - rbase + 63) / 64)), s, g));
     int rc = launch_gred(pl, w, parts, w.G, true, flag, s);
     if (!rc) rc = launch_chol(pl, w, A, lda, up, c0, bw, pidx, 1, Tout, s);
     if (rc) return rc;
@@ -623,8 +498,7 @@ static int panel_passes(const Plan &pl, const Work &w, double *A, int64_t lda, d
     g2.q1top = w.q1top;
     g2.gpart = w.gpart;
     g2.flag = flag;
-    HQR_LAUNCH(K_GRAM2, cqr_gram2_kernel, dim3((unsigned)parts), dim3(256), 0, s, g2);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_cqr_gram2(dim3((unsigned)parts), s, g2));
     rc = launch_gred(pl, w, parts, w.G, false, flag, s);
     if (!rc) rc = launch_chol(pl, w, A, lda, up, c0, bw, pidx, 2, Tout, s);
     return rc;
@@ -644,8 +518,7 @@ static int launch_finish(const Plan &pl, const Work &w, double *A, int64_t lda, 
     f.bw = bw;
     f.winv = w.winv;
     f.flag = w.pflag + pidx;
-    HQR_LAUNCH(K_CQR_FINISH, cqr_finish_kernel, dim3((unsigned)((mp - bw + 63) / 64)), dim3(256), 0, s, f);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_cqr_finish(dim3((unsigned)((mp - bw + 63) / 64)), s, f));
     return 0;
 }
 
@@ -665,8 +538,7 @@ static int launch_narrow_vtx(const Plan &pl, const Work &w, double *A, int64_t l
     a.flag = w.pflag + pidx;
     a.gpart = w.gpart;
     const int parts = (int)((pl.m - c0 + 63) / 64);
-    HQR_LAUNCH(K_NVTX, narrow_vtx_kernel, dim3((unsigned)parts), dim3(256), 0, s, a);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_narrow_vtx(dim3((unsigned)parts), s, a));
     return 0;
 }
 
@@ -692,30 +564,46 @@ static int panel_mode()
     return PANEL_CQR;
 }
 
-// Side stream and events for the look-ahead (one per device, created on first
-// use, default priority).
-struct SideStream {
+// Per caller stream (and device): the look-ahead's side stream with its
+// events, and the pinned staging buffer of the batched descriptor upload.
+// Created on first use and kept for the process; a solve on stream s only
+// ever touches s's context, so solves on different streams neither share
+// events nor serialize their look-ahead work.  Calls on ONE stream from
+// several host threads must be serialized by the caller (as any stream use).
+struct StreamCtx {
     int device = -1;
-    hipStream_t stream = nullptr;
+    hipStream_t caller = nullptr;
+    hipStream_t side = nullptr;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *stage = nullptr;       // pinned host staging buffer
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ready = nullptr;
 };
-static SideStream g_side[16];
+constexpr int MAX_STREAM_CTX = 256;
+static StreamCtx g_ctx[MAX_STREAM_CTX];
+static int g_nctx = 0;
+static std::mutex g_ctx_mu;
 
-static SideStream *side_stream()
+static StreamCtx *stream_ctx(hipStream_t caller)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return nullptr;
-    SideStream &ss = g_side[dev];
-    if (ss.device != dev) {
-        if (hipStreamCreateWithFlags(&ss.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        // the events only order the two streams of one device: no timing and
-        // no system-scope fence (kernel boundaries already release to the device)
-        for (auto &e : ss.ev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
-                return nullptr;
-        ss.device = dev;
-    }
-    return &ss;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    for (int i = 0; i < g_nctx; ++i)
+        if (g_ctx[i].device == dev && g_ctx[i].caller == caller) return &g_ctx[i];
+    if (g_nctx == MAX_STREAM_CTX) return nullptr;
+    StreamCtx &c = g_ctx[g_nctx];
+    if (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    // the events only order the two streams of one device: no timing and
+    // no system-scope fence (kernel boundaries already release to the device)
+    for (auto &e : c.ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
+            return nullptr;
+    if (hipEventCreateWithFlags(&c.stage_ready, hipEventDisableTiming) != hipSuccess) return nullptr;
+    c.device = dev;
+    c.caller = caller;
+    ++g_nctx;
+    return &c;
 }
 
 static bool lookahead_enabled()
@@ -743,11 +631,11 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
     const bool have_t = (mode != PANEL_PERCOL);
     if (have_t) {
         // exact-only mode: every panel flagged up front
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(256), 0, s, w.pflag, mode == PANEL_EXACT ? 1 : 0,
-                   (int64_t)pl.npanels);
+        HQR_CK(k_fill_int(s, w.pflag, mode == PANEL_EXACT ? 1 : 0,
+                   (int64_t)pl.npanels));
         HQR_CK(hipGetLastError());
     }
-    SideStream *ss = (lookahead_enabled() && pl.npanels > 1) ? side_stream() : nullptr;
+    StreamCtx *ss = (lookahead_enabled() && pl.npanels > 1) ? stream_ctx(s) : nullptr;
     const TrailBufs bufN{w.wpart, nullptr, w.wp};
     const TrailBufs bufR{w.wpart2, nullptr, w.wp2};
     double *Tbuf[2] = {w.T, w.T2};
@@ -774,7 +662,7 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
     hipEvent_t ev_a = ss->ev[0], ev_r = ss->ev[1], ev_join = ss->ev[2], ev_fork = ss->ev[3];
     // side stream starts after everything already on the caller's stream
     HQR_CK(hipEventRecord(ev_fork, s));
-    HQR_CK(hipStreamWaitEvent(ss->stream, ev_fork, 0));
+    HQR_CK(hipStreamWaitEvent(ss->side, ev_fork, 0));
     bool pending_r = false;
     if (have_t && !pl.f32) {
         // Fused chain on the caller's stream, per panel p:
@@ -798,17 +686,17 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
                            : launch_finish(pl, w, A, lda, (int)c0, bw, pidx, s);
             if (rc) return rc;
             HQR_CK(hipEventRecord(ev_a, s));
-            HQR_CK(hipStreamWaitEvent(ss->stream, ev_a, 0));
+            HQR_CK(hipStreamWaitEvent(ss->side, ev_a, 0));
             // R(p): the columns of panel p+2 first, then r(p) (all that
             // narrow_vtx(p+1) reads), then the rest of the columns and B
             if (ncR + nB > 0) {
                 // late panels, where the main chain is the longer one: V^T C
                 // on at most half the CUs so the chain's kernels find free ones
-                rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, true, ss->stream, false,
+                rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, true, ss->side, false,
                                        std::min(ncR, (int)pl.nb), ev_r, (ncR + nB <= 2048) ? 128 : 0);
                 if (rc) return rc;
             } else {
-                HQR_CK(hipEventRecord(ev_r, ss->stream));
+                HQR_CK(hipEventRecord(ev_r, ss->side));
             }
             if (bw1 > 0) {
                 XwArgs xa;
@@ -816,8 +704,7 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
                 xa.parts = (int)((pl.m - c0 + 63) / 64);
                 xa.T = Tbuf[pidx & 1];
                 xa.Wt = w.xn;
-                HQR_LAUNCH(K_GRED, xw_reduce_kernel, dim3(NB), dim3(256), 0, s, xa);
-                HQR_CK(hipGetLastError());
+                HQR_CK(k_xw_reduce(s, xa));
                 if (!rc)
                     rc = panel_passes(pl, w, A, lda, up, (int)c1, bw1, pidx + 1, Tbuf[(pidx + 1) & 1], true, (int)c0,
                                       s);
@@ -825,7 +712,7 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
             }
             pending_r = true;
         }
-        HQR_CK(hipEventRecord(ev_join, ss->stream));
+        HQR_CK(hipEventRecord(ev_join, ss->side));
         HQR_CK(hipStreamWaitEvent(s, ev_join, 0));
         return 0;
     }
@@ -845,13 +732,13 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
         // R(p) on the side stream: columns beyond the next panel, and B; the
         // columns of panel p+2 first, then r(p), then the rest and B
         HQR_CK(hipEventRecord(ev_a, s));
-        HQR_CK(hipStreamWaitEvent(ss->stream, ev_a, 0));
+        HQR_CK(hipStreamWaitEvent(ss->side, ev_a, 0));
         if (ncR + nB > 0) {
-            rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, have_t, ss->stream, pl.f32,
+            rc = apply_panel_block(pl, br, A, lda, B, ldb, up, (int)c0, bw, bw1, ncR, nB, have_t, ss->side, pl.f32,
                                    std::min(ncR, (int)pl.nb), ev_r);
             if (rc) return rc;
         } else {
-            HQR_CK(hipEventRecord(ev_r, ss->stream));
+            HQR_CK(hipEventRecord(ev_r, ss->side));
         }
         // main: N(p), then P(p+1)
         if (bw1 > 0) {
@@ -863,19 +750,17 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
         pending_r = true;
     }
     // join: the caller's stream waits for the last side-stream work
-    HQR_CK(hipEventRecord(ev_join, ss->stream));
+    HQR_CK(hipEventRecord(ev_join, ss->side));
     HQR_CK(hipStreamWaitEvent(s, ev_join, 0));
     return 0;
 }
 
 static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int64_t lda, double *B, int64_t ldb,
-                             int nrhs, int *info, hipStream_t s, bool trans = false)
+                             int nrhs, int *info, hipStream_t s, bool trans = false, const int *active = nullptr)
 {
-    HQR_LAUNCH(K_DIAG, diag_check_kernel, dim3(1), dim3(256), 0, s, A, lda, pl.n, info);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_diag_check(s, A, lda, pl.n, info));
     for (int c = 0; c < nrhs; c += TRSV_MAXRHS) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(256), 0, s, w.flags, 0, (int64_t)pl.nblk);
-        HQR_CK(hipGetLastError());
+        HQR_CK(k_fill_int(s, w.flags, 0, (int64_t)pl.nblk));
         TrsvArgs t;
         t.A = A;
         t.lda = lda;
@@ -887,18 +772,8 @@ static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int
         t.info = info;
         t.epoch = 1;
         t.spin_limit = 20000000L;
-        if (t.nrhs == 1) {
-            if (trans)
-                HQR_LAUNCH(K_TRSV, (trsv_kernel<true, 1>), dim3(pl.nblk), dim3(256), 0, s, t);
-            else
-                HQR_LAUNCH(K_TRSV, (trsv_kernel<false, 1>), dim3(pl.nblk), dim3(256), 0, s, t);
-        } else {
-            if (trans)
-                HQR_LAUNCH(K_TRSV, (trsv_kernel<true, TRSV_MAXRHS>), dim3(pl.nblk), dim3(256), 0, s, t);
-            else
-                HQR_LAUNCH(K_TRSV, (trsv_kernel<false, TRSV_MAXRHS>), dim3(pl.nblk), dim3(256), 0, s, t);
-        }
-        HQR_CK(hipGetLastError());
+        t.active = active;
+        HQR_CK(k_trsv(trans, t.nrhs, dim3(pl.nblk), s, t));
     }
     return 0;
 }
@@ -927,24 +802,52 @@ static int get_work(const Plan &pl, void *work, int64_t lwork, hipStream_t s, Wo
     return 0;
 }
 
+// B <- Q^T B (transpose) or Q B with the stored reflectors in (A, up).  With
+// skip, B's column j is only touched by the panels that start at or before
+// column j: B then starts as leading columns of the identity, and no
+// reflector k > j changes column j of the identity (its vector is zero in
+// rows 0..k-1).
+static int apply_stored(const Plan &pl, const Work &w, const double *A, int64_t lda, const double *up, double *B,
+                        int64_t ldb, int64_t nrhs, bool transpose, bool skip, hipStream_t s)
+{
+    const int64_t m = pl.m, n = pl.n;
+    if (n == 0 || nrhs == 0) return 0;
+    if (const WgVariant *v = pick_wg_single(m, n, nrhs)) {
+        const int64_t fl = (transpose ? 0 : WG_APPLY_Q) | (skip ? WG_QSKIP : 0);
+        const WgDesc d{m, n, nrhs, lda, ldb, const_cast<double *>(A), B, const_cast<double *>(up), nullptr, 0, fl};
+        return launch_wg_single(v, d, nullptr, s);
+    }
+    const int npan = (int)((n + NB - 1) / NB);
+    for (int q = 0; q < npan; ++q) {
+        const int p = transpose ? q : npan - 1 - q;
+        const int64_t c0 = (int64_t)p * NB;
+        const int bw = (int)std::min<int64_t>(NB, n - c0);
+        const int64_t j0 = skip ? c0 : 0;
+        if (nrhs <= j0) continue;
+        int rc = apply_panel_block(pl, TrailBufs{w.wpart, w.T, w.wp}, const_cast<double *>(A), lda,
+                                   B + (size_t)j0 * ldb, ldb, up, (int)c0, bw, 0, 0, (int)(nrhs - j0), false, s,
+                                   false, 0, nullptr, 0, !transpose);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
 // The FP64 path: small problems in one register-resident workgroup, larger
 // ones by the blocked factorization, then residual norms and back-substitution.
 static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B, int64_t ldb,
                     double *resnorm, void *work, int64_t lwork, int *info, hipStream_t s)
 {
     if (n == 0) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
+        HQR_CK(k_fill_int(s, info, 0, (int64_t)1));
         HQR_CK(hipGetLastError());
         if (resnorm && nrhs > 0) {
-            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, (const double *)B, ldb,
-                       (int64_t)0, m, resnorm);
-            HQR_CK(hipGetLastError());
+            HQR_CK(k_resnorm(dim3((unsigned)nrhs), s, B, ldb, 0, m, resnorm));
         }
         return 0;
     }
     if (const WgVariant *v = pick_wg_single(m, n, nrhs)) {
         if (nrhs == 0) {
-            HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
+            HQR_CK(k_fill_int(s, info, 0, (int64_t)1));
             HQR_CK(hipGetLastError());
         }
         const WgDesc d{m, n, nrhs, lda, ldb, A, B, up, resnorm, 0, WG_FACTOR | (nrhs > 0 ? WG_SOLVE : 0)};
@@ -955,94 +858,89 @@ static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, 
     Work w;
     int rc = get_work(pl, work, lwork, s, g, &w);
     if (rc) return rc;
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
+    HQR_CK(k_fill_int(s, info, 0, (int64_t)1));
     HQR_CK(hipGetLastError());
     rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, s);
     if (rc) return rc;
     if (nrhs == 0) return 0;
     if (resnorm) {
-        HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, (const double *)B, ldb, n, m,
-                   resnorm);
-        HQR_CK(hipGetLastError());
+        HQR_CK(k_resnorm(dim3((unsigned)nrhs), s, B, ldb, n, m, resnorm));
     }
     return backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, s);
 }
 
-// Mixed precision: FP32 trailing contractions in the factorization, then
-// corrections of the semi-normal equations with FP64 residuals:
-//   r = b - A0 x,  g = A0^T r,  R^T z = g,  R dx = z,  x += dx
-// (A0 = the unmodified FP64 matrix, R = the factor's triangle).  A run of
-// max_iter steps is enqueued; the stream is synchronized once at the end to
-// read the convergence record and, without convergence, the FP64 path is
-// run on the restored inputs (info gets HQR_INFO_NOCONV).
-// Corrections of the semi-normal equations for every right-hand side:
-// x (in B[0:n]) += dx until converged (see csne_update_kernel), with FP64
-// residuals of A0 against the original right-hand sides in w.borig and
-// triangular solves with R (upper triangle of A).  Reports the largest
-// first-converged step and whether every column converged.
+// Refinement of every right-hand side with the semi-normal equations
+// (RefineArgs): max_iter steps are enqueued; a column that converges or fails
+// freezes and, once none is left, the remaining launches return at once.  The
+// verdict kernel then writes iters and verdict (1: every column converged),
+// and with or_info ORs HQR_INFO_NOCONV into info when not.  Residual norms
+// ||b - A0 x|| go to resnorm.  Nothing here waits on the host.
 static int mixed_refine(const Plan &pl, const Work &w, const double *A, int64_t lda, double *B, int64_t ldb,
                         int64_t nrhs, double *resnorm, double tol, int max_iter, const double *A0, int64_t lda0,
-                        hipStream_t s, int *first, bool *converged)
+                        hipStream_t s, int *info, int *iters, bool or_info)
 {
-    const int64_t m = pl.m, n = pl.n;
-    *first = 0;
-    *converged = true;
-    for (int64_t c = 0; c < nrhs; ++c) {
-        double *x = B + (size_t)c * ldb;
-        const double *b0 = w.borig + (size_t)c * m;
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, w.mstat, 0, (int64_t)4);
-        HQR_CK(hipGetLastError());
-        for (int it = 0; it < max_iter; ++it) {
-            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
-                       (const double *)x, w.rvec, m, n);
-            HQR_LAUNCH(K_REFINE, gemvt_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, A0, lda0,
-                       (const double *)w.rvec, w.gvec, m, n);
-            HQR_CK(hipGetLastError());
-            int rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, true);
-            if (rc) return rc;
-            rc = backsolve_blocked(pl, w, A, lda, w.gvec, std::max<int64_t>(n, 1), 1, w.iscratch, s, false);
-            if (rc) return rc;
-            HQR_LAUNCH(K_REFINE, csne_update_kernel, dim3(1), dim3(1024), 0, s, x, (const double *)w.gvec, n, tol,
-                       it, w.mstat, w.mstat_d);
-            HQR_CK(hipGetLastError());
-        }
-        if (resnorm) {
-            HQR_LAUNCH(K_REFINE, resid_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, A0, lda0, b0,
-                       (const double *)x, w.rvec, m, n);
-            HQR_LAUNCH(K_RESNORM, resnorm_kernel, dim3(1), dim3(256), 0, s, (const double *)w.rvec,
-                       std::max<int64_t>(m, 1), (int64_t)0, m, resnorm + c);
-            HQR_CK(hipGetLastError());
-        }
-        int st[4] = {0, 0, 0, 0};
-        HQR_CK(hipMemcpyAsync(st, w.mstat, sizeof(st), hipMemcpyDeviceToHost, s));
-        HQR_CK(hipStreamSynchronize(s));
-        if (st[0] == 0 || st[1]) *converged = false;
-        *first = std::max(*first, st[0]);
+    RefineArgs r;
+    r.A0 = A0;
+    r.lda0 = lda0;
+    r.borig = w.borig;
+    r.X = B;
+    r.ldx = ldb;
+    r.rvec = w.rvec;
+    r.gvec = w.gvec;
+    r.m = pl.m;
+    r.n = pl.n;
+    r.nrhs = (int)nrhs;
+    r.tol = tol;
+    r.max_iter = max_iter;
+    r.stat = w.mstat;
+    r.dxprev = w.mstat_d;
+    r.active = w.mstat + 4 * nrhs;
+    int *verdict = w.mstat + 4 * nrhs + 1;
+    HQR_CK(k_refine_init(s, r));
+    const int64_t ldg = std::max<int64_t>(pl.n, 1);
+    for (int it = 0; it < max_iter; ++it) {
+        HQR_CK(k_resid(false, s, r));
+        HQR_CK(k_gemvt(s, r));
+        int rc = backsolve_blocked(pl, w, A, lda, w.gvec, ldg, (int)nrhs, w.iscratch, s, true, r.active);
+        if (rc) return rc;
+        rc = backsolve_blocked(pl, w, A, lda, w.gvec, ldg, (int)nrhs, w.iscratch, s, false, r.active);
+        if (rc) return rc;
+        HQR_CK(k_csne_update(s, r, it));
     }
+    if (resnorm) {
+        HQR_CK(k_resid(true, s, r));
+        HQR_CK(k_resnorm(dim3((unsigned)nrhs), s, w.rvec, std::max<int64_t>(pl.m, 1), 0, pl.m, resnorm));
+    }
+    HQR_CK(k_refine_verdict(s, r, verdict, info, iters, or_info));
     return 0;
 }
 
-static int write_iters(int *iters, int v, hipStream_t s)
+// Reads the refinement verdict back (one synchronization of the stream).
+static int read_verdict(const Work &w, int64_t nrhs, hipStream_t s, bool *converged)
 {
-    if (!iters) return 0;
-    HQR_CK(hipMemcpyAsync(iters, &v, sizeof(int), hipMemcpyHostToDevice, s));
+    int v = 0;
+    HQR_CK(hipMemcpyAsync(&v, w.mstat + 4 * nrhs + 1, sizeof(int), hipMemcpyDeviceToHost, s));
     HQR_CK(hipStreamSynchronize(s));
+    *converged = v != 0;
     return 0;
 }
 
-// Mixed precision: FP32 trailing contractions in the factorization, then
-// corrections of the semi-normal equations with FP64 residuals:
-//   r = b - A0 x,  g = A0^T r,  R^T z = g,  R dx = z,  x += dx
-// (A0 = the unmodified FP64 matrix, R = the factor's triangle).  A run of
-// max_iter steps is enqueued; the stream is synchronized once per right-hand
-// side to read the convergence record and, without convergence, the FP64
-// path is run on the restored inputs (info gets HQR_INFO_NOCONV).
+static bool no_fallback(const hqr_opts *opt) { return opt && (opt->flags & HQR_OPT_NO_FALLBACK); }
+
+// Mixed precision: FP32 trailing contractions in the factorization, FP64
+// back-substitution, then the refinement above.  Without HQR_OPT_NO_FALLBACK
+// the stream is synchronized once to read the verdict and, without
+// convergence, the FP64 path runs on the restored inputs and
+// HQR_INFO_NOCONV is ORed into the info it reports.  With it nothing waits
+// on the host: HQR_INFO_NOCONV is ORed into info on the device and x is the
+// last iterate.
 static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B,
                      int64_t ldb, double *resnorm, const hqr_opts *opt, const double *A0, int64_t lda0, void *work,
                      int64_t lwork, int *info, int *iters, hipStream_t s)
 {
     const double tol = (opt && opt->tol > 0.0) ? opt->tol : 1e-13;
     const int max_iter = (opt && opt->max_iter >= 0) ? opt->max_iter : 10;
+    const bool async = no_fallback(opt);
     const int nb = (n <= 256) ? 16 : NB;
     Plan pl = make_plan(m, n, nrhs, nb, true);
     WorkGuard g;
@@ -1051,33 +949,26 @@ static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
     if (rc) return rc;
     HQR_CK(hipMemcpy2DAsync(w.borig, sizeof(double) * m, B, sizeof(double) * ldb, sizeof(double) * m, nrhs,
                             hipMemcpyDeviceToDevice, s));
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, s, info, 0, (int64_t)1);
-    HQR_CK(hipGetLastError());
+    HQR_CK(k_fill_int(s, info, 0, (int64_t)1));
     rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, s);
     if (rc) return rc;
     rc = backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, s);
     if (rc) return rc;
-    int first = 0;
+    rc = mixed_refine(pl, w, A, lda, B, ldb, nrhs, resnorm, tol, max_iter, A0, lda0, s, info, iters, async);
+    if (rc || async) return rc;
     bool converged = true;
-    rc = mixed_refine(pl, w, A, lda, B, ldb, nrhs, resnorm, tol, max_iter, A0, lda0, s, &first, &converged);
+    rc = read_verdict(w, nrhs, s, &converged);
+    if (rc || converged) return rc;
+    // FP64 fallback on the restored inputs: the same call as precision FP64,
+    // then the flag ORed into whatever info that call reports
+    HQR_CK(hipMemcpy2DAsync(A, sizeof(double) * lda, A0, sizeof(double) * lda0, sizeof(double) * m, n,
+                            hipMemcpyDeviceToDevice, s));
+    HQR_CK(hipMemcpy2DAsync(B, sizeof(double) * ldb, w.borig, sizeof(double) * m, sizeof(double) * m, nrhs,
+                            hipMemcpyDeviceToDevice, s));
+    rc = lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, nullptr, 0, info, s);
     if (rc) return rc;
-    int hinfo = 0;
-    HQR_CK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
-    HQR_CK(hipStreamSynchronize(s));
-    if (!converged && hinfo == 0) {
-        // FP64 fallback on the restored inputs: the same call as precision FP64
-        HQR_CK(hipMemcpy2DAsync(A, sizeof(double) * lda, A0, sizeof(double) * lda0, sizeof(double) * m, n,
-                                hipMemcpyDeviceToDevice, s));
-        HQR_CK(hipMemcpy2DAsync(B, sizeof(double) * ldb, w.borig, sizeof(double) * m, sizeof(double) * m, nrhs,
-                                hipMemcpyDeviceToDevice, s));
-        rc = lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, nullptr, 0, info, s);
-        if (rc) return rc;
-        hinfo = HQR_INFO_NOCONV;
-        HQR_CK(hipMemcpyAsync(info, &hinfo, sizeof(int), hipMemcpyHostToDevice, s));
-        first = max_iter;
-        HQR_CK(hipStreamSynchronize(s));
-    }
-    return write_iters(iters, first, s);
+    HQR_CK(k_or_int(s, info, HQR_INFO_NOCONV));
+    return 0;
 }
 
 } // namespace hqr
@@ -1088,28 +979,24 @@ using namespace hqr;
 // ------------------------------------------------------------ batched path
 namespace hqr {
 
-// Pinned staging buffer for the descriptor upload; `ready` fences reuse.
-struct Staging {
-    void *host = nullptr;
-    size_t bytes = 0;
-    hipEvent_t ready = nullptr;
-};
-static Staging g_stage;
-
+// Descriptor upload through the caller stream's pinned staging buffer; the
+// buffer's `stage_ready` event fences its reuse by the next call on that
+// stream.
 static int stage_upload(const void *src, size_t bytes, void *dst, hipStream_t s)
 {
-    if (g_stage.ready) HQR_CK(hipEventSynchronize(g_stage.ready));
-    if (g_stage.bytes < bytes) {
-        if (g_stage.host) (void)hipHostFree(g_stage.host);
-        g_stage.host = nullptr;
-        g_stage.bytes = 0;
-        if (hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault) != hipSuccess) return HQR_ENOMEM;
-        g_stage.bytes = bytes;
+    StreamCtx *c = stream_ctx(s);
+    if (!c) return HQR_EDEVICE;
+    HQR_CK(hipEventSynchronize(c->stage_ready));
+    if (c->stage_bytes < bytes) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        c->stage = nullptr;
+        c->stage_bytes = 0;
+        if (hipHostMalloc(&c->stage, bytes, hipHostMallocDefault) != hipSuccess) return HQR_ENOMEM;
+        c->stage_bytes = bytes;
     }
-    if (!g_stage.ready) HQR_CK(hipEventCreateWithFlags(&g_stage.ready, hipEventDisableTiming));
-    memcpy(g_stage.host, src, bytes);
-    HQR_CK(hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, s));
-    HQR_CK(hipEventRecord(g_stage.ready, s));
+    memcpy(c->stage, src, bytes);
+    HQR_CK(hipMemcpyAsync(dst, c->stage, bytes, hipMemcpyHostToDevice, s));
+    HQR_CK(hipEventRecord(c->stage_ready, s));
     return 0;
 }
 
@@ -1215,13 +1102,11 @@ static int lsq_batched_impl(int count, const int64_t *m, const int64_t *n, const
     memcpy(img.data() + sizeof(WgDesc) * (size_t)nwg, sorted.data() + nwg, sizeof(BatchDesc) * (size_t)(count - nwg));
     int rc = stage_upload(img.data(), img.size(), dbase, stream);
     if (rc) return rc;
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, head, 0, (int64_t)2);
+    HQR_CK(k_fill_int(stream, head, 0, (int64_t)2));
     HQR_CK(hipGetLastError());
     if (nwg > 0) {
         const int grid = std::min(nwg, var->per_cu * num_cus());
-        HQR_LAUNCH(K_BATCHED, var->batched, dim3(grid), dim3(var->nt), 0, stream, (const WgDesc *)dbase, nwg, head,
-                   info);
-        HQR_CK(hipGetLastError());
+        HQR_CK(k_wg_batched(var, grid, stream, (const WgDesc *)dbase, nwg, head, info));
     }
     if (nwg < count) {
         BatchArgs a;
@@ -1231,8 +1116,7 @@ static int lsq_batched_impl(int count, const int64_t *m, const int64_t *n, const
         a.info = info;
         a.max_ntot = max_ntot;
         const int grid = std::min(count - nwg, 2 * num_cus());
-        HQR_LAUNCH(K_BATCHED, batched_lsq_kernel, dim3(grid), dim3(1024), 0, stream, a);
-        HQR_CK(hipGetLastError());
+        HQR_CK(k_batched_lsq(dim3(grid), stream, a));
     }
     return 0;
 }
@@ -1277,11 +1161,11 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up, void *wo
     if (n > 0 && !up) return -5;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2) return HQR_ENOTSUP;
     if (n == 0) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
         return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
     }
     if (const WgVariant *v = pick_wg_single(m, n, 0)) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
         HQR_CK(hipGetLastError());
         const WgDesc d{m, n, 0, lda, std::max<int64_t>(1, m), A, nullptr, up, nullptr, 0, WG_FACTOR};
         return launch_wg_single(v, d, info, stream);
@@ -1291,7 +1175,7 @@ int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up, void *wo
     Work w;
     int rc = get_work(pl, work, lwork, stream, g, &w);
     if (rc) return rc;
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+    HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
     HQR_CK(hipGetLastError());
     return factor_blocked(pl, w, A, lda, up, nullptr, 1, 0, stream);
 }
@@ -1309,21 +1193,62 @@ int qr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda
     if (!up) return -6;
     if (!B) return -7;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
-    if (const WgVariant *v = pick_wg_single(m, n, nrhs)) {
-        const WgDesc d{m, n, nrhs, lda, ldb, const_cast<double *>(A), B, const_cast<double *>(up), nullptr, 0, 0};
-        return launch_wg_single(v, d, nullptr, stream);
-    }
     Plan pl = make_plan(m, n, nrhs);
     WorkGuard g;
     Work w;
-    int rc = get_work(pl, work, lwork, stream, g, &w);
-    if (rc) return rc;
-    for (int64_t c0 = 0; c0 < n; c0 += NB) {
-        const int bw = (int)std::min<int64_t>(NB, n - c0);
-        rc = apply_panel_block(pl, TrailBufs{w.wpart, w.T, w.wp}, const_cast<double *>(A), lda, B, ldb, up, (int)c0, bw, 0, 0, (int)nrhs, false, stream);
+    if (!pick_wg_single(m, n, nrhs)) {
+        const int rc = get_work(pl, work, lwork, stream, g, &w);
         if (rc) return rc;
     }
-    return 0;
+    return apply_stored(pl, w, A, lda, up, B, ldb, nrhs, true, false, stream);
+}
+
+int qr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *up, double *B,
+               int64_t ldb, void *work, int64_t lwork, hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (nrhs < 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (ldb < std::max<int64_t>(1, m)) return -8;
+    if (n == 0 || nrhs == 0) return 0;
+    if (!A) return -4;
+    if (!up) return -6;
+    if (!B) return -7;
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
+    Plan pl = make_plan(m, n, nrhs);
+    WorkGuard g;
+    Work w;
+    if (!pick_wg_single(m, n, nrhs)) {
+        const int rc = get_work(pl, work, lwork, stream, g, &w);
+        if (rc) return rc;
+    }
+    return apply_stored(pl, w, A, lda, up, B, ldb, nrhs, false, false, stream);
+}
+
+int qr_form_q(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *up, double *Q,
+              int64_t ldq, void *work, int64_t lwork, hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (k < 0 || k > m) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (ldq < std::max<int64_t>(1, m)) return -8;
+    if (k == 0) return 0;
+    if (!Q) return -7;
+    if (n > 0 && !A) return -4;
+    if (n > 0 && !up) return -6;
+    if (m > INT32_MAX / 2 || k > INT32_MAX / 4) return HQR_ENOTSUP;
+    HQR_CK(k_eye(stream, Q, ldq, m, k));
+    if (n == 0) return 0;
+    Plan pl = make_plan(m, n, k);
+    WorkGuard g;
+    Work w;
+    if (!pick_wg_single(m, n, k)) {
+        const int rc = get_work(pl, work, lwork, stream, g, &w);
+        if (rc) return rc;
+    }
+    return apply_stored(pl, w, A, lda, up, Q, ldq, k, false, true, stream);
 }
 
 int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *B, int64_t ldb, int *info,
@@ -1340,7 +1265,7 @@ int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda, double *
     }
     if (n > INT32_MAX / 2) return HQR_ENOTSUP;
     if (n == 0 || nrhs == 0) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+        HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
         return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
     }
     Plan pl = make_plan(n, n, nrhs);
@@ -1373,11 +1298,11 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
         if (lda_orig < std::max<int64_t>(1, m)) return -12;
         if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
         if (iters) {
-            HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
+            HQR_CK(k_fill_int(stream, iters, 0, (int64_t)1));
             HQR_CK(hipGetLastError());
         }
         if (n == 0 || nrhs == 0) {
-            HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
+            HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
             return hipGetLastError() == hipSuccess ? 0 : HQR_EDEVICE;
         }
         return lsq_mixed(m, n, nrhs, A, lda, up, B, ldb, resnorm, opt, A_orig, lda_orig, work, lwork, info, iters,
@@ -1387,7 +1312,7 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
     (void)lda_orig;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
     if (iters) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
+        HQR_CK(k_fill_int(stream, iters, 0, (int64_t)1));
         HQR_CK(hipGetLastError());
     }
     return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, work, lwork, info, stream);
@@ -1409,15 +1334,12 @@ int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t l
     if (n > 0 && !A_orig) return -11;
     if (lda_orig < std::max<int64_t>(1, m)) return -12;
     if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, info, 0, (int64_t)1);
-    HQR_CK(hipGetLastError());
-    if (iters) {
-        HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(64), 0, stream, iters, 0, (int64_t)1);
-        HQR_CK(hipGetLastError());
-    }
+    HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
+    if (iters) HQR_CK(k_fill_int(stream, iters, 0, (int64_t)1));
     if (n == 0 || nrhs == 0) return 0;
     const double tol = (opt && opt->tol > 0.0) ? opt->tol : 1e-13;
     const int max_iter = (opt && opt->max_iter >= 0) ? opt->max_iter : 10;
+    const bool async = no_fallback(opt);
     Plan pl = make_plan(m, n, nrhs, NB, true);
     WorkGuard g;
     Work w;
@@ -1425,45 +1347,36 @@ int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t l
     if (rc) return rc;
     HQR_CK(hipMemcpy2DAsync(w.borig, sizeof(double) * m, B, sizeof(double) * ldb, sizeof(double) * m, nrhs,
                             hipMemcpyDeviceToDevice, stream));
-    rc = qr_apply_qt(m, n, nrhs, A, lda, up, B, ldb, nullptr, 0, stream);
+    rc = apply_stored(pl, w, A, lda, up, B, ldb, nrhs, true, false, stream);
     if (rc) return rc;
     rc = backsolve_blocked(pl, w, A, lda, B, ldb, (int)nrhs, info, stream);
     if (rc) return rc;
-    int first = 0;
+    rc = mixed_refine(pl, w, A, lda, B, ldb, nrhs, resnorm, tol, max_iter, A_orig, lda_orig, stream, info, iters,
+                      async);
+    if (rc || async) return rc;
     bool converged = true;
-    rc = mixed_refine(pl, w, A, lda, B, ldb, nrhs, resnorm, tol, max_iter, A_orig, lda_orig, stream, &first,
-                      &converged);
+    rc = read_verdict(w, nrhs, stream, &converged);
+    if (rc || converged) return rc;
+    // FP64 solve from a copy of A_orig; the stored factorization is kept
+    double *A2 = nullptr;
+    if (hipMallocAsync((void **)&A2, sizeof(double) * (size_t)m * (size_t)n, stream) != hipSuccess)
+        return HQR_ENOMEM;
+    WorkGuard g2;
+    g2.ptr = A2;
+    g2.s = stream;
+    double *up2 = nullptr;
+    if (hipMallocAsync((void **)&up2, sizeof(double) * (size_t)n, stream) != hipSuccess) return HQR_ENOMEM;
+    WorkGuard g3;
+    g3.ptr = up2;
+    g3.s = stream;
+    HQR_CK(hipMemcpy2DAsync(A2, sizeof(double) * m, A_orig, sizeof(double) * lda_orig, sizeof(double) * m, n,
+                            hipMemcpyDeviceToDevice, stream));
+    HQR_CK(hipMemcpy2DAsync(B, sizeof(double) * ldb, w.borig, sizeof(double) * m, sizeof(double) * m, nrhs,
+                            hipMemcpyDeviceToDevice, stream));
+    rc = lsq_fp64(m, n, nrhs, A2, m, up2, B, ldb, resnorm, nullptr, 0, info, stream);
     if (rc) return rc;
-    int hinfo = 0;
-    HQR_CK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, stream));
-    HQR_CK(hipStreamSynchronize(stream));
-    if (!converged && hinfo == 0) {
-        // FP64 solve from a copy of A_orig; the stored factorization is kept
-        double *A2 = nullptr;
-        if (hipMallocAsync((void **)&A2, sizeof(double) * (size_t)m * (size_t)n, stream) != hipSuccess)
-            return HQR_ENOMEM;
-        WorkGuard g2;
-        g2.ptr = A2;
-        g2.s = stream;
-        double *up2 = nullptr;
-        if (hipMallocAsync((void **)&up2, sizeof(double) * (size_t)n, stream) != hipSuccess) return HQR_ENOMEM;
-        WorkGuard g3;
-        g3.ptr = up2;
-        g3.s = stream;
-        HQR_CK(hipMemcpy2DAsync(A2, sizeof(double) * m, A_orig, sizeof(double) * lda_orig, sizeof(double) * m, n,
-                                hipMemcpyDeviceToDevice, stream));
-        HQR_CK(hipMemcpy2DAsync(B, sizeof(double) * ldb, w.borig, sizeof(double) * m, sizeof(double) * m, nrhs,
-                                hipMemcpyDeviceToDevice, stream));
-        rc = lsq_fp64(m, n, nrhs, A2, m, up2, B, ldb, resnorm, nullptr, 0, info, stream);
-        if (rc) return rc;
-        HQR_CK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, stream));
-        HQR_CK(hipStreamSynchronize(stream));
-        hinfo |= HQR_INFO_NOCONV;
-        HQR_CK(hipMemcpyAsync(info, &hinfo, sizeof(int), hipMemcpyHostToDevice, stream));
-        HQR_CK(hipStreamSynchronize(stream));
-        first = max_iter;
-    }
-    return write_iters(iters, first, stream);
+    HQR_CK(k_or_int(stream, info, HQR_INFO_NOCONV));
+    return 0;
 }
 
 int hqr_tune_set(int op, int64_t m_lo, int64_t m_hi, int64_t n_lo, int64_t n_hi, int precision, int choice)

@@ -24,25 +24,12 @@
 
 #include <utility>
 
-#include "hqr_device.hpp"
+#include "hqr_args.hpp"
 
 namespace hqr {
 
-constexpr int WG_P = 16;    // panel width
-constexpr int WG_LD = 17;   // LDS row stride (doubles) of V and T
-constexpr int WG_PIPE = 4;  // 16-row blocks whose loads the trailing update issues together
 
-enum : int64_t { WG_FACTOR = 1, WG_SOLVE = 2 };
 
-struct WgDesc {
-    int64_t m, n, nrhs, lda, ldb;
-    double *A;
-    double *B;       // may be null when nrhs == 0
-    double *up;
-    double *resnorm; // may be null
-    int64_t index;   // info slot
-    int64_t flags;   // WG_FACTOR | WG_SOLVE
-};
 
 // Rows a variant holds (NT threads x QM rows) bound m; n * nrhs must fit the
 // V area for the back-substitution.
@@ -389,7 +376,9 @@ HQR_DEV double *wg_colptr(const WgDesc &d, int64_t ci, int64_t colA, int64_t ncA
     return (ci < ncA) ? d.A + (size_t)(colA + ci) * d.lda : d.B + (size_t)(ci - ncA) * d.ldb;
 }
 
-template <int NT, int QM>
+// QMODE: C <- C - V T V^T C instead (applying Q_panel rather than its
+// transpose).
+template <int NT, int QM, bool QMODE = false>
 HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA, WgShared<NT, QM> &sh)
 {
     constexpr int NWV = NT / 64;
@@ -427,11 +416,12 @@ HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA,
         f64x4 wm;
 #pragma unroll
         for (int r = 0; r < 4; ++r) wm[r] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
-        // W' = T^T W: A operand T^T[i][4q+k] = T[4q+k][i]; B operand = W's register q
+        // W' = T^T W: A operand T^T[i][4q+k] = T[4q+k][i]; B operand = W's
+        // register q (QMODE: W' = T W, A operand T[i][4q+k])
         f64x4 wp = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double tv = sh.t[(4 * q + kq) * WG_LD + i16];
+            const double tv = QMODE ? sh.t[i16 * WG_LD + 4 * q + kq] : sh.t[(4 * q + kq) * WG_LD + i16];
             wp = __builtin_amdgcn_mfma_f64_16x16x4f64(tv, wm[q], wp, 0, 0, 0);
         }
         // C^T <- C^T - W'^T V^T per 16-row block: D[c][row] at lane row + 16 (c % 4), reg c / 4
@@ -568,6 +558,23 @@ __device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<N
 template <int NT, int QM>
 HQR_DEV void wg_instance(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
 {
+    if (d.flags & WG_APPLY_Q) {
+        // Q B = H_0 .. H_{n-1} B: stored panels applied last to first
+        const int64_t npan = (d.n + WG_P - 1) / WG_P;
+        for (int64_t p = npan - 1; p >= 0; --p) {
+            const int64_t c0 = p * WG_P;
+            const int pw = (int)((d.n - c0 < WG_P) ? d.n - c0 : WG_P);
+            const int64_t j0 = (d.flags & WG_QSKIP) ? c0 : 0;
+            if (d.nrhs <= j0) continue;
+            wg_panel_load<NT, QM>(d, c0, pw, sh);
+            WgDesc dq = d;
+            dq.B = d.B + (size_t)j0 * d.ldb;
+            dq.nrhs = d.nrhs - j0;
+            wg_trailing<NT, QM, true>(dq, c0, c0 + pw, 0, sh);
+            __syncthreads();
+        }
+        return;
+    }
     const bool factor = (d.flags & WG_FACTOR) != 0;
     for (int64_t c0 = 0; c0 < d.n; c0 += WG_P) {
         const int pw = (int)((d.n - c0 < WG_P) ? d.n - c0 : WG_P);

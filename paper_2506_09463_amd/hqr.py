@@ -27,7 +27,8 @@ HQR_TUNE_SINGLE = 0
 HQR_TUNE_BATCHED = 1
 TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 
-EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_backsolve",
+HQR_OPT_NO_FALLBACK = 1
+EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve",
            "qr_lsq_solve", "qr_lsq_refine", "hqr_batched_workspace_size", "qr_lsq_solve_batched",
            "qr_lsq_batched_mixed",
            "hqr_tune_set", "hqr_tune_clear", "hqr_tune_variants", "hqr_tune_variant_name",
@@ -42,7 +43,8 @@ class HQRError(RuntimeError):
 
 
 class hqr_opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("flags", ctypes.c_int)]
 
 
 _lib = None
@@ -61,12 +63,15 @@ def load(path: str = LIB_PATH):
     lib.hqr_workspace_size.restype = i64
     lib.qr_factor.argtypes = [i64, i64, vp, i64, vp, vp, i64, ip, vp]
     lib.qr_apply_qt.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]
+    lib.qr_apply_q.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]
+    lib.qr_form_q.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]
     lib.qr_backsolve.argtypes = [i64, i64, vp, i64, vp, i64, ip, vp]
     lib.qr_lsq_solve.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp,
                                  ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
     lib.qr_lsq_refine.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp,
                                   ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
-    for fn in ("qr_factor", "qr_apply_qt", "qr_backsolve", "qr_lsq_solve", "qr_lsq_refine"):
+    for fn in ("qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve", "qr_lsq_solve",
+               "qr_lsq_refine"):
         getattr(lib, fn).restype = ctypes.c_int
     lib.hqr_status_string.argtypes = [ctypes.c_int]
     lib.hqr_status_string.restype = ctypes.c_char_p
@@ -247,6 +252,35 @@ def qr_apply_qt(A, up, B, work=None, stream=None):
     return B
 
 
+def qr_apply_q(A, up, B, work=None, stream=None):
+    """B <- Q B in place using the output of qr_factor."""
+    lib = load()
+    m, n = A.shape
+    mb, nrhs = B.shape
+    if mb != m:
+        raise ValueError("B must have m rows")
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("qr_apply_q", lib.qr_apply_q(m, n, nrhs, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(B), _ld(B, "B"),
+                                        _ptr(work), lw, _stream(stream)))
+    return B
+
+
+def qr_form_q(A, up, k=None, Q=None, work=None, stream=None):
+    """Leading k columns (default n) of Q from the output of qr_factor, into
+    a new (or the given) m x k column-major device tensor."""
+    lib = load()
+    m, n = A.shape
+    k = n if k is None else int(k)
+    if Q is None:
+        Q = empty_colmajor(m, k, device=A.device)
+    if tuple(Q.shape) != (m, k):
+        raise ValueError("Q must be m x k")
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("qr_form_q", lib.qr_form_q(m, n, k, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(Q), _ld(Q, "Q"),
+                                      _ptr(work), lw, _stream(stream)))
+    return Q
+
+
 def qr_backsolve(R, B, info=None, stream=None):
     """B[0:n] <- R^{-1} B[0:n] with R the upper triangle of the n x n view R."""
     lib = load()
@@ -260,7 +294,7 @@ def qr_backsolve(R, B, info=None, stream=None):
 
 
 def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=HQR_PREC_FP64,
-                 tol=0.0, max_iter=-1, A_orig=None, work=None, stream=None):
+                 tol=0.0, max_iter=-1, A_orig=None, work=None, stream=None, no_fallback=False):
     """Least squares in place: A factored, B[0:n] <- x, returns (up, resnorm, info, iters)."""
     torch = _torch()
     lib = load()
@@ -275,7 +309,7 @@ def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=H
         resnorm = torch.empty(max(nrhs, 1), dtype=torch.float64, device=dev)
     info = _int_dev(info, dev)
     iters = _int_dev(iters, dev)
-    opts = hqr_opts(int(precision), float(tol), int(max_iter))
+    opts = hqr_opts(int(precision), float(tol), int(max_iter), HQR_OPT_NO_FALLBACK if no_fallback else 0)
     lda_o = _ld(A_orig, "A_orig") if A_orig is not None else max(1, m)
     lw = 0 if work is None else work.numel() * work.element_size()
     _check("qr_lsq_solve", lib.qr_lsq_solve(m, n, nrhs, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(B), _ld(B, "B"),
@@ -285,7 +319,7 @@ def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=H
 
 
 def qr_lsq_refine(A, up, B, A_orig, resnorm=None, info=None, iters=None, tol=0.0, max_iter=-1, work=None,
-                  stream=None):
+                  stream=None, no_fallback=False):
     """Solve again with the stored factorization in (A, up) and refine against
     A_orig (FP64 copy of the original matrix); B[0:n] <- x.  A, up are not
     modified.  Returns (resnorm, info, iters)."""
@@ -300,7 +334,7 @@ def qr_lsq_refine(A, up, B, A_orig, resnorm=None, info=None, iters=None, tol=0.0
         resnorm = torch.empty(max(nrhs, 1), dtype=torch.float64, device=dev)
     info = _int_dev(info, dev)
     iters = _int_dev(iters, dev)
-    opts = hqr_opts(HQR_PREC_MIXED, float(tol), int(max_iter))
+    opts = hqr_opts(HQR_PREC_MIXED, float(tol), int(max_iter), HQR_OPT_NO_FALLBACK if no_fallback else 0)
     lw = 0 if work is None else work.numel() * work.element_size()
     _check("qr_lsq_refine", lib.qr_lsq_refine(m, n, nrhs, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(B), _ld(B, "B"),
                                               _ptr(resnorm), ctypes.byref(opts), _ptr(A_orig), _ld(A_orig, "A_orig"),

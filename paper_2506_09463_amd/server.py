@@ -21,6 +21,10 @@ Scheduling policy (host side; the GPU work is libhqr's):
   * factor cache: completed factorizations stay on the device (LRU) for
     later solve-only requests and are evicted least-recently-used when the
     budget needs the bytes;
+  * mixed precision without host waits: a mixed request whose refinement
+    does not converge comes back flagged (HQR_INFO_NOCONV) and is queued
+    again as an FP64 solve of its instance (``fallback``), keeping its slot;
+    the dispatcher never blocks on a convergence read;
   * latency = completion observed by the dispatcher minus arrival.
 
 The executor is pluggable: ``GpuExecutor`` drives libhqr on torch streams;
@@ -39,6 +43,7 @@ import numpy as np
 
 GiB = 1 << 30
 MIXED_MIN_N = 513   # smallest n served by the mixed-precision path
+INFO_NOCONV = 1 << 29  # HQR_INFO_NOCONV
 
 
 @dataclasses.dataclass
@@ -58,6 +63,7 @@ class Request:
     resnorm: Optional[np.ndarray] = None
     info: int = 0
     status: str = "new"            # new|waiting|pending|running|done|rejected
+    fallback: bool = False         # re-run in FP64 after an unconverged refinement
 
     @property
     def nrhs(self) -> int:
@@ -243,6 +249,13 @@ class Server:
             now = self.clock() if now is None else now
             self.ex.collect(handle, batch)
             for r in batch:
+                if r.mixed_path and (r.info & INFO_NOCONV) and not r.fallback:
+                    # refinement did not converge: solve the instance again in
+                    # FP64 (the request keeps its slot and bytes)
+                    r.fallback = True
+                    r.status = "pending"
+                    self.pending.append(r)
+                    continue
                 r.t_done = now
                 r.status = "done"
                 self.done.append(r)
@@ -295,9 +308,16 @@ class GpuExecutor:
     path on the same stream, after the batched launch: FP64 requests by
     qr_lsq_solve (cached factors: qr_apply_qt + qr_backsolve), mixed ones by
     the mixed-precision qr_lsq_solve, keeping an FP64 copy of A beside the
-    factor, and for cached factors qr_lsq_refine against that copy."""
+    factor, and for cached factors qr_lsq_refine against that copy -- both
+    with HQR_OPT_NO_FALLBACK, so no call waits on the host.  A request
+    marked ``fallback`` solves its instance again in FP64 from that copy, in
+    buffers of its own (the cached factor is left as it is).
 
-    def __init__(self, nstreams: int = 2, batch_n_max: int = 512, device="cuda"):
+    ``plain=True`` is the reference executor: one plain FP64 library call
+    per request (qr_lsq_solve, or qr_apply_qt + qr_backsolve on a cached
+    factor), whatever the size and precision flag, no batched launch."""
+
+    def __init__(self, nstreams: int = 2, batch_n_max: int = 512, device="cuda", plain: bool = False):
         import torch
         import paper_2506_09463_amd as hqr
         self.torch = torch
@@ -307,6 +327,7 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
         self.busy = [False] * nstreams
         self.batch_n_max = batch_n_max
+        self.plain = plain
 
     def idle_stream(self) -> bool:
         return not all(self.busy)
@@ -328,18 +349,28 @@ class GpuExecutor:
         with torch.cuda.stream(s):
             small_A, small_B, small_up, small_res, small_fact, small_req = [], [], [], [], [], []
             large = []
+            keep = []
             for r, e in zip(batch, entries):
-                if r.kind == "factor_solve":
+                mixed = r.mixed_path and r.n > self.batch_n_max and not self.plain
+                if r.kind == "factor_solve" and not r.fallback:
                     A = hqr.empty_colmajor(r.m, r.n, device=self.device)
                     A.copy_(self._host(r.A), non_blocking=True)
                     up = torch.empty(max(r.n, 1), dtype=torch.float64, device=self.device)
-                    A0 = A.clone() if (r.mixed_path and r.n > self.batch_n_max) else None
-                    e.handle = (A, up, A0)
-                A, up, A0 = e.handle
+                    A0 = A.clone() if mixed else None
+                    e.handle = [A, up, A0, mixed]
+                A, up, A0, mixed_factor = e.handle
                 B = hqr.empty_colmajor(r.m, r.nrhs, device=self.device)
                 B.copy_(self._host(r.B), non_blocking=True)
                 res = torch.empty(max(r.nrhs, 1), dtype=torch.float64, device=self.device)
-                if r.n <= self.batch_n_max:
+                if r.fallback:
+                    # FP64 solve of the instance from its unmodified copy, in
+                    # buffers of its own (other requests may be reading the
+                    # cached factor on another stream); the cache is unchanged
+                    Afb = A0.clone()
+                    upfb = torch.empty_like(up)
+                    keep += [Afb, upfb]
+                    large.append((r, Afb, upfb, None, B, res, "fp64"))
+                elif r.n <= self.batch_n_max and not self.plain:
                     small_A.append(A)
                     small_B.append(B)
                     small_up.append(up)
@@ -347,21 +378,22 @@ class GpuExecutor:
                     small_fact.append(r.kind == "solve")
                     small_req.append(r)
                 else:
-                    large.append((r, A, up, A0, B, res))
+                    kind = "mixed" if mixed_factor else "fp64"
+                    large.append((r, A, up, A0, B, res, kind))
             info = torch.zeros(max(len(small_req), 1), dtype=torch.int32, device=self.device)
             if small_req:
                 hqr.qr_lsq_solve_batched(small_A, small_B, ups=small_up, resnorms=small_res, info=info,
                                          stream=s, factored=small_fact)
             linfo = []
-            for r, A, up, A0, B, res in large:
+            for r, A, up, A0, B, res, kind in large:
                 li = torch.zeros(1, dtype=torch.int32, device=self.device)
-                if A0 is not None:
+                if kind == "mixed":
                     if r.kind == "factor_solve":
                         hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=li, precision=hqr.HQR_PREC_MIXED,
-                                         A_orig=A0, stream=s)
+                                         A_orig=A0, stream=s, no_fallback=True)
                     else:
-                        hqr.qr_lsq_refine(A, up, B, A0, resnorm=res, info=li, stream=s)
-                elif r.kind == "factor_solve":
+                        hqr.qr_lsq_refine(A, up, B, A0, resnorm=res, info=li, stream=s, no_fallback=True)
+                elif r.kind == "factor_solve" or r.fallback:
                     hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=li, stream=s)
                 else:
                     hqr.qr_apply_qt(A, up, B, stream=s)
@@ -370,10 +402,10 @@ class GpuExecutor:
             ev = torch.cuda.Event()
             ev.record(s)
         outs = {id(r): (B, res) for r, B, res in zip(small_req, small_B, small_res)}
-        for k, (r, A, up, A0, B, res) in enumerate(large):
+        for r, A, up, A0, B, res, kind in large:
             outs[id(r)] = (B, res)
         return {"stream": si, "event": ev, "outs": outs, "small": small_req, "info": info,
-                "large": [(r, li) for (r, *_), li in zip(large, linfo)]}
+                "large": [(r, li) for (r, *_), li in zip(large, linfo)], "keep": keep}
 
     def poll(self, h) -> bool:
         return h["event"].query()
@@ -384,7 +416,7 @@ class GpuExecutor:
         for i, r in enumerate(h["small"]):
             r.info = int(info[i])
         for r, li in h["large"]:
-            r.info = int(li.item())
+            r.info = int(li.item()) | (INFO_NOCONV if r.fallback else 0)
         for r in batch:
             B, res = h["outs"][id(r)]
             r.x = B[: r.n].cpu().numpy()

@@ -52,3 +52,33 @@ def check_reflector_invariants(A0, F, up):
     cn = np.linalg.norm(A0, axis=0)
     rn = np.array([np.linalg.norm(F[: j + 1, j]) for j in range(n)])
     assert np.all(np.abs(cn - rn) <= 100 * m * U * np.maximum(cn, 1e-300)), "column norms"
+
+
+def check_backward_orthogonality(oracle, A0, F, up, ncols=None, seed=0, factor=50.0):
+    """Spec invariants on a GPU factorization: with Q applied from the
+    GPU's own stored reflectors (F, up) by the oracle's apply_q,
+      ||A - Q R||_F / ||A||_F <= 50 n u  and  ||Q^T Q - I||_F <= 50 n u
+    (thin Q, n columns).  With ncols < n both are taken over a seeded sample
+    of ncols columns (of A and R, and of Q); by default all columns up to
+    n = 256 and a sample of 256 beyond.  Returns the two measured values."""
+    m, n = A0.shape
+    if n == 0:
+        return 0.0, 0.0
+    if ncols is None:
+        ncols = 256
+    if ncols >= n:
+        cols = np.arange(n)
+    else:
+        cols = np.sort(np.random.default_rng(seed).choice(n, ncols, replace=False))
+    E = np.zeros((m, cols.size))
+    E[:n] = np.triu(F[:n, :n])[:, cols]
+    QR = oracle.apply_q(F, up, E)
+    berr = np.linalg.norm(A0[:, cols] - QR) / max(np.linalg.norm(A0[:, cols]), 1e-300)
+    I = np.zeros((m, cols.size))
+    I[cols, np.arange(cols.size)] = 1.0
+    Qc = oracle.apply_q(F, up, I)
+    orth = np.linalg.norm(Qc.T @ Qc - np.eye(cols.size))
+    bound = factor * n * U
+    assert berr <= bound, ("||A - QR|| / ||A||", berr, bound)
+    assert orth <= bound, ("||Q^T Q - I||", orth, bound)
+    return berr, orth

@@ -128,3 +128,75 @@ def test_refine_with_fp64_factor_and_fallback(hqr, oracle_mod):
     xo = oracle_mod.lsq_solve(A, b)[0][:, 0]
     r = b - A @ xo
     assert np.linalg.norm(to_host(dB)[:n, 0] - xo) / np.linalg.norm(xo) <= 2 * lsq_forward_bound(A, xo, r)
+
+
+@pytest.mark.parametrize("kappa,seed", [(1e8, 23), (3e7, 24)])
+def test_mixed_never_misses_unflagged(hqr, oracle_mod, kappa, seed):
+    """Conditioning where the FP32-update factor may not support refinement
+    to 1e-10: the result is within 1e-10 of the extended-precision
+    reference, or it carries HQR_INFO_NOCONV (and then equals the plain FP64
+    solve, whose own accuracy is what the conditioning allows).  Never an
+    unflagged miss."""
+    import torch
+    m, n = 128, 64
+    A, b, _ = workloads.conditioned(m, n, kappa, seed=seed)
+    print("[case] mixed stall", (m, n, kappa), flush=True)
+    X, res, info, iters = _mixed(hqr, A, b)
+    xref, _ = oracle_mod.lsq_reference(A, b)
+    err = np.linalg.norm(X[:, 0] - xref) / np.linalg.norm(xref)
+    print("[case] err %.2e info %#x iters %d" % (err, info, iters), flush=True)
+    if info & hqr.HQR_INFO_NOCONV:
+        dA, dB = to_dev(A), to_dev(b.reshape(m, 1))
+        hqr.qr_lsq_solve(dA, dB)
+        torch.cuda.synchronize()
+        assert np.array_equal(X, to_host(dB)[:n])
+    else:
+        assert info == 0
+        assert err <= 1e-10
+
+
+def test_mixed_no_fallback_mode(hqr, oracle_mod):
+    """HQR_OPT_NO_FALLBACK: no host wait; a converged run gives bitwise the
+    default mode's result; an unconverged one is flagged on the device and
+    returns the last iterate (with max_iter = 0: the unrefined solution)."""
+    import torch
+    m, n = 300, 100
+    A, b, _ = workloads.conditioned(m, n, 1e5, seed=25)
+    print("[case] no-fallback", (m, n), flush=True)
+    X1, r1, i1, it1 = _mixed(hqr, A, b)
+    X2, r2, i2, it2 = _mixed(hqr, A, b, no_fallback=True)
+    assert i1 == i2 == 0 and it1 == it2
+    assert np.array_equal(X1, X2) and np.array_equal(r1, r2)
+    X3, r3, i3, it3 = _mixed(hqr, A, b, no_fallback=True, max_iter=0)
+    assert i3 == hqr.HQR_INFO_NOCONV and it3 == 0
+    # the unrefined mixed solution: far from x_ref at kappa 1e5, but finite
+    assert np.isfinite(X3).all()
+
+
+def test_mixed_fallback_keeps_singular_info(hqr):
+    """A rank-deficient input that takes the FP64 fallback (no refinement
+    steps allowed) reports both the fallback and the zero diagonal entry."""
+    rng = np.random.default_rng(26)
+    m, n = 300, 80
+    A = rng.standard_normal((m, n))
+    A[:, 5] = 0.0
+    b = rng.standard_normal(m)
+    print("[case] singular fallback", (m, n), flush=True)
+    X, res, info, iters = _mixed(hqr, A, b, max_iter=0)
+    assert info & hqr.HQR_INFO_NOCONV
+    assert (info & ~hqr.HQR_INFO_NOCONV) == 6
+
+
+def test_mixed_many_rhs_one_verdict(hqr, oracle_mod):
+    """Ten right-hand sides (two TRSV passes) refined together: each within
+    1e-10 of its extended-precision reference."""
+    A, b, _ = workloads.conditioned(400, 150, 1e4, seed=27)
+    rng = np.random.default_rng(28)
+    B = np.column_stack([b] + [A @ rng.standard_normal(150) + 1e-8 * rng.standard_normal(400) for _ in range(9)])
+    print("[case] mixed 10 rhs", flush=True)
+    X, res, info, iters = _mixed(hqr, A, B)
+    assert info == 0
+    for c in range(10):
+        xref, _ = oracle_mod.lsq_reference(A, B[:, c])
+        assert np.linalg.norm(X[:, c] - xref) / np.linalg.norm(xref) <= 1e-10, c
+        assert abs(res[c] - np.linalg.norm(B[:, c] - A @ X[:, c])) <= 1e-12 * max(1.0, np.linalg.norm(B[:, c]))

@@ -153,3 +153,41 @@ def test_percentile_nearest_rank():
     v = list(range(1, 101))
     assert percentile(v, 50) == 50 and percentile(v, 99) == 99 and percentile(v, 100) == 100
     assert percentile([3.0], 99) == 3.0
+
+
+class NoConvExecutor(FakeExecutor):
+    """Reports an unconverged refinement for every mixed request until it is
+    re-run as a fallback."""
+
+    def collect(self, h, batch):
+        super().collect(h, batch)
+        for r in batch:
+            if r.mixed_path and not r.fallback:
+                r.info |= (1 << 29)
+
+
+def test_unconverged_mixed_request_is_requeued_as_fp64(oracle_mod, monkeypatch):
+    from paper_2506_09463_amd import server
+    monkeypatch.setattr(server, "MIXED_MIN_N", 1)
+    clk = Clock()
+    ex = NoConvExecutor(clk, nstreams=1, dur=1.0, oracle=oracle_mod)
+    srv = Server(ex, budget_bytes=1 << 20, clock=clk)
+    a = _req(0, 3, "factor_solve")
+    a.precision = "mixed"
+    b = _req(1, 4, "factor_solve")
+    srv.submit(a)
+    srv.submit(b)
+    srv.step()
+    assert ex.batches == [[0, 1]]
+    clk.t = 1.0
+    srv.step()
+    # b is done; a came back unconverged and runs again as a fallback, keeping
+    # its slot; its solve-only followers still wait for its factor
+    assert b.status == "done" and a.status == "running" and a.fallback
+    assert ex.batches == [[0, 1], [0]] and srv.slots == 1
+    clk.t = 2.0
+    srv.step()
+    assert a.status == "done" and a.t_done == 2.0 and not srv.busy()
+    A0 = np.random.default_rng(0).standard_normal((8, 4))
+    xo, *_ = oracle_mod.lsq_solve(A0, a.B)
+    assert np.allclose(a.x, xo, rtol=1e-12, atol=1e-12)
