@@ -149,7 +149,7 @@ int qr_backsolve(int64_t n, int64_t nrhs, const double *A, int64_t lda,
  *   iters: device int or NULL, refinement steps taken (0 for FP64).
  *   Refinement (opt->tol, opt->max_iter) of every right-hand side: a column
  *   is converged when ||dx|| <= tol ||x||, or when ||dx|| stops halving at or
- *   below 1e-11 ||x|| (the rounding floor); corrections that stop halving
+ *   below 3e-11 ||x|| (the rounding floor); corrections that stop halving
  *   above that floor twice in a row, or max_iter steps without convergence,
  *   mean no convergence.  A converged column's x is left as it is.
  *   The mixed form synchronizes `stream` with the host once, after the
