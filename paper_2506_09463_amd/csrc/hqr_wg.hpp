@@ -541,8 +541,11 @@ __device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<N
             for (int l = 0; l < WG_P; ++l) rv[l] = (l < bw) ? d.A[(size_t)(b0 + l) * d.lda + i] : 0.0;
             for (int64_t c = 0; c < nrhs; ++c) {
                 double acc = xs[c * n + i];
+                // only the block's bw solved rows: past them the staging area
+                // holds other columns' values or stale LDS, and 0 * NaN = NaN
 #pragma unroll
-                for (int l = 0; l < WG_P; ++l) acc = fma(-rv[l], xs[c * n + b0 + l], acc);
+                for (int l = 0; l < WG_P; ++l)
+                    if (l < bw) acc = fma(-rv[l], xs[c * n + b0 + l], acc);
                 xs[c * n + i] = acc;
             }
         }

@@ -78,9 +78,13 @@ def test_mixed_fallback_when_refinement_cannot_converge(hqr, oracle_mod, m, n):
 
 @pytest.mark.parametrize("m,n,kappa", [(128, 64, 1e6), (700, 300, 1e5)])
 def test_refine_with_stored_mixed_factor(hqr, oracle_mod, m, n, kappa):
-    """A factor from a mixed solve is reused for new right-hand sides: each
-    refined solution is within 1e-10 of the extended-precision reference and
-    the stored factor is left bitwise unchanged."""
+    """A factor from a mixed solve is reused for new right-hand sides and the
+    stored factor is left bitwise unchanged.  A nearly consistent right-hand
+    side (b = A x + 1e-8 noise) is refined to within 1e-10 of the
+    extended-precision reference.  A random one (large residual: attainable
+    accuracy about kappa u + kappa^2 u ||r|| / (||A|| ||x||), near 1e-10 at
+    kappa 1e6) is either within 1e-10 unflagged, or flagged and then bitwise
+    the FP64 solve of A_orig."""
     import torch
     A, b, _ = workloads.conditioned(m, n, kappa, seed=19)
     print("[case] refine", (m, n, kappa), flush=True)
@@ -91,17 +95,27 @@ def test_refine_with_stored_mixed_factor(hqr, oracle_mod, m, n, kappa):
     assert int(info.item()) == 0
     F, U = to_host(dA).copy(), to_host(up).copy()
     rng = np.random.default_rng(20)
-    B2 = np.stack([A @ rng.standard_normal(n) + 1e-8 * rng.standard_normal(m), rng.standard_normal(m)], axis=1)
-    dB2 = to_dev(B2)
-    res, info2, it = hqr.qr_lsq_refine(dA, up, dB2, dA0)
-    torch.cuda.synchronize()
-    assert int(info2.item()) == 0 and 1 <= int(it.item()) <= 10
-    assert np.array_equal(to_host(dA), F) and np.array_equal(to_host(up), U)
-    X = to_host(dB2)[:n]
-    for c in range(2):
-        xref, _ = oracle_mod.lsq_reference(A, B2[:, c])
-        assert np.linalg.norm(X[:, c] - xref) / np.linalg.norm(xref) <= 1e-10
-        assert abs(to_host(res)[c] - np.linalg.norm(B2[:, c] - A @ X[:, c])) <= 1e-12 * max(1.0, np.linalg.norm(B2[:, c]))
+    b_cons = A @ rng.standard_normal(n) + 1e-8 * rng.standard_normal(m)
+    b_rand = rng.standard_normal(m)
+    for which, bb in (("consistent", b_cons), ("random", b_rand)):
+        dB2 = to_dev(bb.reshape(m, 1))
+        res, info2, it = hqr.qr_lsq_refine(dA, up, dB2, dA0)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(dA), F) and np.array_equal(to_host(up), U)
+        x = to_host(dB2)[:n, 0]
+        xref, _ = oracle_mod.lsq_reference(A, bb)
+        err = np.linalg.norm(x - xref) / np.linalg.norm(xref)
+        i2 = int(info2.item())
+        print("[case] %s rhs: err %.2e info %#x steps %d" % (which, err, i2, int(it.item())), flush=True)
+        if which == "consistent" or not (i2 & hqr.HQR_INFO_NOCONV):
+            assert i2 == 0 and 1 <= int(it.item()) <= 10
+            assert err <= 1e-10
+            assert abs(to_host(res)[0] - np.linalg.norm(bb - A @ x)) <= 1e-12 * max(1.0, np.linalg.norm(bb))
+        else:
+            dA2, dB3 = to_dev(A), to_dev(bb.reshape(m, 1))
+            hqr.qr_lsq_solve(dA2, dB3)
+            torch.cuda.synchronize()
+            assert np.array_equal(x, to_host(dB3)[:n, 0])
 
 
 def test_refine_with_fp64_factor_and_fallback(hqr, oracle_mod):
