@@ -165,6 +165,23 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
                  void *work, int64_t lwork, int *info, int *iters,
                  hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): qr_lsq_solve in FP64
+ * (opt == NULL) that allocates nothing.  Its workspace is a device array of
+ * HQR_STATIC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends; problems needing more (hqr_workspace_size(m, n, nrhs,
+ * HQR_PREC_FP64) > HQR_STATIC_SCRATCH_BYTES; 8192 x 4096 with up to 8
+ * right-hand sides fits) return HQR_ENOMEM before anything is enqueued.
+ * The look-ahead side stream is not used (everything runs on `stream`), so
+ * nothing is created either.  Arguments, outputs and info as qr_lsq_solve.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from different threads) race and must be
+ * serialized by the caller. */
+#define HQR_STATIC_SCRATCH_BYTES (80ll << 20)
+int qr_lsq_solve_static(int64_t m, int64_t n, int64_t nrhs, double *A,
+                        int64_t lda, double *up, double *B, int64_t ldb,
+                        double *resnorm, int *info, hipStream_t stream);
+
 /* Solve again with a stored factorization (qr_factor's output, from either
  * precision, e.g. a previous mixed-precision qr_lsq_solve), then refine:
  * B (m x nrhs) <- Q^T B, back-substitute, and correct x with the

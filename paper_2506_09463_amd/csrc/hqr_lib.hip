@@ -163,6 +163,7 @@ struct Plan {
     int npanels;
     int nb;          // panel width (<= NB)
     bool f32;        // trailing-update contractions in FP32
+    bool no_side;    // no look-ahead side stream (one stream only)
 };
 
 static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -181,6 +182,7 @@ static Plan make_plan(int64_t m, int64_t n, int64_t nrhs, int nb = NB, bool f32 
     p.nblk = (int)((n + 63) / 64);
     p.ngroups = (int)((m + CQR_ROWS - 1) / CQR_ROWS);
     p.npanels = (int)((n + nb - 1) / nb);
+    p.no_side = false;
     return p;
 }
 
@@ -635,7 +637,7 @@ static int factor_blocked(const Plan &pl, const Work &w, double *A, int64_t lda,
                    (int64_t)pl.npanels));
         HQR_CK(hipGetLastError());
     }
-    StreamCtx *ss = (lookahead_enabled() && pl.npanels > 1) ? stream_ctx(s) : nullptr;
+    StreamCtx *ss = (lookahead_enabled() && pl.npanels > 1 && !pl.no_side) ? stream_ctx(s) : nullptr;
     const TrailBufs bufN{w.wpart, nullptr, w.wp};
     const TrailBufs bufR{w.wpart2, nullptr, w.wp2};
     double *Tbuf[2] = {w.T, w.T2};
@@ -835,7 +837,7 @@ static int apply_stored(const Plan &pl, const Work &w, const double *A, int64_t 
 // The FP64 path: small problems in one register-resident workgroup, larger
 // ones by the blocked factorization, then residual norms and back-substitution.
 static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B, int64_t ldb,
-                    double *resnorm, void *work, int64_t lwork, int *info, hipStream_t s)
+                    double *resnorm, void *work, int64_t lwork, int *info, hipStream_t s, bool side = true)
 {
     if (n == 0) {
         HQR_CK(k_fill_int(s, info, 0, (int64_t)1));
@@ -854,12 +856,12 @@ static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, 
         return launch_wg_single(v, d, info, s);
     }
     Plan pl = make_plan(m, n, nrhs);
+    pl.no_side = !side;
     WorkGuard g;
     Work w;
     int rc = get_work(pl, work, lwork, s, g, &w);
     if (rc) return rc;
     HQR_CK(k_fill_int(s, info, 0, (int64_t)1));
-    HQR_CK(hipGetLastError());
     rc = factor_blocked(pl, w, A, lda, up, B, ldb, (int)nrhs, s);
     if (rc) return rc;
     if (nrhs == 0) return 0;
@@ -1316,6 +1318,57 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
         HQR_CK(hipGetLastError());
     }
     return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, work, lwork, info, stream);
+}
+
+// ------------------------------------------- entry point without allocation
+// qr_lsq_solve_static works in `scratch`, a device array of the library's
+// own (one per GPU, held until the process ends).  Host code never uses the
+// array's name as an address: its device address is looked up once per
+// device with hipGetSymbolAddress, on the first call on that device (with
+// the device current), and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[HQR_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static void *g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static int scratch_address(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return HQR_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HQR_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+int qr_lsq_solve_static(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B,
+                        int64_t ldb, double *resnorm, int *info, hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (nrhs < 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (ldb < std::max<int64_t>(1, m)) return -8;
+    if (!info) return -10;
+    if (n > 0) {
+        if (!A) return -4;
+        if (!up) return -6;
+    }
+    if (nrhs > 0 && !B) return -7;
+    if (m > INT32_MAX / 2 || n > INT32_MAX / 2 || nrhs > INT32_MAX / 4) return HQR_ENOTSUP;
+    const int64_t need = hqr_workspace_size(m, n, nrhs, HQR_PREC_FP64);
+    if (need < 0) return (int)need;
+    if (need > (int64_t)HQR_STATIC_SCRATCH_BYTES) return HQR_ENOMEM;
+    void *p = nullptr;
+    const int rc = scratch_address(&p);
+    if (rc) return rc;
+    return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, p, (int64_t)HQR_STATIC_SCRATCH_BYTES, info, stream,
+                    false);
 }
 
 int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *up, double *B,

@@ -29,7 +29,8 @@ TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 
 HQR_OPT_NO_FALLBACK = 1
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve",
-           "qr_lsq_solve", "qr_lsq_refine", "hqr_batched_workspace_size", "qr_lsq_solve_batched",
+           "qr_lsq_solve", "qr_lsq_solve_static", "qr_lsq_refine", "hqr_batched_workspace_size",
+           "qr_lsq_solve_batched",
            "qr_lsq_batched_mixed",
            "hqr_tune_set", "hqr_tune_clear", "hqr_tune_variants", "hqr_tune_variant_name",
            "hqr_profile_begin", "hqr_profile_end", "hqr_profile_class",
@@ -70,6 +71,8 @@ def load(path: str = LIB_PATH):
                                  ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
     lib.qr_lsq_refine.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp,
                                   ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
+    lib.qr_lsq_solve_static.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, ip, vp]
+    lib.qr_lsq_solve_static.restype = ctypes.c_int
     for fn in ("qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve", "qr_lsq_solve",
                "qr_lsq_refine"):
         getattr(lib, fn).restype = ctypes.c_int
