@@ -132,18 +132,72 @@ def roofline_entry(name, work, prof):
             "avg_launch_ms": avg_ms, "algorithmic_per_launch": amount / cnt}
 
 
+def host_cpu():
+    """(usable cores, CPU model name) of this host."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def cpu_baseline_full_start(A_host, b_host):
+    """Start the oracle's whole least-squares solve of the workload in a
+    thread (single-threaded C); returns the handle for the join."""
+    import threading
+    import oracle
+    oracle.build(force=False)
+    out = {}
+
+    def run():
+        t = time.perf_counter()
+        xo, _, _, reso, infoo = oracle.lsq_solve(A_host, b_host)
+        out.update(x=xo[:, 0], res=float(reso[0]), info=int(infoo), seconds=time.perf_counter() - t)
+
+    th = threading.Thread(target=run, daemon=True)
+    th.start()
+    return th, out
+
+
+def cpu_baseline_full_join(handle):
+    th, out = handle
+    th.join()
+    return out
+
+
 def cpu_baseline(A_host, ncols):
-    """The oracle's QR on the leading ncols columns of the workload matrix."""
+    """The oracle's QR on the leading ncols columns of the workload matrix:
+    single-threaded, and under the paper's barrier schedule on every usable
+    host core (bitwise the same factorization)."""
     import oracle
     oracle.build(force=False)
     sample = np.asfortranarray(A_host[:, :ncols])
+    m, n = sample.shape
     t0 = time.perf_counter()
     oracle.qr_factor(sample)
     dt = time.perf_counter() - t0
-    m, n = sample.shape
+    cores, model = host_cpu()
+    threads = max(1, min(cores, 64))
+    t0 = time.perf_counter()
+    oracle.qr_factor_barrier(sample, threads)
+    dtb = time.perf_counter() - t0
     return {"value": qr_flops(m, n) / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
             "sample": "oracle qr_factor of the leading %dx%d block of the workload matrix "
-                      "(single thread, %.1f s)" % (m, n, dt)}
+                      "(single thread, %.1f s)" % (m, n, dt),
+            "barrier": {"value": qr_flops(m, n) / dtb / 1e9, "unit": "GFLOP/s", "cores": threads,
+                        "seconds": dtb,
+                        "sample": "the same block under the paper's barrier schedule (one barrier after each "
+                                  "reflector's generation and application), %d threads" % threads},
+            "host_nproc": cores, "host_cpu_model": model}
 
 
 def main():
@@ -155,7 +209,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--kappa", type=float, default=1e6)
     ap.add_argument("--ld-pad", type=int, default=0)
-    ap.add_argument("--cpu-cols", type=int, default=1280)
+    ap.add_argument("--cpu-cols", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--workload", default="large", choices=["large", "small", "batched", "mixed", "served"],
@@ -194,6 +248,12 @@ def main():
     t0 = time.time()
     A_h, b_h, x_true = workloads.conditioned(m, n, args.kappa, seed=workloads.SEED_LARGE)
     print("[bench] inputs generated in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+
+    # CPU baseline leg, part 1: the FP64 oracle's whole solve of the same
+    # input, in a thread of its own while the GPU is timed (the C call
+    # releases the interpreter lock); its x also gives the GPU result's error
+    # against the oracle
+    full_oracle = None if args.no_cpu_baseline else cpu_baseline_full_start(A_h, b_h)
 
     lda = m + args.ld_pad
     A0 = hqr.colmajor(A_h, ld=lda)
@@ -281,8 +341,18 @@ def main():
               file=sys.stderr, flush=True)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    oracle_err = None
+    if full_oracle is not None:
+        # CPU baseline leg, part 2: join the whole solve, then the bounded samples
+        fo = cpu_baseline_full_join(full_oracle)
+        xo = fo["x"]
+        oracle_err = {"x_rel_err_vs_oracle": float(np.linalg.norm(x - xo) / np.linalg.norm(xo)),
+                      "resnorm_rel_diff_vs_oracle": abs(float(res.item()) - fo["res"]) / fo["res"],
+                      "oracle_info": fo["info"]}
+        print("[bench] vs oracle: %s (oracle solve %.1f s)" % (oracle_err, fo["seconds"]), file=sys.stderr,
+              flush=True)
         cpu = cpu_baseline(A_h, min(args.cpu_cols, n))
+        cpu["full_solve_seconds_single_thread"] = fo["seconds"]
 
     gflops = qr_flops(m, n) / (ms * 1e-3) / 1e9
     line = {
@@ -302,6 +372,7 @@ def main():
                    "m": m, "n": n, "nrhs": 1, "lda": lda, "kappa": args.kappa,
                    "frac_of_fp64_peak": gflops / 1e3 / PEAK_F64_TFLOPS,
                    "lsq_orthogonality": ortho,
+                   "error_vs_oracle": oracle_err,
                    "x_true_rel_err": float(np.linalg.norm(x - x_true) / np.linalg.norm(x_true)),
                    "wall_s_timed_loop": wall,
                    "ms_per_step_with_kernel_events": prof_ms,
@@ -532,8 +603,7 @@ def run_served(args):
         print("[bench] load %.2f: %s" % (f, st), file=sys.stderr, flush=True)
     cfg = {"workload": "served LSQ stream: %d instances x 3 solves, n log-uniform [16,2048], m = n + U{0..n/2}, "
                        "1-4 RHS, factor reuse, 64 GB budget, 2 streams" % ninst,
-           "requests": len(base), "saturation": sat, "poisson_loads": loads,
-           "note": "precision flag carried; mixed-flagged requests are served in FP64 by this executor"}
+           "requests": len(base), "saturation": sat, "poisson_loads": loads}
     p99 = loads["0.80"]["p99_ms"]
     print(json.dumps(_line(("p99 latency at 0.8 x saturation", "ms"), p99, sat["mean_ms"], args, cfg,
                            None, None, hib=False)), flush=True)

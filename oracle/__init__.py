@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle into ``oracle/liboracle.so`` with gcc."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
@@ -42,6 +42,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         i64, dp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
         lib.oracle_qr_factor.argtypes = [i64, i64, dp, i64, dp]
+        lib.oracle_qr_factor_barrier.argtypes = [i64, i64, dp, i64, dp, ctypes.c_int]
         lib.oracle_apply_qt.argtypes = [i64, i64, i64, dp, i64, dp, dp, i64]
         lib.oracle_apply_q.argtypes = [i64, i64, i64, dp, i64, dp, dp, i64]
         lib.oracle_backsolve.argtypes = [i64, i64, dp, i64, dp, i64, ip]
@@ -52,7 +53,7 @@ def _load():
                                          dp, ip]
         lib.oracle_lsq_refine_ext.argtypes = [i64, i64, dp, i64, dp, i64, dp,
                                               dp, dp, dp, ctypes.c_int]
-        for name in ("oracle_qr_factor", "oracle_apply_qt", "oracle_apply_q",
+        for name in ("oracle_qr_factor", "oracle_qr_factor_barrier", "oracle_apply_qt", "oracle_apply_q",
                      "oracle_backsolve", "oracle_backsolve_t",
                      "oracle_lsq_solve", "oracle_lsq_refine_ext"):
             getattr(lib, name).restype = ctypes.c_int
@@ -84,6 +85,16 @@ def qr_factor(A):
     m, n = F.shape
     up = np.zeros(n, dtype=np.float64)
     _check(_load().oracle_qr_factor(m, n, _p(F), max(1, m), _p(up)), "qr_factor")
+    return F, up
+
+
+def qr_factor_barrier(A, nthreads):
+    """The paper's barrier schedule on `nthreads` threads (timing only; the
+    result is bitwise qr_factor's)."""
+    F = _fmat(A)
+    m, n = F.shape
+    up = np.zeros(n, dtype=np.float64)
+    _check(_load().oracle_qr_factor_barrier(m, n, _p(F), max(1, m), _p(up), int(nthreads)), "qr_factor_barrier")
     return F, up
 
 

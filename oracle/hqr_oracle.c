@@ -125,6 +125,44 @@ int oracle_qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up)
     return 0;
 }
 
+/*
+ * The paper's multi-threaded "barrier" schedule (Section 3.2): for each
+ * pivot k, one thread generates reflector k, all threads wait, then the
+ * trailing columns are shared among the threads and each applies reflector
+ * k to its columns, and all threads wait again before pivot k+1.  Every
+ * column sees exactly the arithmetic of oracle_qr_factor in the same order,
+ * so the result is bitwise the sequential one; only the wall time differs.
+ * Used to time the paper's own CPU baseline; never a parity reference.
+ */
+int oracle_qr_factor_barrier(int64_t m, int64_t n, double *A, int64_t lda,
+                             double *up, int nthreads)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (nthreads < 1) return -6;
+    if (n == 0) return 0;
+    if (!A) return -3;
+    if (!up) return -5;
+    int reflect = 0;
+#pragma omp parallel num_threads(nthreads)
+    {
+        for (int64_t k = 0; k < n; ++k) {
+#pragma omp single
+            reflect = update_pivot_row(m, k, A, lda, &up[k]);
+            /* implicit barrier after the single construct; every thread
+             * reaches the loop's barrier, skipped reflector or not, so no
+             * thread's next `single` can overwrite `reflect` before all have
+             * read it */
+#pragma omp for schedule(static)
+            for (int64_t j = k + 1; j < n; ++j)
+                if (reflect) update_trailing(m, k, A, lda, up[k], AT(A, k, k, lda), &AT(A, 0, j, lda));
+            /* implicit barrier after the loop */
+        }
+    }
+    return 0;
+}
+
 static int check_apply(int64_t m, int64_t n, int64_t nrhs, const double *A,
                        int64_t lda, const double *up, const double *B,
                        int64_t ldb)

@@ -29,6 +29,13 @@ extern "C" {
 /* Factor A in place.  Returns 0, or -i when argument i is invalid. */
 int oracle_qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up);
 
+/* The same factorization under the paper's barrier schedule on nthreads
+ * threads (one barrier after each reflector's generation and after its
+ * application); bitwise the result of oracle_qr_factor.  For timing the
+ * paper's CPU baseline only. */
+int oracle_qr_factor_barrier(int64_t m, int64_t n, double *A, int64_t lda,
+                             double *up, int nthreads);
+
 /* B (m x nrhs) <- Q^T B = H_{n-1} ... H_0 B (reflectors in ascending order). */
 int oracle_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A,
                     int64_t lda, const double *up, double *B, int64_t ldb);

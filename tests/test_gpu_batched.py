@@ -119,3 +119,41 @@ def test_batched_argument_errors(hqr):
     with pytest.raises(hqr.HQRError) as e:
         hqr.qr_lsq_solve_batched([A], [B])
     assert e.value.status == -3
+
+
+@pytest.mark.timeout(900)
+def test_batched_full_workload_vs_oracle(hqr, oracle_mod):
+    """All 2000 instances of the batched workload (n ~ U{16..512},
+    m = n + U{0..n}, 8 right-hand sides) in one launch, the launch the
+    benchmark times, each compared with the oracle: the factored matrix
+    element-wise within 50 n u kappa ||A||, every x within the LSQ forward
+    bound, info exact.  kappa is taken from the oracle's R (same singular
+    values as A)."""
+    import time
+    probs = workloads.batch_problem(count=2000, seed=workloads.SEED_BATCH)
+    _say("full batched workload", len(probs))
+    out, info = _solve_batch(hqr, probs)
+    assert np.all(info == 0)
+    t0 = time.time()
+    worst_f, worst_x = 0.0, 0.0
+    for i, ((A, B), (F, up, X, res)) in enumerate(zip(probs, out)):
+        m, n = A.shape
+        Xo, Fo, upo, reso, infoo = oracle_mod.lsq_solve(A, B)
+        assert infoo == 0, i
+        sv = np.linalg.svd(np.triu(Fo[:n]), compute_uv=False)
+        k, nA = sv[0] / sv[-1], sv[0]
+        ftol = 50 * n * U * k * nA
+        df = np.abs(F - Fo).max()
+        assert df <= ftol, (i, df, ftol)
+        assert np.array_equal(up == 0.0, upo == 0.0), i
+        worst_f = max(worst_f, df / ftol)
+        for c in range(B.shape[1]):
+            xo = Xo[:, c]
+            r = B[:, c] - A @ xo
+            bound = 50 * n * U * k * (1 + k * np.linalg.norm(r) / (nA * np.linalg.norm(xo)))
+            e = np.linalg.norm(X[:n, c] - xo) / np.linalg.norm(xo)
+            assert e <= 2 * bound, (i, c, e, bound)
+            worst_x = max(worst_x, e / bound)
+        if i % 250 == 0:
+            _say("checked %d instances (%.0f s)" % (i + 1, time.time() - t0))
+    _say("worst |F - F_o| / tol %.2e, worst x error / bound %.2e" % (worst_f, worst_x))

@@ -354,3 +354,18 @@ def test_planted_mistakes(tmp_path, name):
 
 def test_unmutated_oracle_passes_pins(oracle_mod):
     assert _pins_pass(ctypes.CDLL(oracle_mod.build(force=False)))
+
+
+@pytest.mark.parametrize("m,n,threads", [(1, 1, 2), (9, 9, 3), (300, 120, 4), (64, 64, 8)])
+def test_barrier_schedule_is_bitwise_sequential(oracle_mod, m, n, threads):
+    """The barrier-scheduled oracle (the paper's multi-threaded baseline,
+    timed by the benchmark) changes only the wall time: every entry of the
+    factorization is bitwise that of the sequential loop, identity
+    reflectors included."""
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n))
+    if n > 3:
+        A[:, 2] = 0.0
+    F1, u1 = oracle_mod.qr_factor(A)
+    F2, u2 = oracle_mod.qr_factor_barrier(A, threads)
+    assert np.array_equal(F1, F2) and np.array_equal(u1, u2)
