@@ -538,45 +538,49 @@ def run_small(args):
 
 def run_served(args):
     """Poisson stream of LSQ requests: n log-uniform in [16, 2048], m = n + U{0..n/2},
-    1-4 RHS, 3 successive solves per instance on its cached factor, 64 GB
-    admission budget.  Saturation throughput first (everything submitted at
-    t=0), then arrival rates 0.5/0.8/0.95 x saturation; p50/p99 latency."""
+    1-4 RHS, FP64 or mixed precision per request (p = 1/2), 3 successive solves
+    per instance on its cached factor, 64 GB admission budget, 2 streams.
+    Saturation throughput first (everything submitted at t = 0), then Poisson
+    arrivals at 0.5/0.8/0.95 x saturation: p50/p99 latency and throughput.
+    The same stream is then served with one plain FP64 library call per
+    request on one stream (no batched launch, no mixed precision): the
+    speedup is the ratio of the two saturation throughputs."""
+    import copy
     import torch
     from paper_2506_09463_amd.server import GpuExecutor, Server, make_stream, poisson_arrivals, GiB
 
-    ninst = args.count if args.count != 2000 else 300
+    ninst = args.count if args.count != 2000 else 5000
     t0 = time.time()
     base = make_stream(ninst, seed=6, solves_per_instance=3)
+    host_bytes = 0
     # pre-pin host data so uploads are asynchronous
     for r in base:
         r.B = torch.from_numpy(np.asfortranarray(r.B)).pin_memory()
+        host_bytes += r.B.numel() * 8
         if r.A is not None:
             r.A = torch.from_numpy(np.asfortranarray(r.A)).pin_memory()
-    print("[bench] %d requests (%d instances) in %.1f s" % (len(base), ninst, time.time() - t0),
-          file=sys.stderr, flush=True)
-    import copy
+            host_bytes += r.A.numel() * 8
+    print("[bench] %d requests (%d instances, %.1f GB pinned) in %.1f s"
+          % (len(base), ninst, host_bytes / 1e9, time.time() - t0), file=sys.stderr, flush=True)
 
-    def fresh():
+    def fresh(reqs):
         out = []
-        for r in base:
+        for r in reqs:
             c = copy.copy(r)
-            c.t_arrival, c.t_done, c.x, c.status = 0.0, -1.0, None, "new"
+            c.t_arrival, c.t_done, c.x, c.status, c.fallback, c.info = 0.0, -1.0, None, "new", False, 0
             out.append(c)
         return out
 
-    class _B:  # numpy-like view for shape access on pinned tensors
-        pass
-
-    def run(rate):
-        reqs = fresh()
-        ex = GpuExecutor(nstreams=2)
+    def run(rate, plain=False, reqs_in=None, keep=False):
+        reqs = fresh(base if reqs_in is None else reqs_in)
+        ex = GpuExecutor(nstreams=1 if plain else 2, plain=plain)
         srv = Server(ex, budget_bytes=64 * GiB)
         start = time.perf_counter()
         if rate is None:
             for r in reqs:
                 r.t_arrival = start
                 srv.submit(r)
-            srv.drain(timeout=600)
+            srv.drain(timeout=900)
         else:
             arr = poisson_arrivals(rate, len(reqs), seed=7)
             i = 0
@@ -590,23 +594,64 @@ def run_served(args):
                 if time.perf_counter() - start > 900:
                     raise TimeoutError("served run did not finish")
         torch.cuda.synchronize()
-        return srv.stats()
+        st = srv.stats()
+        st["fallbacks"] = sum(1 for r in srv.done if r.fallback)
+        st["nonzero_info"] = sum(1 for r in srv.done if r.info & ~(1 << 29))
+        return (st, reqs) if keep else st
 
-    run(None)  # warm-up
-    sat = run(None)
+    run(None, reqs_in=base[:600])                 # warm-up (kernels, allocator)
+    run(None, plain=True, reqs_in=base[:600])
+    sat, done = run(None, keep=True)
     print("[bench] saturation: %s" % sat, file=sys.stderr, flush=True)
+    plain = run(None, plain=True)
+    print("[bench] plain FP64, one call per request: %s" % plain, file=sys.stderr, flush=True)
     rate_sat = sat["throughput_per_s"]
     loads = {}
     for f in (0.5, 0.8, 0.95):
         st = run(f * rate_sat)
         loads["%.2f" % f] = st
         print("[bench] load %.2f: %s" % (f, st), file=sys.stderr, flush=True)
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        cpu, err = served_cpu_baseline(done, base)
     cfg = {"workload": "served LSQ stream: %d instances x 3 solves, n log-uniform [16,2048], m = n + U{0..n/2}, "
-                       "1-4 RHS, factor reuse, 64 GB budget, 2 streams" % ninst,
-           "requests": len(base), "saturation": sat, "poisson_loads": loads}
+                       "1-4 RHS, FP64 or mixed per request, factor reuse, 64 GB budget, 2 streams" % ninst,
+           "requests": len(base), "saturation": sat, "poisson_loads": loads,
+           "plain_fp64_one_call_per_request": plain,
+           "speedup_vs_plain_fp64": sat["throughput_per_s"] / plain["throughput_per_s"],
+           "error_vs_oracle_sample": err}
     p99 = loads["0.80"]["p99_ms"]
     print(json.dumps(_line(("p99 latency at 0.8 x saturation", "ms"), p99, sat["mean_ms"], args, cfg,
-                           None, None, hib=False)), flush=True)
+                           None, cpu, hib=False)), flush=True)
+
+
+def served_cpu_baseline(done, base, nsample=40):
+    """CPU baseline leg of the served workload: the oracle's solves of a
+    seeded sample of the stream's requests, timed (solves/s on one core), and
+    the served results' relative errors against them."""
+    import oracle
+    oracle.build(force=False)
+    mats = {}
+    for r in base:
+        if r.kind == "factor_solve":
+            mats[r.instance] = r.A
+    rng = np.random.default_rng(17)
+    pick = rng.choice(len(done), size=min(nsample, len(done)), replace=False)
+    worst, t_total, nmixed = 0.0, 0.0, 0
+    for i in pick:
+        r = done[i]
+        A = mats[r.instance].numpy()
+        B = r.B.numpy()
+        t = time.perf_counter()
+        xo, *_ = oracle.lsq_solve(A, B)
+        t_total += time.perf_counter() - t
+        e = float(np.linalg.norm(r.x - xo) / np.linalg.norm(xo))
+        worst = max(worst, e)
+        nmixed += int(r.mixed_path)
+    cpu = {"value": len(pick) / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": "oracle lsq_solve of %d requests drawn from the stream (seed 17), %.1f s" % (len(pick), t_total)}
+    return cpu, {"requests": int(len(pick)), "mixed_path_requests": nmixed, "max_x_rel_err_vs_oracle": worst}
 
 
 def run_mixed(args):

@@ -182,10 +182,9 @@ class Server:
     def _admit(self):
         keep = collections.deque()
         while self.queued:
-            req = self.queued.popleft()
             if self.slots >= self.max_slots:
-                keep.append(req)
-                continue
+                break                      # the rest stays queued, in order
+            req = self.queued.popleft()
             entry = self.cache.get(req.instance)
             if req.kind == "solve":
                 if entry is None:
@@ -226,6 +225,7 @@ class Server:
                 self.slots += 1
                 req.status = "pending"
                 self.pending.append(req)
+        keep.extend(self.queued)
         self.queued = keep
 
     def _launch(self):
