@@ -53,7 +53,9 @@ def _load():
                                          dp, ip]
         lib.oracle_lsq_refine_ext.argtypes = [i64, i64, dp, i64, dp, i64, dp,
                                               dp, dp, dp, ctypes.c_int]
+        lib.oracle_lse_solve.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, dp, dp, ip]
         for name in ("oracle_qr_factor", "oracle_qr_factor_barrier", "oracle_apply_qt", "oracle_apply_q",
+                     "oracle_lse_solve",
                      "oracle_backsolve", "oracle_backsolve_t",
                      "oracle_lsq_solve", "oracle_lsq_refine_ext"):
             getattr(lib, name).restype = ctypes.c_int
@@ -146,6 +148,21 @@ def lsq_solve(A, B):
                                     max(1, m), _p(res), ctypes.byref(info)),
            "lsq_solve")
     return Bm[:n].copy(), F, up, res, info.value
+
+
+def lse_solve(A, C, b, d):
+    """Return (x, info) of min ||A x - b|| subject to C x = d."""
+    A = _fmat(A)
+    m, n = A.shape
+    Cm = np.array(np.asarray(C, dtype=np.float64).reshape(-1, n), order="F", copy=True)
+    p = Cm.shape[0]
+    bv = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+    dv = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1))
+    x = np.zeros(n, dtype=np.float64)
+    info = ctypes.c_int(0)
+    _check(_load().oracle_lse_solve(m, n, p, _p(A), max(1, m), _p(Cm), max(1, p), _p(bv), _p(dv), _p(x),
+                                    ctypes.byref(info)), "lse_solve")
+    return x, info.value
 
 
 def lsq_reference(A, b, steps=10):

@@ -342,3 +342,96 @@ int oracle_lsq_refine_ext(int64_t m, int64_t n, const double *A0, int64_t lda0,
     free(g);
     return info ? (int)info : 0;
 }
+
+/*
+ * Equality-constrained least squares, min ||A x - b|| subject to C x = d
+ * (A m x n, C p x n, p <= n), by the null-space method (Golub and Van Loan,
+ * Matrix Computations, Section 6.2) built from the routines above:
+ *   1. C^T = Q [R; 0]              (the in-place Householder QR of C^T)
+ *   2. R^T y1 = d                  (forward substitution)
+ *   3. A Q = (Q^T A^T)^T           (Q^T applied to the columns of A^T)
+ *   4. b1 = b - (A Q)[:, 0:p] y1
+ *   5. y2 = argmin ||(A Q)[:, p:n] y2 - b1||   (the least-squares solve above)
+ *   6. x = Q [y1; y2]
+ * Every x with C x = d is x = Q [y1; y2] for some y2, so step 5 minimizes
+ * over exactly the feasible set.  x (n) is the output; A, C, b, d are left
+ * unchanged.  info: 0; k+1 (k < p) when R_kk == 0 (C rank deficient);
+ * p + k + 1 when the reduced problem's R_kk == 0.  Returns 0 or -i.
+ * SLSQP's least-squares subproblem is of this form with the linearized
+ * equality constraints (paper, Section 1).
+ */
+int oracle_lse_solve(int64_t m, int64_t n, int64_t p, const double *A,
+                     int64_t lda, const double *C, int64_t ldc,
+                     const double *b, const double *d, double *x, int *info)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (p < 0 || p > n) return -3;
+    if (lda < (m > 1 ? m : 1)) return -5;
+    if (ldc < (p > 1 ? p : 1)) return -7;
+    if (m < n - p) return -1;
+    if (!info) return -11;
+    *info = 0;
+    if (n == 0) return 0;
+    if (!x) return -10;
+    int64_t nr = n - p;
+    double *Ct = (double *)malloc(sizeof(double) * (size_t)n * (size_t)(p > 0 ? p : 1));
+    double *upc = (double *)malloc(sizeof(double) * (size_t)(p > 0 ? p : 1));
+    double *At = (double *)malloc(sizeof(double) * (size_t)n * (size_t)(m > 0 ? m : 1));
+    double *Ar = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * (size_t)(nr > 0 ? nr : 1));
+    double *upr = (double *)malloc(sizeof(double) * (size_t)(nr > 0 ? nr : 1));
+    double *b1 = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    double *res = (double *)malloc(sizeof(double) * 1);
+    int rc = 0;
+    if (!Ct || !upc || !At || !Ar || !upr || !b1 || !res) {
+        rc = -100;
+        goto done;
+    }
+    /* 1. C^T (n x p) and its QR */
+    for (int64_t i = 0; i < p; ++i)
+        for (int64_t j = 0; j < n; ++j) AT(Ct, j, i, n) = AT(C, i, j, ldc);
+    if (p > 0) oracle_qr_factor(n, p, Ct, n, upc);
+    /* 2. R^T y1 = d, y1 in x[0:p] */
+    for (int64_t i = 0; i < p; ++i) x[i] = d[i];
+    if (p > 0) {
+        int inf = 0;
+        oracle_backsolve_t(p, 1, Ct, n, x, p > 1 ? p : 1, &inf);
+        if (inf) {
+            *info = inf;
+            goto done;
+        }
+    }
+    /* 3. A^T (n x m), then Q^T A^T */
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) AT(At, j, i, n) = AT(A, i, j, lda);
+    if (p > 0) oracle_apply_qt(n, p, m, Ct, n, upc, At, n);
+    /* 4. b1 = b - (A Q)[:, 0:p] y1, with (A Q)[i][j] = At[j][i] */
+    for (int64_t i = 0; i < m; ++i) {
+        double t = b[i];
+        for (int64_t j = 0; j < p; ++j) t -= AT(At, j, i, n) * x[j];
+        b1[i] = t;
+    }
+    /* 5. the reduced least-squares problem on (A Q)[:, p:n] */
+    for (int64_t j = 0; j < nr; ++j)
+        for (int64_t i = 0; i < m; ++i) AT(Ar, i, j, m) = AT(At, p + j, i, n);
+    if (nr > 0) {
+        int inf = 0;
+        oracle_lsq_solve(m, nr, 1, Ar, m > 1 ? m : 1, upr, b1, m > 1 ? m : 1, res, &inf);
+        if (inf) {
+            *info = (int)p + inf;
+            goto done;
+        }
+        for (int64_t j = 0; j < nr; ++j) x[p + j] = b1[j];
+    }
+    /* 6. x = Q [y1; y2] */
+    if (p > 0) oracle_apply_q(n, p, 1, Ct, n, upc, x, n);
+done:
+    free(Ct);
+    free(upc);
+    free(At);
+    free(Ar);
+    free(upr);
+    free(b1);
+    free(res);
+    return rc;
+}

@@ -70,6 +70,14 @@ int oracle_lsq_refine_ext(int64_t m, int64_t n, const double *A0, int64_t lda0,
                           const double *Af, int64_t ldaf, const double *up,
                           const double *b, double *x, double *r, int steps);
 
+/* Equality-constrained least squares min ||A x - b|| s.t. C x = d
+ * (C p x n, p <= n, m >= n - p) by the null-space method on the routines
+ * above.  x: n outputs.  info: 0, k+1 for a zero pivot of C's R, p+k+1 for
+ * a zero pivot of the reduced problem.  Returns 0 or -i. */
+int oracle_lse_solve(int64_t m, int64_t n, int64_t p, const double *A,
+                     int64_t lda, const double *C, int64_t ldc,
+                     const double *b, const double *d, double *x, int *info);
+
 #ifdef __cplusplus
 }
 #endif
