@@ -165,6 +165,26 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
                  void *work, int64_t lwork, int *info, int *iters,
                  hipStream_t stream);
 
+/* Equality-constrained least squares: x = argmin ||A x - b|| subject to
+ * C x = d (A m x n, C p x n, 0 <= p <= n, m >= n - p), the form of SLSQP's
+ * least-squares subproblem with its linearized equality constraints
+ * (Section 1), solved by the null-space method on this library's QR:
+ *   C^T = Q [R; 0] (qr_factor of C^T), R^T y1 = d, A Q = (Q^T A^T)^T,
+ *   y2 = argmin ||(A Q)[:, p:n] y2 - (b - (A Q)[:, 0:p] y1)|| (the
+ *   least-squares solve above), x = Q [y1; y2].
+ * A (lda >= max(1,m)) is overwritten by A Q and then by the reduced
+ * problem's factorization; b (m) is overwritten; C (ldc >= max(1,p)) and d
+ * (p) are read only; x (n, device) is the output.  Requires rank(C) = p and
+ * the reduced problem of full column rank: info (device int) = k+1 when
+ * C^T's R_kk == 0, p + k + 1 when the reduced problem's R_kk == 0, else 0.
+ * Workspace: hqr_lse_workspace_size(m, n, p) bytes, or NULL.  Returns 0 or
+ * -i (argument i invalid; -3 also when m < n - p). */
+int64_t hqr_lse_workspace_size(int64_t m, int64_t n, int64_t p);
+int qr_lse_solve(int64_t m, int64_t n, int64_t p, double *A, int64_t lda,
+                 double *C, int64_t ldc, double *b, const double *d,
+                 double *x, void *work, int64_t lwork, int *info,
+                 hipStream_t stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): qr_lsq_solve in FP64
  * (opt == NULL) that allocates nothing.  Its workspace is a device array of

@@ -394,6 +394,14 @@ hipError_t k_wg_single(const WgVariant *v, hipStream_t s, const WgDesc &d, int *
 hipError_t k_wg_batched(const WgVariant *v, int grid, hipStream_t s, const WgDesc *desc, int count, int *head,
                         int *info);
 
+// hqr_lse.hpp (k_lse.hip)
+hipError_t k_transpose(hipStream_t s, const double *in, int64_t ldi, double *out, int64_t ldo, int64_t rows,
+                       int64_t cols);
+hipError_t k_gemv_sub(hipStream_t s, const double *M, int64_t ldm, const double *y, double *b, int64_t m,
+                      int64_t p);
+hipError_t k_copy_vec(hipStream_t s, const double *src, double *dst, int64_t n);
+hipError_t k_lse_info(hipStream_t s, int *info, const int *info_c, const int *info_r, int64_t p);
+
 // hqr_batched.hpp (k_batched.hip)
 hipError_t k_batched_lsq(dim3 grid, hipStream_t s, const BatchArgs &a);
 

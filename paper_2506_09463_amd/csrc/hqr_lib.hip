@@ -1371,6 +1371,127 @@ int qr_lsq_solve_static(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t l
                     false);
 }
 
+// ------------------------------------- equality-constrained least squares
+// Pieces of the LSE workspace: C^T, its up, A^T, the reduced problem's up,
+// info words, then one region shared by the sub-steps in turn (each
+// sub-step's own workspace, at most the largest of them).
+struct LseParts {
+    double *ct, *upc, *at, *upr;
+    int *ints;
+    char *sub;
+    int64_t sub_bytes;
+};
+
+static int64_t lse_sub_bytes(int64_t m, int64_t n, int64_t p)
+{
+    int64_t s = 0;
+    if (p > 0) {
+        s = std::max(s, hqr_workspace_size(n, p, 0, HQR_PREC_FP64));
+        s = std::max(s, hqr_workspace_size(n, p, std::max<int64_t>(m, 1), HQR_PREC_FP64));
+        s = std::max(s, hqr_workspace_size(p, p, 1, HQR_PREC_FP64));
+    }
+    if (n - p > 0) s = std::max(s, hqr_workspace_size(m, n - p, 1, HQR_PREC_FP64));
+    return s;
+}
+
+static size_t lse_bytes(int64_t m, int64_t n, int64_t p, LseParts *lp, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *ptr = base ? base + off : nullptr;
+        off += align256(std::max<size_t>(bytes, 1));
+        return ptr;
+    };
+    char *ct = take(sizeof(double) * (size_t)n * (size_t)p);
+    char *upc = take(sizeof(double) * (size_t)p);
+    char *at = take(sizeof(double) * (size_t)n * (size_t)m);
+    char *upr = take(sizeof(double) * (size_t)(n - p));
+    char *ints = take(sizeof(int) * 4);
+    const int64_t sb = lse_sub_bytes(m, n, p);
+    char *sub = take((size_t)sb);
+    if (lp) *lp = LseParts{(double *)ct, (double *)upc, (double *)at, (double *)upr, (int *)ints, sub, sb};
+    return off;
+}
+
+int64_t hqr_lse_workspace_size(int64_t m, int64_t n, int64_t p)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (p < 0 || p > n || m < n - p) return -3;
+    return (int64_t)lse_bytes(m, n, p, nullptr, nullptr);
+}
+
+int qr_lse_solve(int64_t m, int64_t n, int64_t p, double *A, int64_t lda, double *C, int64_t ldc, double *b,
+                 const double *d, double *x, void *work, int64_t lwork, int *info, hipStream_t stream)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (p < 0 || p > n || m < n - p) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (ldc < std::max<int64_t>(1, p)) return -7;
+    if (!info) return -13;
+    if (n > 0 && m > 0 && !A) return -4;
+    if (p > 0 && !C) return -6;
+    if (p > 0 && !d) return -9;
+    if (m > 0 && !b) return -8;
+    if (n > 0 && !x) return -10;
+    if (m > INT32_MAX / 4 || n > INT32_MAX / 4) return HQR_ENOTSUP;
+    HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
+    if (n == 0) return 0;
+    const size_t need = lse_bytes(m, n, p, nullptr, nullptr);
+    WorkGuard g;
+    char *base = (char *)work;
+    if (!base) {
+        if (hipMallocAsync((void **)&base, need, stream) != hipSuccess) return HQR_ENOMEM;
+        g.ptr = base;
+        g.s = stream;
+    } else if (lwork < (int64_t)need) {
+        return HQR_ENOMEM;
+    }
+    LseParts lp;
+    lse_bytes(m, n, p, &lp, base);
+    int *info_c = lp.ints, *info_r = lp.ints + 1;
+    HQR_CK(k_fill_int(stream, lp.ints, 0, (int64_t)4));
+    int rc = 0;
+    if (p > 0) {
+        // 1. C^T = Q [R; 0]
+        HQR_CK(k_transpose(stream, C, ldc, lp.ct, n, p, n));
+        rc = qr_factor(n, p, lp.ct, n, lp.upc, lp.sub, lp.sub_bytes, lp.ints + 2, stream);
+        if (rc) return rc;
+        // 2. R^T y1 = d, y1 in x[0:p]
+        HQR_CK(k_copy_vec(stream, d, x, p));
+        Plan pb = make_plan(p, p, 1);
+        Work wb;
+        WorkGuard gb;
+        rc = get_work(pb, lp.sub, lp.sub_bytes, stream, gb, &wb);
+        if (!rc) rc = backsolve_blocked(pb, wb, lp.ct, n, x, std::max<int64_t>(p, 1), 1, info_c, stream, true);
+        if (rc) return rc;
+        // 3. A Q = (Q^T A^T)^T, written over A
+        if (m > 0) {
+            HQR_CK(k_transpose(stream, A, lda, lp.at, n, m, n));
+            rc = qr_apply_qt(n, p, m, lp.ct, n, lp.upc, lp.at, n, lp.sub, lp.sub_bytes, stream);
+            if (rc) return rc;
+            HQR_CK(k_transpose(stream, lp.at, n, A, lda, n, m));
+            // 4. b -= (A Q)[:, 0:p] y1
+            HQR_CK(k_gemv_sub(stream, A, lda, x, b, m, p));
+        }
+    }
+    // 5. the reduced least-squares problem on (A Q)[:, p:n]; y2 in x[p:n]
+    if (n - p > 0) {
+        rc = lsq_fp64(m, n - p, 1, A + (size_t)p * lda, lda, lp.upr, b, std::max<int64_t>(m, 1), nullptr, lp.sub,
+                      lp.sub_bytes, info_r, stream);
+        if (rc) return rc;
+        HQR_CK(k_copy_vec(stream, b, x + p, n - p));
+    }
+    // 6. x = Q [y1; y2]
+    if (p > 0) {
+        rc = qr_apply_q(n, p, 1, lp.ct, n, lp.upc, x, std::max<int64_t>(n, 1), lp.sub, lp.sub_bytes, stream);
+        if (rc) return rc;
+    }
+    HQR_CK(k_lse_info(stream, info, info_c, info_r, p));
+    return 0;
+}
+
 int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *up, double *B,
                   int64_t ldb, double *resnorm, const hqr_opts *opt, const double *A_orig, int64_t lda_orig,
                   void *work, int64_t lwork, int *info, int *iters, hipStream_t stream)

@@ -29,7 +29,8 @@ TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 
 HQR_OPT_NO_FALLBACK = 1
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve",
-           "qr_lsq_solve", "qr_lsq_solve_static", "qr_lsq_refine", "hqr_batched_workspace_size",
+           "qr_lsq_solve", "qr_lsq_solve_static", "qr_lsq_refine", "hqr_lse_workspace_size", "qr_lse_solve",
+           "hqr_batched_workspace_size",
            "qr_lsq_solve_batched",
            "qr_lsq_batched_mixed",
            "hqr_tune_set", "hqr_tune_clear", "hqr_tune_variants", "hqr_tune_variant_name",
@@ -73,6 +74,10 @@ def load(path: str = LIB_PATH):
                                   ctypes.POINTER(hqr_opts), vp, i64, vp, i64, ip, ip, vp]
     lib.qr_lsq_solve_static.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, ip, vp]
     lib.qr_lsq_solve_static.restype = ctypes.c_int
+    lib.hqr_lse_workspace_size.argtypes = [i64, i64, i64]
+    lib.hqr_lse_workspace_size.restype = i64
+    lib.qr_lse_solve.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, vp, vp, vp, i64, ip, vp]
+    lib.qr_lse_solve.restype = ctypes.c_int
     for fn in ("qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve", "qr_lsq_solve",
                "qr_lsq_refine"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -343,6 +348,27 @@ def qr_lsq_refine(A, up, B, A_orig, resnorm=None, info=None, iters=None, tol=0.0
                                               _ptr(resnorm), ctypes.byref(opts), _ptr(A_orig), _ld(A_orig, "A_orig"),
                                               _ptr(work), lw, _ptr(info), _ptr(iters), _stream(stream)))
     return resnorm, info, iters
+
+
+def qr_lse_solve(A, C, b, d, x=None, info=None, work=None, stream=None):
+    """x = argmin ||A x - b|| subject to C x = d (device tensors: A m x n and
+    C p x n column-major, b (m) and d (p) vectors).  A and b are overwritten.
+    Returns (x, info)."""
+    torch = _torch()
+    lib = load()
+    m, n = A.shape
+    p = C.shape[0]
+    if C.shape[1] != n and p > 0:
+        raise ValueError("C must have n columns")
+    if x is None:
+        x = torch.empty(max(n, 1), dtype=torch.float64, device=A.device)
+    info = _int_dev(info, A.device)
+    ldc = _ld(C, "C") if p > 0 else 1
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("qr_lse_solve", lib.qr_lse_solve(m, n, p, _ptr(A), _ld(A, "A"), _ptr(C) if p > 0 else None, ldc,
+                                            _ptr(b), _ptr(d) if p > 0 else None, _ptr(x), _ptr(work), lw,
+                                            _ptr(info), _stream(stream)))
+    return x, info
 
 
 def profile_begin():
