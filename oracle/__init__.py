@@ -54,8 +54,10 @@ def _load():
         lib.oracle_lsq_refine_ext.argtypes = [i64, i64, dp, i64, dp, i64, dp,
                                               dp, dp, dp, ctypes.c_int]
         lib.oracle_lse_solve.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, dp, dp, ip]
+        lib.oracle_cholesky.argtypes = [i64, dp, i64, ip]
+        lib.oracle_chol_update.argtypes = [i64, dp, i64, dp]
         for name in ("oracle_qr_factor", "oracle_qr_factor_barrier", "oracle_apply_qt", "oracle_apply_q",
-                     "oracle_lse_solve",
+                     "oracle_lse_solve", "oracle_cholesky", "oracle_chol_update",
                      "oracle_backsolve", "oracle_backsolve_t",
                      "oracle_lsq_solve", "oracle_lsq_refine_ext"):
             getattr(lib, name).restype = ctypes.c_int
@@ -163,6 +165,24 @@ def lse_solve(A, C, b, d):
     _check(_load().oracle_lse_solve(m, n, p, _p(A), max(1, m), _p(Cm), max(1, p), _p(bv), _p(dv), _p(x),
                                     ctypes.byref(info)), "lse_solve")
     return x, info.value
+
+
+def cholesky(S):
+    """Return (R, info): R upper with S = R^T R (strict lower part zero)."""
+    F = _fmat(S)
+    n = F.shape[0]
+    info = ctypes.c_int(0)
+    _check(_load().oracle_cholesky(n, _p(F), max(1, n), ctypes.byref(info)), "cholesky")
+    return np.triu(F), info.value
+
+
+def chol_update(R, v):
+    """R' (upper) with R'^T R' = R^T R + v v^T."""
+    F = _fmat(np.triu(R))
+    n = F.shape[0]
+    vv = np.array(np.asarray(v, dtype=np.float64).reshape(-1), copy=True)
+    _check(_load().oracle_chol_update(n, _p(F), max(1, n), _p(vv)), "chol_update")
+    return F
 
 
 def lsq_reference(A, b, steps=10):

@@ -435,3 +435,79 @@ done:
     free(res);
     return rc;
 }
+
+/*
+ * Cholesky factorization S = R^T R of a symmetric positive definite n x n
+ * matrix (upper triangle of S read, R written over it; the strict lower
+ * triangle is left as it is), the textbook column-by-column definition:
+ *   R[j][j] = sqrt(S[j][j] - sum_{k<j} R[k][j]^2),
+ *   R[j][i] = (S[j][i] - sum_{k<j} R[k][j] R[k][i]) / R[j][j]   (i > j),
+ * sums in ascending k.  info = j+1 at the first pivot that is not positive
+ * (S not positive definite; R is then partial), else 0.  SLSQP keeps its
+ * Hessian approximation as such a factorization (paper, Section 6 names
+ * Cholesky as a further kernel of the solver).
+ */
+int oracle_cholesky(int64_t n, double *S, int64_t lds, int *info)
+{
+    if (n < 0) return -1;
+    if (lds < (n > 1 ? n : 1)) return -3;
+    if (!info) return -4;
+    *info = 0;
+    if (n == 0) return 0;
+    if (!S) return -2;
+    for (int64_t j = 0; j < n; ++j) {
+        double t = AT(S, j, j, lds);
+        for (int64_t k = 0; k < j; ++k) t -= AT(S, k, j, lds) * AT(S, k, j, lds);
+        if (!(t > 0.0)) {
+            *info = (int)(j + 1);
+            return 0;
+        }
+        double rjj = sqrt(t);
+        AT(S, j, j, lds) = rjj;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double u = AT(S, j, i, lds);
+            for (int64_t k = 0; k < j; ++k) u -= AT(S, k, j, lds) * AT(S, k, i, lds);
+            AT(S, j, i, lds) = u / rjj;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Rank-one update of a triangular factor: R (n x n upper, ldr) becomes R'
+ * with R'^T R' = R^T R + v v^T, by one plane rotation per row (Golub and
+ * Van Loan, Matrix Computations, Section 6.5.4): for k = 0..n-1,
+ *   r = sgn(R[k][k]) hypot(R[k][k], v[k])  (sgn(0) = +1, keeping the sign
+ *       convention of R's diagonal), c = R[k][k] / r, s = v[k] / r
+ *       (c = 1, s = 0 when r = 0),
+ *   R[k][k] = r; for j > k: (R[k][j], v[j]) <- (c R[k][j] + s v[j],
+ *                                               -s R[k][j] + c v[j]).
+ * The same operation updates the R of a QR factorization when a row v^T is
+ * appended to the matrix.  v is overwritten (it ends as zeros).
+ */
+int oracle_chol_update(int64_t n, double *R, int64_t ldr, double *v)
+{
+    if (n < 0) return -1;
+    if (ldr < (n > 1 ? n : 1)) return -3;
+    if (n == 0) return 0;
+    if (!R) return -2;
+    if (!v) return -4;
+    for (int64_t k = 0; k < n; ++k) {
+        double rkk = AT(R, k, k, ldr);
+        double h = hypot(rkk, v[k]);
+        double r = (rkk >= 0.0) ? h : -h;
+        double c = 1.0, s = 0.0;
+        if (r != 0.0) {
+            c = rkk / r;
+            s = v[k] / r;
+        }
+        AT(R, k, k, ldr) = r;
+        v[k] = 0.0;
+        for (int64_t j = k + 1; j < n; ++j) {
+            double a = AT(R, k, j, ldr), b = v[j];
+            AT(R, k, j, ldr) = c * a + s * b;
+            v[j] = -s * a + c * b;
+        }
+    }
+    return 0;
+}

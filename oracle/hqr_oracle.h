@@ -78,6 +78,14 @@ int oracle_lse_solve(int64_t m, int64_t n, int64_t p, const double *A,
                      int64_t lda, const double *C, int64_t ldc,
                      const double *b, const double *d, double *x, int *info);
 
+/* Cholesky S = R^T R (upper triangle of S overwritten by R).  info = j+1
+ * at the first non-positive pivot, else 0.  Returns 0 or -i. */
+int oracle_cholesky(int64_t n, double *S, int64_t lds, int *info);
+
+/* R'^T R' = R^T R + v v^T by plane rotations (v overwritten).  Returns 0
+ * or -i. */
+int oracle_chol_update(int64_t n, double *R, int64_t ldr, double *v);
+
 #ifdef __cplusplus
 }
 #endif
