@@ -185,6 +185,28 @@ int qr_lse_solve(int64_t m, int64_t n, int64_t p, double *A, int64_t lda,
                  double *x, void *work, int64_t lwork, int *info,
                  hipStream_t stream);
 
+/* Cholesky factorization S = R^T R of a symmetric positive definite n x n
+ * matrix (SLSQP keeps its Hessian approximation in this factored form;
+ * Section 6 names Cholesky as a further kernel of the solver).  Only the
+ * upper triangle of S (lds >= max(1,n), device) is read and it is
+ * overwritten by R (positive diagonal); the strict lower triangle is not
+ * touched.  Right-looking by 64-column blocks on FP64 MFMA.  info (device
+ * int): 0, or j+1 for the first pivot that is not positive (S not positive
+ * definite; R is then partial).  Workspace: 32768 bytes, or NULL.  Returns
+ * 0 or -i. */
+int hqr_cholesky(int64_t n, double *S, int64_t lds, void *work, int64_t lwork,
+                 int *info, hipStream_t stream);
+
+/* Rank-one update of a triangular factor: R (n x n upper, ldr >= max(1,n),
+ * device) becomes R' with R'^T R' = R^T R + v v^T, by one plane rotation per
+ * row, keeping the sign of each diagonal entry.  For a Cholesky factor this
+ * is the factor of the updated matrix; for the R of a QR factorization
+ * (qr_factor's upper triangle, read in place with lda) it is the R of the
+ * matrix with the row v^T appended.  v (n, device) is overwritten.  One
+ * workgroup; n <= 4096 (else HQR_ENOTSUP).  Returns 0 or -i. */
+int hqr_chol_update(int64_t n, double *R, int64_t ldr, double *v,
+                    hipStream_t stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): qr_lsq_solve in FP64
  * (opt == NULL) that allocates nothing.  Its workspace is a device array of

@@ -402,6 +402,13 @@ hipError_t k_gemv_sub(hipStream_t s, const double *M, int64_t ldm, const double 
 hipError_t k_copy_vec(hipStream_t s, const double *src, double *dst, int64_t n);
 hipError_t k_lse_info(hipStream_t s, int *info, const int *info_c, const int *info_r, int64_t p);
 
+// hqr_chol.hpp (k_chol.hip): one 64-column block step of the Cholesky
+// factorization (diagonal block, block row, trailing update); the rank-one
+// update (n <= 4096)
+hipError_t k_chol_block(hipStream_t s, double *S, int64_t lds, int64_t n, int64_t k0, int bw, double *rinv,
+                        int *info);
+hipError_t k_chol_update(hipStream_t s, double *R, int64_t ldr, double *v, int64_t n);
+
 // hqr_batched.hpp (k_batched.hip)
 hipError_t k_batched_lsq(dim3 grid, hipStream_t s, const BatchArgs &a);
 

@@ -1492,6 +1492,45 @@ int qr_lse_solve(int64_t m, int64_t n, int64_t p, double *A, int64_t lda, double
     return 0;
 }
 
+// ------------------------------------------------ Cholesky and its update
+int hqr_cholesky(int64_t n, double *S, int64_t lds, void *work, int64_t lwork, int *info, hipStream_t stream)
+{
+    if (n < 0) return -1;
+    if (lds < std::max<int64_t>(1, n)) return -3;
+    if (!info) return -6;
+    if (n > 0 && !S) return -2;
+    if (n > INT32_MAX / 4) return HQR_ENOTSUP;
+    HQR_CK(k_fill_int(stream, info, 0, (int64_t)1));
+    if (n == 0) return 0;
+    const size_t need = sizeof(double) * 64 * 64;
+    WorkGuard g;
+    double *rinv = (double *)work;
+    if (!rinv) {
+        if (hipMallocAsync((void **)&rinv, need, stream) != hipSuccess) return HQR_ENOMEM;
+        g.ptr = rinv;
+        g.s = stream;
+    } else if (lwork < (int64_t)need) {
+        return HQR_ENOMEM;
+    }
+    for (int64_t k0 = 0; k0 < n; k0 += 64) {
+        const int bw = (int)std::min<int64_t>(64, n - k0);
+        HQR_CK(k_chol_block(stream, S, lds, n, k0, bw, rinv, info));
+    }
+    return 0;
+}
+
+int hqr_chol_update(int64_t n, double *R, int64_t ldr, double *v, hipStream_t stream)
+{
+    if (n < 0) return -1;
+    if (ldr < std::max<int64_t>(1, n)) return -3;
+    if (n > 0 && !R) return -2;
+    if (n > 0 && !v) return -4;
+    if (n > 4096) return HQR_ENOTSUP;
+    if (n == 0) return 0;
+    HQR_CK(k_chol_update(stream, R, ldr, v, n));
+    return 0;
+}
+
 int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *up, double *B,
                   int64_t ldb, double *resnorm, const hqr_opts *opt, const double *A_orig, int64_t lda_orig,
                   void *work, int64_t lwork, int *info, int *iters, hipStream_t stream)

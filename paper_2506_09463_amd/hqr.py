@@ -30,7 +30,7 @@ TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 HQR_OPT_NO_FALLBACK = 1
 EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve",
            "qr_lsq_solve", "qr_lsq_solve_static", "qr_lsq_refine", "hqr_lse_workspace_size", "qr_lse_solve",
-           "hqr_batched_workspace_size",
+           "hqr_cholesky", "hqr_chol_update", "hqr_batched_workspace_size",
            "qr_lsq_solve_batched",
            "qr_lsq_batched_mixed",
            "hqr_tune_set", "hqr_tune_clear", "hqr_tune_variants", "hqr_tune_variant_name",
@@ -78,6 +78,10 @@ def load(path: str = LIB_PATH):
     lib.hqr_lse_workspace_size.restype = i64
     lib.qr_lse_solve.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, vp, vp, vp, i64, ip, vp]
     lib.qr_lse_solve.restype = ctypes.c_int
+    lib.hqr_cholesky.argtypes = [i64, vp, i64, vp, i64, ip, vp]
+    lib.hqr_cholesky.restype = ctypes.c_int
+    lib.hqr_chol_update.argtypes = [i64, vp, i64, vp, vp]
+    lib.hqr_chol_update.restype = ctypes.c_int
     for fn in ("qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve", "qr_lsq_solve",
                "qr_lsq_refine"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -369,6 +373,28 @@ def qr_lse_solve(A, C, b, d, x=None, info=None, work=None, stream=None):
                                             _ptr(b), _ptr(d) if p > 0 else None, _ptr(x), _ptr(work), lw,
                                             _ptr(info), _stream(stream)))
     return x, info
+
+
+def cholesky(S, info=None, work=None, stream=None):
+    """S (n x n column-major device tensor, upper triangle) <- R with
+    S = R^T R in place; returns (S, info)."""
+    lib = load()
+    n = S.shape[0]
+    if S.shape[1] != n:
+        raise ValueError("S must be square")
+    info = _int_dev(info, S.device)
+    lw = 0 if work is None else work.numel() * work.element_size()
+    _check("hqr_cholesky", lib.hqr_cholesky(n, _ptr(S), _ld(S, "S"), _ptr(work), lw, _ptr(info), _stream(stream)))
+    return S, info
+
+
+def chol_update(R, v, stream=None):
+    """R (n x n upper, column-major device tensor) <- R' with
+    R'^T R' = R^T R + v v^T in place; v (device vector) is overwritten."""
+    lib = load()
+    n = R.shape[1]
+    _check("hqr_chol_update", lib.hqr_chol_update(n, _ptr(R), _ld(R, "R"), _ptr(v), _stream(stream)))
+    return R
 
 
 def profile_begin():
