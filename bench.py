@@ -212,7 +212,7 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--workload", default="large", choices=["large", "small", "batched", "mixed", "served"],
+    ap.add_argument("--workload", default="large", choices=["large", "small", "batched", "mixed", "served", "slsqp"],
                     help="large (default, the headline line), or one of the other configurations")
     ap.add_argument("--count", type=int, default=2000, help="batched: number of instances")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -723,7 +723,34 @@ def run_mixed(args):
           flush=True)
 
 
-OTHER = {"batched": run_batched, "small": run_small, "mixed": run_mixed, "served": run_served}
+def run_slsqp(args):
+    """The synthetic SLSQP-style driver (Gauss-Newton with two chord
+    corrections per factorization on a discretized nonlinear boundary-value
+    fit, n log-uniform in [32, 1024]): every subproblem is a request to the
+    continuous-batching server; reports the request rate, latency and the
+    outer iterations to convergence."""
+    from paper_2506_09463_amd import slsqp_driver
+    from paper_2506_09463_amd.server import GpuExecutor, Server, percentile, GiB
+    count = args.count if args.count != 2000 else 200
+    probs = slsqp_driver.make_problems(count, seed=11, nmin=32, nmax=1024)
+    warm = slsqp_driver.make_problems(8, seed=12, nmin=32, nmax=1024)
+    slsqp_driver.run_served(warm, Server(GpuExecutor(nstreams=2), budget_bytes=64 * GiB), max_outer=3)
+    srv = Server(GpuExecutor(nstreams=2), budget_bytes=64 * GiB)
+    stats, us = slsqp_driver.run_served(probs, srv, max_outer=15, tol=1e-11)
+    lat = stats.latencies_ms
+    print("[bench] slsqp driver: %d instances, %d outer iterations, %d requests in %.2f s, %d converged"
+          % (count, stats.outer_iterations, stats.requests, stats.wall_s, stats.converged), file=sys.stderr,
+          flush=True)
+    cfg = {"workload": "synthetic SLSQP-style driver: %d nonlinear BVP fits, n log-uniform [32, 1024], "
+                       "Gauss-Newton step + 2 chord solves per factor, served" % count,
+           "instances": count, "outer_iterations": stats.outer_iterations, "requests": stats.requests,
+           "converged": stats.converged, "wall_s": stats.wall_s,
+           "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99)}
+    print(json.dumps(_line(("LSQ requests/s (synthetic SLSQP driver)", "requests/s"), stats.requests / stats.wall_s,
+                           stats.wall_s * 1e3, args, cfg)), flush=True)
+
+
+OTHER = {"batched": run_batched, "small": run_small, "mixed": run_mixed, "served": run_served, "slsqp": run_slsqp}
 
 
 if __name__ == "__main__":
