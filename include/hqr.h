@@ -290,14 +290,20 @@ int qr_lsq_batched_mixed(int count, const int64_t *m, const int64_t *n,
  *     only variants with 256 threads qualify (they share one arithmetic, so
  *     results do not depend on the batch); without a rule, the smallest such
  *     variant that holds the largest m.
+ *   op HQR_TUNE_OCCUPANCY: workgroups per CU of the batched launch (choice
+ *     1..8, capped by what the variant's LDS allows), matched like
+ *     HQR_TUNE_BATCHED; without a rule, min(2, that cap).
  * Host-side state, process-global, not thread-safe.  Returns 0 or -i. */
-#define HQR_TUNE_SINGLE  0
-#define HQR_TUNE_BATCHED 1
+#define HQR_TUNE_SINGLE    0
+#define HQR_TUNE_BATCHED   1
+#define HQR_TUNE_OCCUPANCY 2
 int hqr_tune_set(int op, int64_t m_lo, int64_t m_hi, int64_t n_lo,
                  int64_t n_hi, int precision, int choice);
 int hqr_tune_clear(void);
-/* Number of one-workgroup variants, and the name of variant i ("wgNTxQM":
- * NT threads holding QM rows each, so m <= NT*QM), or NULL. */
+/* Number of one-workgroup variants, and the name of variant i ("wgNTxQM"
+ * or "wgNTxQMpP": NT threads holding QM rows each, so m <= NT*QM, and P
+ * 16-row blocks loaded together in the trailing update, 4 when not given),
+ * or NULL. */
 int hqr_tune_variants(void);
 const char *hqr_tune_variant_name(int i);
 

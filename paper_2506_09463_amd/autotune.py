@@ -1,17 +1,21 @@
 """Autotuner: measures libhqr's kernel choices on the GPU and writes the rule
 database that ``hqr.load()`` installs (``tune_db.json`` next to the library).
 
-Two decisions are tuned, each per shape bucket:
+Three decisions are tuned, each per shape bucket:
   * single problems (qr_lsq_solve, qr_factor, qr_apply_qt): the blocked
-    multi-kernel path or one of the one-workgroup kernel variants, bucketed
-    by (m, n); timed on one seeded N(0,1) problem at the bucket's upper
-    corner with one right-hand side;
-  * batched launches: the one-workgroup variant (256-thread variants only),
-    bucketed by the batch's largest m; timed on a seeded batch of uneven
-    instances (n ~ U{16..min(512, m_hi/2)}, m = n + U{0..n}, 8 RHS).
+    multi-kernel path or one of the one-workgroup kernel variants (threads,
+    rows per thread, trailing-update load depth), bucketed by (m, n); timed
+    on one seeded N(0,1) problem at the bucket's upper corner with one
+    right-hand side;
+  * batched launches: the one-workgroup variant (256-thread variants only:
+    rows per thread and load depth) together with the workgroups per CU of
+    the persistent launch, bucketed by the batch's largest m; timed on a
+    seeded batch of uneven instances (n ~ U{16..min(512, m_hi/2)},
+    m = n + U{0..n}, 8 RHS).
 Every candidate that can hold the bucket's shape is run (exhaustive search,
-as in the paper's parameter sweep of Section 4.1, here over kernel variants
-instead of thread counts and chunk sizes); the fastest median wins.
+as in the paper's parameter sweep of Section 4.1, here over kernel tile and
+schedule parameters instead of thread counts and chunk sizes); the fastest
+median wins.
 
     python -m paper_2506_09463_amd.autotune --out tune_db.json
 
@@ -30,13 +34,20 @@ import numpy as np
 
 M_BUCKETS = [(1, 64), (65, 128), (129, 256), (257, 512), (513, 1024)]
 N_BUCKETS = [(1, 16), (17, 32), (33, 64), (65, 128), (129, 256), (257, 512), (513, 1024)]
-BATCH_M_BUCKETS = [(1, 512), (513, 1024)]
+BATCH_M_BUCKETS = [(1, 256), (257, 512), (513, 1024)]
+OCCUPANCIES = (1, 2, 3, 4)
+LDS_BYTES = 160 * 1024
 
 
-def _median_ms(fn, reps, stream):
+def _median_ms(fn, reps, stream, setup=None):
+    """Median event time of fn() on `stream`; setup() (restoring the inputs)
+    runs before each repetition, outside the timed region."""
     import torch
     ts = []
     for _ in range(reps):
+        if setup is not None:
+            setup()
+            torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -48,8 +59,17 @@ def _median_ms(fn, reps, stream):
 
 
 def _variant_rows(name):
-    nt, qm = (int(x) for x in name[2:].split("x"))
+    from paper_2506_09463_amd.hqr import variant_shape
+    nt, qm, _ = variant_shape(name)
     return nt, nt * qm, nt * qm * 17
+
+
+def _max_per_cu(name):
+    """Workgroups per CU the variant's LDS (V area, T, reductions) allows."""
+    from paper_2506_09463_amd.hqr import variant_shape
+    nt, qm, _ = variant_shape(name)
+    lds = 8 * (nt * qm * 17 + 16 * 17 + 2 * (nt // 64) * 17 + 32 + nt // 64) + 16
+    return max(1, LDS_BYTES // lds)
 
 
 def tune_single(hqr, seed=11, reps=7, log=print):
@@ -71,9 +91,11 @@ def tune_single(hqr, seed=11, reps=7, log=print):
             res = torch.empty(1, dtype=torch.float64, device="cuda")
             info = torch.zeros(1, dtype=torch.int32, device="cuda")
 
-            def run():
+            def restore():
                 A.copy_(A0)
                 B.copy_(B0)
+
+            def run():
                 hqr.qr_lsq_solve(A, B, up=up, resnorm=res, info=info, stream=stream)
 
             cands = ["blocked"] + [nm for nm in names if _variant_rows(nm)[1] >= m and _variant_rows(nm)[2] >= n]
@@ -81,11 +103,12 @@ def tune_single(hqr, seed=11, reps=7, log=print):
             for c in cands:
                 hqr.tune_clear()
                 hqr.tune_set(hqr.HQR_TUNE_SINGLE, 0, 1 << 40, 0, 1 << 40, -1 if c == "blocked" else names.index(c))
+                restore()
                 run()
                 torch.cuda.synchronize()
-                times[c] = _median_ms(run, reps, stream)
+                times[c] = _median_ms(run, reps, stream, restore)
             hqr.tune_clear()
-            base = _median_ms(run, reps, stream)  # built-in default
+            base = _median_ms(run, reps, stream, restore)  # built-in default
             best = min(times, key=times.get)
             meas.append({"op": "single", "m": [mlo, mhi], "n": [nlo, nhi], "shape": [m, n], "ms": times,
                          "default_ms": base})
@@ -94,7 +117,7 @@ def tune_single(hqr, seed=11, reps=7, log=print):
     return rules, meas
 
 
-def tune_batched(hqr, seed=12, count=256, reps=5, log=print):
+def tune_batched(hqr, seed=12, count=512, reps=5, log=print):
     import torch
     names = hqr.tune_variants()
     stream = torch.cuda.current_stream()
@@ -116,25 +139,33 @@ def tune_batched(hqr, seed=12, count=256, reps=5, log=print):
         info = torch.zeros(len(probs), dtype=torch.int32, device="cuda")
         work = torch.empty(hqr.batched_workspace_size(len(probs)), dtype=torch.uint8, device="cuda")
 
-        def run():
+        def restore():
             for a, a0 in zip(As, A0):
                 a.copy_(a0)
             for b, b0 in zip(Bs, B0):
                 b.copy_(b0)
+
+        def run():
             hqr.qr_lsq_solve_batched(As, Bs, ups=ups, resnorms=res, info=info, work=work, stream=stream)
 
-        cands = [nm for nm in names if nm.startswith("wg256x") and _variant_rows(nm)[1] >= max(A.shape[0] for A, _ in probs)]
+        mmax = max(A.shape[0] for A, _ in probs)
+        cands = [(nm, occ) for nm in names if nm.startswith("wg256x") and _variant_rows(nm)[1] >= mmax
+                 for occ in OCCUPANCIES if occ <= _max_per_cu(nm)]
         times = {}
-        for c in cands:
+        for nm, occ in cands:
             hqr.tune_clear()
-            hqr.tune_set(hqr.HQR_TUNE_BATCHED, 0, 1 << 40, 0, 1 << 40, names.index(c))
+            hqr.tune_set(hqr.HQR_TUNE_BATCHED, 0, 1 << 40, 0, 1 << 40, names.index(nm))
+            hqr.tune_set(hqr.HQR_TUNE_OCCUPANCY, 0, 1 << 40, 0, 1 << 40, occ)
+            restore()
             run()
             torch.cuda.synchronize()
-            times[c] = _median_ms(run, reps, stream)
+            times["%s/%d" % (nm, occ)] = _median_ms(run, reps, stream, restore)
         hqr.tune_clear()
         best = min(times, key=times.get)
+        bname, bocc = best.split("/")
         meas.append({"op": "batched", "m": [mlo, mhi], "count": count, "ms": times})
-        rules.append({"op": "batched", "m": [mlo, mhi], "n": [0, 1 << 40], "choice": best})
+        rules.append({"op": "batched", "m": [mlo, mhi], "n": [0, 1 << 40], "choice": bname})
+        rules.append({"op": "occupancy", "m": [mlo, mhi], "n": [0, 1 << 40], "choice": int(bocc)})
         log("[tune] batched m<=%d: %s -> %s" % (mhi, {k: round(v, 3) for k, v in times.items()}, best))
     return rules, meas
 

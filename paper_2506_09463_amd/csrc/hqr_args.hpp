@@ -290,7 +290,7 @@ constexpr int WG_P = 16;    // panel width
 
 constexpr int WG_LD = 17;   // LDS row stride (doubles) of V and T
 
-constexpr int WG_PIPE = 4;  // 16-row blocks whose loads the trailing update issues together
+constexpr int WG_PIPE = 4;  // default 16-row blocks whose loads the trailing update issues together
 
 // WG_FACTOR: factor A (B's columns ride along: Q^T B); without it A and up
 // hold a stored factorization, which is applied to B: Q^T B, or Q B with
@@ -385,7 +385,8 @@ hipError_t k_xw_reduce(hipStream_t s, const XwArgs &a);
 // threads holding QM rows each)
 struct WgVariant {
     const char *name;
-    int nt, qm, per_cu;
+    int nt, qm, pipe;
+    int per_cu;         // workgroups per CU the LDS allows
     int64_t max_rows, max_x;
     int index;          // position in wg_variants()
 };

@@ -1107,7 +1107,9 @@ static int lsq_batched_impl(int count, const int64_t *m, const int64_t *n, const
     HQR_CK(k_fill_int(stream, head, 0, (int64_t)2));
     HQR_CK(hipGetLastError());
     if (nwg > 0) {
-        const int grid = std::min(nwg, var->per_cu * num_cus());
+        int occ = tune_lookup(HQR_TUNE_OCCUPANCY, mmax, nmax, HQR_PREC_FP64);
+        occ = (occ >= 1) ? std::min(occ, var->per_cu) : std::min(var->per_cu, 2);
+        const int grid = std::min(nwg, occ * num_cus());
         HQR_CK(k_wg_batched(var, grid, stream, (const WgDesc *)dbase, nwg, head, info));
     }
     if (nwg < count) {
@@ -1594,7 +1596,7 @@ int qr_lsq_refine(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t l
 
 int hqr_tune_set(int op, int64_t m_lo, int64_t m_hi, int64_t n_lo, int64_t n_hi, int precision, int choice)
 {
-    if (op != HQR_TUNE_SINGLE && op != HQR_TUNE_BATCHED) return -1;
+    if (op != HQR_TUNE_SINGLE && op != HQR_TUNE_BATCHED && op != HQR_TUNE_OCCUPANCY) return -1;
     if (m_lo < 0) return -2;
     if (m_hi < m_lo) return -3;
     if (n_lo < 0) return -4;
@@ -1602,8 +1604,12 @@ int hqr_tune_set(int op, int64_t m_lo, int64_t m_hi, int64_t n_lo, int64_t n_hi,
     if (precision != HQR_PREC_FP64 && precision != HQR_PREC_MIXED) return -6;
     int cnt = 0;
     (void)wg_variants(&cnt);
-    if (choice < (op == HQR_TUNE_SINGLE ? -1 : 0) || choice >= cnt) return -7;
-    if (op == HQR_TUNE_BATCHED && !batch_variant(wg_variants(&cnt)[choice])) return -7;
+    if (op == HQR_TUNE_OCCUPANCY) {
+        if (choice < 1 || choice > 8) return -7;
+    } else {
+        if (choice < (op == HQR_TUNE_SINGLE ? -1 : 0) || choice >= cnt) return -7;
+        if (op == HQR_TUNE_BATCHED && !batch_variant(wg_variants(&cnt)[choice])) return -7;
+    }
     g_rules.push_back(TuneRule{op, m_lo, m_hi, n_lo, n_hi, precision, choice});
     return 0;
 }

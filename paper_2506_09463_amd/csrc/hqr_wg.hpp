@@ -377,8 +377,9 @@ HQR_DEV double *wg_colptr(const WgDesc &d, int64_t ci, int64_t colA, int64_t ncA
 }
 
 // QMODE: C <- C - V T V^T C instead (applying Q_panel rather than its
-// transpose).
-template <int NT, int QM, bool QMODE = false>
+// transpose).  PIPE: 16-row blocks whose loads are issued together (load
+// scheduling only: the arithmetic and its order do not depend on it).
+template <int NT, int QM, int PIPE, bool QMODE = false>
 HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA, WgShared<NT, QM> &sh)
 {
     constexpr int NWV = NT / 64;
@@ -394,17 +395,17 @@ HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA,
         f64x4 acc[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-        // WG_PIPE 16-row blocks per round: all their loads are issued first
-        for (int64_t rb0 = 0; rb0 < nb16; rb0 += WG_PIPE) {
-            double cv[WG_PIPE][4];
+        // PIPE 16-row blocks per round: all their loads are issued first
+        for (int64_t rb0 = 0; rb0 < nb16; rb0 += PIPE) {
+            double cv[PIPE][4];
 #pragma unroll
-            for (int u = 0; u < WG_PIPE; ++u) {
+            for (int u = 0; u < PIPE; ++u) {
                 const int64_t rr0 = (rb0 + u) * 16 + 4 * kq;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) cv[u][s] = (cp && rr0 + s < nrows) ? cp[c0 + rr0 + s] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < WG_PIPE; ++u) {
+            for (int u = 0; u < PIPE; ++u) {
                 const int64_t rr0 = (rb0 + u) * 16 + 4 * kq;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
@@ -428,16 +429,16 @@ HQR_DEV void wg_trailing(const WgDesc &d, int64_t c0, int64_t colA, int64_t ncA,
         double *cq[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g) cq[g] = wg_colptr(d, tile * 16 + 4 * g + kq, colA, ncA, ntot);
-        for (int64_t rb0 = 0; rb0 < nb16; rb0 += WG_PIPE) {
-            f64x4 cacc[WG_PIPE];
+        for (int64_t rb0 = 0; rb0 < nb16; rb0 += PIPE) {
+            f64x4 cacc[PIPE];
 #pragma unroll
-            for (int u = 0; u < WG_PIPE; ++u) {
+            for (int u = 0; u < PIPE; ++u) {
                 const int64_t rr = (rb0 + u) * 16 + i16;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) cacc[u][g] = (cq[g] && rr < nrows) ? cq[g][c0 + rr] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < WG_PIPE; ++u) {
+            for (int u = 0; u < PIPE; ++u) {
                 const int64_t rr = (rb0 + u) * 16 + i16;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -558,7 +559,7 @@ __device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<N
     __syncthreads();
 }
 
-template <int NT, int QM>
+template <int NT, int QM, int PIPE>
 HQR_DEV void wg_instance(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
 {
     if (d.flags & WG_APPLY_Q) {
@@ -573,7 +574,7 @@ HQR_DEV void wg_instance(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
             WgDesc dq = d;
             dq.B = d.B + (size_t)j0 * d.ldb;
             dq.nrhs = d.nrhs - j0;
-            wg_trailing<NT, QM, true>(dq, c0, c0 + pw, 0, sh);
+            wg_trailing<NT, QM, PIPE, true>(dq, c0, c0 + pw, 0, sh);
             __syncthreads();
         }
         return;
@@ -584,7 +585,7 @@ HQR_DEV void wg_instance(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
         if (factor) wg_panel_factor<NT, QM>(d, (int)c0, pw, sh);
         else wg_panel_load<NT, QM>(d, c0, pw, sh);
         const int64_t ncA = factor ? d.n - c0 - pw : 0;
-        wg_trailing<NT, QM>(d, c0, c0 + pw, ncA, sh);
+        wg_trailing<NT, QM, PIPE>(d, c0, c0 + pw, ncA, sh);
         __syncthreads();
     }
     if (d.resnorm && d.nrhs > 0) wg_resnorm<NT, QM>(d);
@@ -594,7 +595,7 @@ HQR_DEV void wg_instance(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
 
 // Persistent: workgroups take instances from an atomic queue head until it
 // passes `count`.
-template <int NT, int QM>
+template <int NT, int QM, int PIPE>
 __global__ void __launch_bounds__(NT) wg_batched_kernel(const WgDesc *desc, int count, int *head, int *info)
 {
     __shared__ WgShared<NT, QM> sh;
@@ -604,16 +605,16 @@ __global__ void __launch_bounds__(NT) wg_batched_kernel(const WgDesc *desc, int 
         const int id = sh.isc[1];
         __syncthreads();
         if (id >= count) break;
-        wg_instance<NT, QM>(desc[id], info, sh);
+        wg_instance<NT, QM, PIPE>(desc[id], info, sh);
     }
 }
 
 // One problem, descriptor by value (info slot d.index of `info`).
-template <int NT, int QM>
+template <int NT, int QM, int PIPE>
 __global__ void __launch_bounds__(NT) wg_single_kernel(WgDesc d, int *info)
 {
     __shared__ WgShared<NT, QM> sh;
-    wg_instance<NT, QM>(d, info, sh);
+    wg_instance<NT, QM, PIPE>(d, info, sh);
 }
 
 } // namespace hqr

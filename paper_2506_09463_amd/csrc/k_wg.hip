@@ -16,25 +16,33 @@ struct WgKernels {
     wg_single_fn single;
 };
 
-template <int NT, int QM>
+template <int NT, int QM, int PIPE>
 WgVariant describe(const char *name, int index)
 {
-    // workgroups per CU the LDS allows (at most 2 are launched per CU)
     const int per_cu = (int)std::max<size_t>(1, (160 * 1024) / sizeof(WgShared<NT, QM>));
-    return WgVariant{name, NT, QM, std::min(per_cu, 2), wg_max_rows<NT, QM>(), wg_max_x<NT, QM>(), index};
+    return WgVariant{name, NT, QM, PIPE, std::min(per_cu, 8), wg_max_rows<NT, QM>(), wg_max_x<NT, QM>(), index};
 }
 
+// (index, threads, rows per thread, 16-row blocks loaded together).  The
+// 256-thread variants differ only in rows per thread and load scheduling,
+// never in arithmetic, so the batched launch may use any of them.
 #define HQR_WG_VARIANTS(X)                                                                                        \
-    X(0, 64, 2)   /* m <= 128, one wave */                                                                        \
-    X(1, 64, 4)   /* m <= 256, one wave */                                                                        \
-    X(2, 128, 1)  /* m <= 128 */                                                                                  \
-    X(3, 256, 1)  /* m <= 256 */                                                                                  \
-    X(4, 128, 4)  /* m <= 512 */                                                                                  \
-    X(5, 256, 2)  /* m <= 512 */                                                                                  \
-    X(6, 256, 4)  /* m <= 1024 */
+    X(0, 64, 2, 4)    /* m <= 128, one wave */                                                                    \
+    X(1, 64, 4, 4)    /* m <= 256, one wave */                                                                    \
+    X(2, 128, 1, 4)   /* m <= 128 */                                                                              \
+    X(3, 256, 1, 4)   /* m <= 256 */                                                                              \
+    X(4, 128, 4, 4)   /* m <= 512 */                                                                              \
+    X(5, 256, 2, 4)   /* m <= 512 */                                                                              \
+    X(6, 256, 4, 4)   /* m <= 1024 */                                                                             \
+    X(7, 256, 1, 2)                                                                                               \
+    X(8, 256, 1, 8)                                                                                               \
+    X(9, 256, 2, 2)                                                                                               \
+    X(10, 256, 2, 8)                                                                                              \
+    X(11, 256, 4, 2)                                                                                              \
+    X(12, 256, 4, 8)
 
 const WgKernels kernels[] = {
-#define HQR_K(I, NT, QM) {wg_batched_kernel<NT, QM>, wg_single_kernel<NT, QM>},
+#define HQR_K(I, NT, QM, P) {wg_batched_kernel<NT, QM, P>, wg_single_kernel<NT, QM, P>},
     HQR_WG_VARIANTS(HQR_K)
 #undef HQR_K
 };
@@ -44,7 +52,7 @@ const WgKernels kernels[] = {
 const WgVariant *wg_variants(int *count)
 {
     static const WgVariant v[] = {
-#define HQR_D(I, NT, QM) describe<NT, QM>("wg" #NT "x" #QM, I),
+#define HQR_D(I, NT, QM, P) describe<NT, QM, P>((P) == 4 ? "wg" #NT "x" #QM : "wg" #NT "x" #QM "p" #P, I),
         HQR_WG_VARIANTS(HQR_D)
 #undef HQR_D
     };

@@ -25,6 +25,7 @@ HQR_PREC_FP64 = 0
 HQR_PREC_MIXED = 1
 HQR_TUNE_SINGLE = 0
 HQR_TUNE_BATCHED = 1
+HQR_TUNE_OCCUPANCY = 2
 TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 
 HQR_OPT_NO_FALLBACK = 1
@@ -116,6 +117,14 @@ def load(path: str = LIB_PATH):
 
 
 # ------------------------------------------------------------------- tuning
+def variant_shape(name):
+    """(threads, rows per thread, 16-row blocks loaded together) of a
+    one-workgroup variant name "wgNTxQM" or "wgNTxQMpP"."""
+    nt, rest = name[2:].split("x")
+    qm, _, pipe = rest.partition("p")
+    return int(nt), int(qm), int(pipe) if pipe else 4
+
+
 def tune_variants():
     """Names of the one-workgroup kernel variants, by index."""
     lib = load()
@@ -143,8 +152,10 @@ def load_tune_db(path=TUNE_DB_PATH):
     tune_clear()
     for r in db.get("rules", []):
         choice = r["choice"]
-        idx = -1 if choice == "blocked" else names.index(choice)
-        op = HQR_TUNE_SINGLE if r["op"] == "single" else HQR_TUNE_BATCHED
+        idx = -1 if choice == "blocked" else (names.index(choice) if isinstance(choice, str) else int(choice))
+        op = {"single": HQR_TUNE_SINGLE, "batched": HQR_TUNE_BATCHED, "occupancy": HQR_TUNE_OCCUPANCY}[r["op"]]
+        if op == HQR_TUNE_OCCUPANCY:
+            idx = int(choice)
         tune_set(op, r["m"][0], r["m"][1], r["n"][0], r["n"][1], idx,
                  HQR_PREC_MIXED if r.get("precision") == "mixed" else HQR_PREC_FP64)
 

@@ -70,8 +70,8 @@ def test_tuning_rules_without_gpu(lib):
     names = hqr.tune_variants()
     assert len(names) >= 2 and all(n.startswith("wg") for n in names)
     for nm in names:
-        nt, qm = (int(x) for x in nm[2:].split("x"))
-        assert nt % 64 == 0 and (nt * qm) % 16 == 0
+        nt, qm, pipe = hqr.variant_shape(nm)
+        assert nt % 64 == 0 and (nt * qm) % 16 == 0 and pipe in (2, 4, 8)
     assert lib.hqr_tune_variant_name(len(names)) is None
     assert lib.hqr_tune_set(7, 0, 1, 0, 1, 0, 0) == -1          # op
     assert lib.hqr_tune_set(0, 5, 4, 0, 1, 0, 0) == -3          # m range
@@ -81,6 +81,9 @@ def test_tuning_rules_without_gpu(lib):
     for i, nm in enumerate(names):                              # batched: 256-thread variants only
         assert (lib.hqr_tune_set(1, 0, 1, 0, 1, 0, i) == 0) == nm.startswith("wg256x")
     assert lib.hqr_tune_set(0, 0, 1, 0, 1, 0, -1) == 0
+    assert lib.hqr_tune_set(2, 0, 1, 0, 1, 0, 0) == -7          # occupancy 1..8
+    assert lib.hqr_tune_set(2, 0, 1, 0, 1, 0, 9) == -7
+    assert lib.hqr_tune_set(2, 0, 1, 0, 1, 0, 3) == 0
     assert lib.hqr_tune_clear() == 0
 
 

@@ -30,7 +30,7 @@ def hqr():
 def _variants(hqr):
     out = []
     for i, nm in enumerate(hqr.tune_variants()):
-        nt, qm = (int(x) for x in nm[2:].split("x"))
+        nt, qm, _ = hqr.variant_shape(nm)
         out.append((i, nm, nt * qm))
     return out
 
@@ -58,7 +58,7 @@ def _shapes(maxrows):
             (97, 33, 5)]
 
 
-@pytest.mark.parametrize("vi", [0, 1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("vi", list(range(13)))
 def test_single_each_variant(hqr, oracle_mod, vi):
     import torch
     vs = _variants(hqr)
@@ -157,3 +157,39 @@ def test_batched_each_variant(hqr, oracle_mod, qm):
     for i, (A, B) in enumerate(probs):
         _check_solve(oracle_mod, A, B, to_host(As[i]), to_host(ups[i]), to_host(Bs[i]),
                      to_host(res[i])[:B.shape[1]], int(info[i]))
+
+
+def test_batched_schedules_are_bitwise_equal(hqr):
+    """The 256-thread variants (rows per thread, load depth) and the
+    workgroups per CU change only how the batch is scheduled, never an
+    instance's arithmetic: every candidate the autotuner may pick gives
+    bitwise the same results."""
+    import torch
+    rng = np.random.default_rng(777)
+    probs = []
+    for i in range(40):
+        n = int(rng.integers(1, 200))
+        m = min(256, n + int(rng.integers(0, n + 1)))
+        probs.append((rng.standard_normal((m, n)), rng.standard_normal((m, 3))))
+    ref = None
+    names = hqr.tune_variants()
+    cands = [(i, nm) for i, nm in enumerate(names) if nm.startswith("wg256x")]
+    print("[case] batched schedules", [nm for _, nm in cands], flush=True)
+    for idx, nm in cands:
+        for occ in (1, 2, 4):
+            hqr.tune_clear()
+            hqr.tune_set(hqr.HQR_TUNE_BATCHED, 0, 1 << 40, 0, 1 << 40, idx)
+            hqr.tune_set(hqr.HQR_TUNE_OCCUPANCY, 0, 1 << 40, 0, 1 << 40, occ)
+            As = [to_dev(A) for A, _ in probs]
+            Bs = [to_dev(B) for _, B in probs]
+            ups, res, info = hqr.qr_lsq_solve_batched(As, Bs)
+            torch.cuda.synchronize()
+            out = [(to_host(a), to_host(u), to_host(b)) for a, u, b in zip(As, ups, Bs)]
+            if ref is None:
+                ref = out
+                continue
+            for i, (x, y) in enumerate(zip(out, ref)):
+                for p, q in zip(x, y):
+                    assert np.array_equal(p, q), (nm, occ, i)
+    hqr.tune_clear()
+    hqr.load_tune_db()
