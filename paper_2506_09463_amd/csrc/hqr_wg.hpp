@@ -48,39 +48,101 @@ constexpr int64_t wg_max_rows() { return (int64_t)NT * QM; }
 template <int NT, int QM>
 constexpr int64_t wg_max_x() { return (int64_t)NT * QM * WG_LD; }
 
+// Cross-lane moves of a double without LDS: gfx950's permlane swaps between
+// the wave's halves (32) and between row pairs (16), and DPP within rows.
+HQR_DEV unsigned lo32(double v) { return (unsigned)__double2loint(v); }
+HQR_DEV unsigned hi32(double v) { return (unsigned)__double2hiint(v); }
+HQR_DEV double mk64(unsigned hi, unsigned lo) { return __hiloint2double((int)hi, (int)lo); }
+
+// S = 32 or 16: lanes with bit log2(S) clear receive a from lane + S, lanes
+// with it set receive b from lane - S (one swap instruction per 32-bit half).
+template <int S>
+HQR_DEV double swap_partner(double a, double b, bool upper)
+{
+    if (S == 32) {
+        const auto rl = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+        const auto rh = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+        return upper ? mk64(rh[0], rl[0]) : mk64(rh[1], rl[1]);
+    } else {
+        const auto rl = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+        const auto rh = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+        return upper ? mk64(rh[0], rl[0]) : mk64(rh[1], rl[1]);
+    }
+}
+
+// DPP move of a double within 16-lane rows (CTRL: a DPP16 control code).
+template <int CTRL>
+HQR_DEV double dpp64(double v)
+{
+    const unsigned l = __builtin_amdgcn_update_dpp(0u, lo32(v), CTRL, 0xf, 0xf, false);
+    const unsigned h = __builtin_amdgcn_update_dpp(0u, hi32(v), CTRL, 0xf, 0xf, false);
+    return mk64(h, l);
+}
+
+constexpr int DPP_ROW_ROR8 = 0x128;      // lane i <- i ^ 8 within the row
+constexpr int DPP_ROW_HALF_MIRROR = 0x141; // lane i <- 7 - i within 8 lanes
+constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+
 // Sum of v[0..15] over the wave by recursive halving: lane L ends with the
-// total of index 8*b5 + 4*b4 + 2*b3 + b2 (b_i = bit i of L).
+// total of index 8*b5 + 4*b4 + 2*b3 + b2 (b_i = bit i of L).  At each step a
+// lane keeps the half of its values selected by one bit of its id and adds
+// the other half of a partner lane across that bit; any pairing that crosses
+// the bit inside the lanes that share the higher bits adds up the same sums
+// (the bit-2 step pairs i with 7 - i, the others with i ^ 2^b).  No LDS.
 HQR_DEV double wave_sum16(const double (&v)[WG_P], int lane)
 {
     double a8[8], a4[4], a2[2];
     const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0, h2 = (lane & 4) != 0;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const double keep = h5 ? v[8 + t] : v[t];
-        const double give = h5 ? v[t] : v[8 + t];
-        a8[t] = keep + __shfl_xor(give, 32);
-    }
+    for (int t = 0; t < 8; ++t) a8[t] = (h5 ? v[8 + t] : v[t]) + swap_partner<32>(v[t], v[8 + t], h5);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const double keep = h4 ? a8[4 + t] : a8[t];
-        const double give = h4 ? a8[t] : a8[4 + t];
-        a4[t] = keep + __shfl_xor(give, 16);
-    }
+    for (int t = 0; t < 4; ++t) a4[t] = (h4 ? a8[4 + t] : a8[t]) + swap_partner<16>(a8[t], a8[4 + t], h4);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const double keep = h3 ? a4[2 + t] : a4[t];
         const double give = h3 ? a4[t] : a4[2 + t];
-        a2[t] = keep + __shfl_xor(give, 8);
+        a2[t] = keep + dpp64<DPP_ROW_ROR8>(give);
     }
-    double a1 = (h2 ? a2[1] : a2[0]) + __shfl_xor(h2 ? a2[0] : a2[1], 4);
-    a1 += __shfl_xor(a1, 2);
-    a1 += __shfl_xor(a1, 1);
+    double a1 = (h2 ? a2[1] : a2[0]) + dpp64<DPP_ROW_HALF_MIRROR>(h2 ? a2[0] : a2[1]);
+    a1 += dpp64<DPP_QUAD_XOR2>(a1);
+    a1 += dpp64<DPP_QUAD_XOR1>(a1);
     return a1;
 }
 
 HQR_DEV int wave_sum16_index(int lane)
 {
     return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+}
+
+// The value lane 16r + i holds, in every lane of row r (DPP row_newbcast;
+// i must be a constant once the caller's loop is unrolled).
+template <int I> HQR_DEV double row_bcast16_c(double v)
+{
+    const long r = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, v), 0x150 + I, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, r);
+}
+
+HQR_DEV double row_bcast16(double v, int i)
+{
+    switch (i) {
+    case 0: return row_bcast16_c<0>(v);
+    case 1: return row_bcast16_c<1>(v);
+    case 2: return row_bcast16_c<2>(v);
+    case 3: return row_bcast16_c<3>(v);
+    case 4: return row_bcast16_c<4>(v);
+    case 5: return row_bcast16_c<5>(v);
+    case 6: return row_bcast16_c<6>(v);
+    case 7: return row_bcast16_c<7>(v);
+    case 8: return row_bcast16_c<8>(v);
+    case 9: return row_bcast16_c<9>(v);
+    case 10: return row_bcast16_c<10>(v);
+    case 11: return row_bcast16_c<11>(v);
+    case 12: return row_bcast16_c<12>(v);
+    case 13: return row_bcast16_c<13>(v);
+    case 14: return row_bcast16_c<14>(v);
+    default: return row_bcast16_c<15>(v);
+    }
 }
 
 // Block-wide sum (op 0) or max (op 1) of one value per thread; uniform result.
@@ -527,7 +589,7 @@ __device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<N
                 for (int l = WG_P - 1; l >= 0; --l) {
                     if (l < bw) {
                         const double cand = xi / rrow[l];
-                        const double xl = __shfl(cand, l + 16 * cg);
+                        const double xl = row_bcast16(cand, l);     // lane l of this 16-lane row
                         if (i == l) xi = xl;
                         else if (i < l) xi = fma(-rrow[l], xl, xi);
                     }
