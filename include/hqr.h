@@ -85,6 +85,20 @@ extern "C" {
                                  HQR_INFO_NOCONV is ORed into info on the
                                  device and x is the last iterate (no FP64
                                  fallback: the caller decides)           */
+#define HQR_OPT_TSQR_PANEL  2 /* blocked path (FP64 and mixed qr_lsq_solve):
+                                 every 64-column panel by TSQR (a reduction
+                                 tree of row-block Householder QRs) with
+                                 Householder reconstruction, stable at any
+                                 panel conditioning; the default CholeskyQR2
+                                 panel hands a panel whose Gram pivots fall
+                                 below 1e-15 of its column norms to the exact
+                                 one-workgroup loop instead (Section 6 names
+                                 tiled and communication-avoiding QR as the
+                                 way forward).  A caller's work area must
+                                 then have hqr_workspace_size_opts() bytes
+                                 (HQR_PANEL=tsqr in the environment selects
+                                 the TSQR panel for every call, and
+                                 hqr_workspace_size then includes it)    */
 
 typedef struct hqr_opts {
     int precision;   /* HQR_PREC_FP64 or HQR_PREC_MIXED                      */
@@ -98,6 +112,11 @@ typedef struct hqr_opts {
  * nrhs right-hand sides at the given precision.  Returns a negative status on
  * invalid arguments. */
 int64_t hqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, int precision);
+
+/* The same for qr_lsq_solve with options: opt->precision and the buffers of
+ * the TSQR tree when opt->flags has HQR_OPT_TSQR_PANEL (opt NULL: FP64, no
+ * flags).  Returns a negative status on invalid arguments. */
+int64_t hqr_workspace_size_opts(int64_t m, int64_t n, int64_t nrhs, const hqr_opts *opt);
 
 /* In-place factorization (Alg. 2 with the storage of Alg. 3).
  *   m >= n >= 0; A: m x n (lda >= max(1,m)), overwritten by R and the

@@ -327,6 +327,46 @@ struct BatchArgs {
     int max_ntot;    // largest n + nrhs in the batch (<= BATCH_MAX_COLS)
 };
 
+// ---------------------------------------------------------------- TSQR
+// One level of the TSQR tree of a panel (bw columns): `rows` rows of X
+// (column-major, leading dimension ldx) in nblk row blocks, block i of
+// base + (i < rem) rows starting at row i * base + min(i, rem).  Level 0 is
+// the panel itself; level l + 1 stacks the bw x bw R factors of level l's
+// blocks (block i at rows i * bw).  Q (ldq) receives the level's explicit
+// orthonormal factor, up the blocks' reflector pivots (64 per block), fdesc
+// and adesc the one-workgroup descriptors that factor the blocks and apply
+// their reflectors.
+constexpr int TSQR_MAX_LEVELS = 8;
+constexpr int64_t TSQR_LEAF_ROWS = 1024;   // rows per block at most (one-workgroup limit)
+
+struct TsqrLevel {
+    int64_t rows, nblk, base, rem;
+    double *X;
+    int64_t ldx;
+    double *Q;
+    int64_t ldq;
+    double *up;
+    WgDesc *fdesc;
+    WgDesc *adesc;
+};
+
+struct TsqrArgs {
+    int *flag;          // the panel's flag: 1 (exact zero tail) skips the panel
+    int bw, nlev;
+    TsqrLevel lev[TSQR_MAX_LEVELS];
+    int *heads;         // 2 * nlev queue heads, zeroed by the descriptor kernel
+};
+
+// first row and row count of block i of a level
+__host__ __device__ inline int64_t tsqr_block_start(const TsqrLevel &L, int64_t i)
+{
+    return i * L.base + (i < L.rem ? i : L.rem);
+}
+__host__ __device__ inline int64_t tsqr_block_rows(const TsqrLevel &L, int64_t i)
+{
+    return L.base + (i < L.rem ? 1 : 0);
+}
+
 constexpr int BATCH_MAX_ROWS = 4096;
 
 constexpr int BATCH_MAX_COLS = 2048;
@@ -337,7 +377,7 @@ constexpr int BATCH_NW = 16;
 // Kernel classes of the optional per-launch event timing (hqr_profile_*).
 enum KClass {
     K_SMALL, K_PANEL, K_VTX, K_TFACTOR, K_WSOLVE, K_UPDATE, K_DIAG, K_TRSV, K_RESNORM, K_FILL,
-    K_GRAM1, K_GRAM2, K_GRED, K_CQR_CHOL, K_CQR_FINISH, K_NVTX, K_BATCHED, K_REFINE, K_NCLASS
+    K_GRAM1, K_GRAM2, K_GRED, K_CQR_CHOL, K_CQR_FINISH, K_NVTX, K_BATCHED, K_REFINE, K_TSQR, K_NCLASS
 };
 // Defined in hqr_lib.hip: while timing is on, every launch is bracketed by a
 // pair of HIP events recorded on the launch's own stream.
@@ -394,6 +434,16 @@ const WgVariant *wg_variants(int *count);
 hipError_t k_wg_single(const WgVariant *v, hipStream_t s, const WgDesc &d, int *info);
 hipError_t k_wg_batched(const WgVariant *v, int grid, hipStream_t s, const WgDesc *desc, int count, int *head,
                         int *info);
+
+// hqr_tsqr.hpp (k_tsqr.hip)
+hipError_t k_tsqr_desc(hipStream_t s, const TsqrArgs &a);
+hipError_t k_tsqr_gather(hipStream_t s, const TsqrArgs &a, int l);
+hipError_t k_tsqr_scatter(hipStream_t s, const TsqrArgs &a, int l);
+// D R and the identity into r1 / r1inv, the signs D into sign; then the
+// panel := Q D (two launches)
+hipError_t k_tsqr_final(hipStream_t s, const TsqrArgs &a, double *Ap, int64_t lda, double *r1, double *r1inv,
+                        double *sign);
+
 
 // hqr_lse.hpp (k_lse.hip)
 hipError_t k_transpose(hipStream_t s, const double *in, int64_t ldi, double *out, int64_t ldo, int64_t rows,

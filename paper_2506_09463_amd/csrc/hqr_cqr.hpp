@@ -1086,7 +1086,9 @@ __global__ void __launch_bounds__(256) cqr_chol_kernel(CholArgs p)
     else
         chol64_dpp(M0, M1, bw, lane, w, CQR_RATIO, gdiag, rdiag, &bad);
     HQR_TS();
-    if (tid == 0 && (bad || structural)) *((volatile int *)p.flag) = 1;
+    // 1: an exactly zero column tail (only the exact loop keeps H_k = I);
+    // 2: a pivot below the ratio (a TSQR panel can still take over)
+    if (tid == 0 && (bad || structural)) *((volatile int *)p.flag) = structural ? 1 : 2;
     __syncthreads();
     if (bad && p.pass == 2) {
         exact_panel<4>(ex, tid, red, wsh, sc, M0, M1, gdiag, rdiag);

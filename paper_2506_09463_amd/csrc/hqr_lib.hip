@@ -23,7 +23,7 @@ namespace hqr {
 static const char *kclass_name[K_NCLASS] = {"small_lsq", "panel_col", "vtx", "tfactor", "wsolve",
                                             "update", "diag_check", "trsv", "resnorm", "fill",
                                             "cqr_gram1", "cqr_gram2", "gram_reduce", "cqr_chol",
-                                            "cqr_finish", "narrow_vtx", "batched_lsq", "refine"};
+                                            "cqr_finish", "narrow_vtx", "batched_lsq", "refine", "tsqr"};
 struct ProfRec {
     int cls;
     hipEvent_t e0, e1;
@@ -152,6 +152,22 @@ static int launch_wg_single(const WgVariant *v, const WgDesc &d, int *info, hipS
     return k_wg_single(v, s, d, info) == hipSuccess ? 0 : HQR_EDEVICE;
 }
 
+// Panel factorization: CholeskyQR2 + reconstruction (default), one launch
+// per pivot, the exact one-workgroup loop for every panel, or a TSQR panel
+// + reconstruction for every panel (HQR_PANEL=percol|exact|tsqr; the TSQR
+// panel also by HQR_OPT_TSQR_PANEL).
+enum PanelMode { PANEL_CQR = 0, PANEL_PERCOL = 1, PANEL_EXACT = 2, PANEL_TSQR = 3 };
+
+static int panel_mode()
+{
+    const char *e = getenv("HQR_PANEL");
+    if (!e) return PANEL_CQR;
+    if (!strcmp(e, "percol")) return PANEL_PERCOL;
+    if (!strcmp(e, "exact")) return PANEL_EXACT;
+    if (!strcmp(e, "tsqr")) return PANEL_TSQR;
+    return PANEL_CQR;
+}
+
 // ------------------------------------------------------------ large path
 struct Plan {
     int64_t m, n, nrhs;
@@ -164,6 +180,7 @@ struct Plan {
     int nb;          // panel width (<= NB)
     bool f32;        // trailing-update contractions in FP32
     bool no_side;    // no look-ahead side stream (one stream only)
+    bool tsqr;       // TSQR panels (workspace for the tree included)
 };
 
 static int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -183,7 +200,31 @@ static Plan make_plan(int64_t m, int64_t n, int64_t nrhs, int nb = NB, bool f32 
     p.ngroups = (int)((m + CQR_ROWS - 1) / CQR_ROWS);
     p.npanels = (int)((n + nb - 1) / nb);
     p.no_side = false;
+    p.tsqr = panel_mode() == PANEL_TSQR;
     return p;
+}
+
+// Levels of a panel's TSQR tree: level 0 is the panel (mp rows), level l + 1
+// stacks the bw x bw R factors of level l's blocks of at most
+// TSQR_LEAF_ROWS rows; the last level is one block.
+struct TsqrGeom {
+    int nlev;
+    int64_t rows[TSQR_MAX_LEVELS], nblk[TSQR_MAX_LEVELS];
+};
+
+static bool tsqr_geometry(int64_t mp, int bw, TsqrGeom &g)
+{
+    g.nlev = 0;
+    int64_t rows = mp;
+    for (;;) {
+        if (g.nlev == TSQR_MAX_LEVELS) return false;
+        const int64_t nblk = std::max<int64_t>(1, (rows + TSQR_LEAF_ROWS - 1) / TSQR_LEAF_ROWS);
+        g.rows[g.nlev] = rows;
+        g.nblk[g.nlev] = nblk;
+        ++g.nlev;
+        if (nblk == 1) return true;
+        rows = nblk * bw;
+    }
 }
 
 struct Work {
@@ -197,6 +238,13 @@ struct Work {
     int *mstat;                              // refinement: [nrhs][4] column states, active count, verdict
     unsigned long long *mask, *mask_all;
     int *pflag;
+    // TSQR panels: level 0's Q (m x NB), the stacked R and Q of levels >= 1,
+    // the blocks' pivots, descriptors, queue heads and an unused info slot
+    double *tq0 = nullptr;
+    double *tstack[TSQR_MAX_LEVELS] = {}, *tqs[TSQR_MAX_LEVELS] = {}, *tup[TSQR_MAX_LEVELS] = {};
+    WgDesc *tdesc[TSQR_MAX_LEVELS] = {};
+    int *theads = nullptr, *tinfo = nullptr;
+    double *tsign = nullptr;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -235,6 +283,35 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *gg = take(sizeof(double) * NB * NB);
     char *xn = take(sizeof(double) * NB * NB);
     char *ma = take(sizeof(unsigned long long));
+    if (p.tsqr) {
+        TsqrGeom g;
+        tsqr_geometry(p.m, NB, g);
+        char *q0 = take(sizeof(double) * (size_t)p.m * NB);
+        char *st[TSQR_MAX_LEVELS] = {}, *qs[TSQR_MAX_LEVELS] = {}, *tu[TSQR_MAX_LEVELS] = {}, *td[TSQR_MAX_LEVELS] = {};
+        for (int l = 0; l < g.nlev; ++l) {
+            if (l > 0) {
+                st[l] = take(sizeof(double) * (size_t)g.rows[l] * NB);
+                qs[l] = take(sizeof(double) * (size_t)g.rows[l] * NB);
+            }
+            tu[l] = take(sizeof(double) * (size_t)g.nblk[l] * NB);
+            td[l] = take(sizeof(WgDesc) * 2 * (size_t)g.nblk[l]);
+        }
+        char *th = take(sizeof(int) * 2 * TSQR_MAX_LEVELS);
+        char *ti = take(sizeof(int) * 64);
+        char *tsg = take(sizeof(double) * NB);
+        if (w) {
+            w->tq0 = (double *)q0;
+            for (int l = 0; l < TSQR_MAX_LEVELS; ++l) {
+                w->tstack[l] = (double *)st[l];
+                w->tqs[l] = (double *)qs[l];
+                w->tup[l] = (double *)tu[l];
+                w->tdesc[l] = (WgDesc *)td[l];
+            }
+            w->theads = (int *)th;
+            w->tinfo = (int *)ti;
+            w->tsign = (double *)tsg;
+        }
+    }
     if (w) {
         w->q1top = (double *)q1;
         w->G = (double *)gg;
@@ -467,6 +544,65 @@ static int launch_chol(const Plan &pl, const Work &w, double *A, int64_t lda, do
 // Panel (c0, bw) by CholeskyQR2 + reconstruction, bottom rows not yet
 // finished.  With upd, the previous panel (start cp, width NB; W = T^T V^T C
 // transposed in w.xn) is first applied to this panel's columns.
+// TSQR panel (c0, bw) after CholeskyQR pass 1 (which has applied the
+// previous panel's update and flagged exact zero tails): the tree's block
+// factorizations bottom-up, the explicit Q top-down, then the panel := Q D
+// and the first factor := D R for the second pass.  Every launch is empty or
+// returns at once for a panel flagged 1 (read on the device).
+static int num_cus();
+
+static int tsqr_panel(const Plan &pl, const Work &w, double *A, int64_t lda, int c0, int bw, int pidx,
+                      hipStream_t s)
+{
+    TsqrGeom g;
+    if (!tsqr_geometry(pl.m - c0, bw, g)) return HQR_ENOTSUP;
+    TsqrArgs a;
+    a.flag = w.pflag + pidx;
+    a.bw = bw;
+    a.nlev = g.nlev;
+    a.heads = w.theads;
+    double *Ap = A + (size_t)c0 * lda + c0;
+    for (int l = 0; l < g.nlev; ++l) {
+        TsqrLevel &L = a.lev[l];
+        L.rows = g.rows[l];
+        L.nblk = g.nblk[l];
+        L.base = L.rows / L.nblk;
+        L.rem = L.rows % L.nblk;
+        L.X = (l == 0) ? Ap : w.tstack[l];
+        L.ldx = (l == 0) ? lda : L.rows;
+        L.Q = (l == 0) ? w.tq0 : w.tqs[l];
+        L.ldq = (l == 0) ? pl.m : L.rows;
+        L.up = w.tup[l];
+        L.fdesc = w.tdesc[l];
+        L.adesc = w.tdesc[l] + L.nblk;
+    }
+    HQR_CK(k_tsqr_desc(s, a));
+    auto batched = [&](int l, const WgDesc *desc, int *head) -> int {
+        const TsqrLevel &L = a.lev[l];
+        const WgVariant *v = pick_wg_batched(L.base + (L.rem > 0 ? 1 : 0), bw);
+        if (!v) return HQR_ENOTSUP;
+        const int grid = (int)std::min<int64_t>(L.nblk, (int64_t)v->per_cu * num_cus());
+        HQR_CK(k_wg_batched(v, grid, s, desc, (int)L.nblk, head, w.tinfo));
+        return 0;
+    };
+    const int top = g.nlev - 1;
+    for (int l = 0; l <= top; ++l) {
+        int rc = batched(l, a.lev[l].fdesc, a.heads + 2 * l);
+        if (rc) return rc;
+        if (l < top) HQR_CK(k_tsqr_gather(s, a, l));
+    }
+    HQR_CK(k_eye(s, a.lev[top].Q, a.lev[top].ldq, a.lev[top].rows, bw));
+    int rc = batched(top, a.lev[top].adesc, a.heads + 2 * top + 1);
+    if (rc) return rc;
+    for (int l = top - 1; l >= 0; --l) {
+        HQR_CK(k_tsqr_scatter(s, a, l));
+        rc = batched(l, a.lev[l].adesc, a.heads + 2 * l + 1);
+        if (rc) return rc;
+    }
+    HQR_CK(k_tsqr_final(s, a, Ap, lda, w.r1, w.r1inv, w.tsign));
+    return 0;
+}
+
 static int panel_passes(const Plan &pl, const Work &w, double *A, int64_t lda, double *up, int c0, int bw, int pidx,
                         double *Tout, bool upd, int cp, hipStream_t s)
 {
@@ -489,6 +625,7 @@ static int panel_passes(const Plan &pl, const Work &w, double *A, int64_t lda, d
     HQR_CK(k_cqr_gram1(dim3((unsigned)((pl.m - rbase + 63) / 64)), s, g));
     int rc = launch_gred(pl, w, parts, w.G, true, flag, s);
     if (!rc) rc = launch_chol(pl, w, A, lda, up, c0, bw, pidx, 1, Tout, s);
+    if (!rc && pl.tsqr) rc = tsqr_panel(pl, w, A, lda, c0, bw, pidx, s);
     if (rc) return rc;
     Gram2Args g2;
     g2.A = A;
@@ -553,17 +690,6 @@ static int panel_cqr(const Plan &pl, const Work &w, double *A, int64_t lda, doub
     int rc = panel_passes(pl, w, A, lda, up, c0, bw, pidx, Tout, false, 0, s);
     if (!rc) rc = launch_finish(pl, w, A, lda, c0, bw, pidx, s);
     return rc;
-}
-
-enum PanelMode { PANEL_CQR = 0, PANEL_PERCOL = 1, PANEL_EXACT = 2 };
-
-static int panel_mode()
-{
-    const char *e = getenv("HQR_PANEL");
-    if (!e) return PANEL_CQR;
-    if (!strcmp(e, "percol")) return PANEL_PERCOL;
-    if (!strcmp(e, "exact")) return PANEL_EXACT;
-    return PANEL_CQR;
 }
 
 // Per caller stream (and device): the look-ahead's side stream with its
@@ -837,7 +963,8 @@ static int apply_stored(const Plan &pl, const Work &w, const double *A, int64_t 
 // The FP64 path: small problems in one register-resident workgroup, larger
 // ones by the blocked factorization, then residual norms and back-substitution.
 static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, double *up, double *B, int64_t ldb,
-                    double *resnorm, void *work, int64_t lwork, int *info, hipStream_t s, bool side = true)
+                    double *resnorm, void *work, int64_t lwork, int *info, hipStream_t s, bool side = true,
+                    bool tsqr = false)
 {
     if (n == 0) {
         HQR_CK(k_fill_int(s, info, 0, (int64_t)1));
@@ -857,6 +984,7 @@ static int lsq_fp64(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, 
     }
     Plan pl = make_plan(m, n, nrhs);
     pl.no_side = !side;
+    pl.tsqr = pl.tsqr || tsqr;
     WorkGuard g;
     Work w;
     int rc = get_work(pl, work, lwork, s, g, &w);
@@ -928,6 +1056,7 @@ static int read_verdict(const Work &w, int64_t nrhs, hipStream_t s, bool *conver
 }
 
 static bool no_fallback(const hqr_opts *opt) { return opt && (opt->flags & HQR_OPT_NO_FALLBACK); }
+static bool tsqr_opt(const hqr_opts *opt) { return opt && (opt->flags & HQR_OPT_TSQR_PANEL); }
 
 // Mixed precision: FP32 trailing contractions in the factorization, FP64
 // back-substitution, then the refinement above.  Without HQR_OPT_NO_FALLBACK
@@ -945,6 +1074,7 @@ static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
     const bool async = no_fallback(opt);
     const int nb = (n <= 256) ? 16 : NB;
     Plan pl = make_plan(m, n, nrhs, nb, true);
+    pl.tsqr = pl.tsqr || tsqr_opt(opt);
     WorkGuard g;
     Work w;
     int rc = get_work(pl, work, lwork, s, g, &w);
@@ -967,7 +1097,7 @@ static int lsq_mixed(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda,
                             hipMemcpyDeviceToDevice, s));
     HQR_CK(hipMemcpy2DAsync(B, sizeof(double) * ldb, w.borig, sizeof(double) * m, sizeof(double) * m, nrhs,
                             hipMemcpyDeviceToDevice, s));
-    rc = lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, nullptr, 0, info, s);
+    rc = lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, nullptr, 0, info, s, true, tsqr_opt(opt));
     if (rc) return rc;
     HQR_CK(k_or_int(s, info, HQR_INFO_NOCONV));
     return 0;
@@ -1154,6 +1284,16 @@ int64_t hqr_workspace_size(int64_t m, int64_t n, int64_t nrhs, int precision)
     return (int64_t)work_bytes(pl, nullptr, nullptr);
 }
 
+int64_t hqr_workspace_size_opts(int64_t m, int64_t n, int64_t nrhs, const hqr_opts *opt)
+{
+    const int precision = opt ? opt->precision : HQR_PREC_FP64;
+    const int64_t base = hqr_workspace_size(m, n, nrhs, precision);
+    if (base < 0 || !tsqr_opt(opt)) return base;
+    Plan pl = (precision == HQR_PREC_MIXED) ? make_plan(m, n, nrhs, (n <= 256) ? 16 : NB, true) : make_plan(m, n, nrhs);
+    pl.tsqr = true;
+    return (int64_t)work_bytes(pl, nullptr, nullptr);
+}
+
 int qr_factor(int64_t m, int64_t n, double *A, int64_t lda, double *up, void *work, int64_t lwork, int *info,
               hipStream_t stream)
 {
@@ -1319,7 +1459,7 @@ int qr_lsq_solve(int64_t m, int64_t n, int64_t nrhs, double *A, int64_t lda, dou
         HQR_CK(k_fill_int(stream, iters, 0, (int64_t)1));
         HQR_CK(hipGetLastError());
     }
-    return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, work, lwork, info, stream);
+    return lsq_fp64(m, n, nrhs, A, lda, up, B, ldb, resnorm, work, lwork, info, stream, true, tsqr_opt(opt));
 }
 
 // ------------------------------------------- entry point without allocation

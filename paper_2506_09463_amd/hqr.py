@@ -29,7 +29,8 @@ HQR_TUNE_OCCUPANCY = 2
 TUNE_DB_PATH = os.path.join(PKG, "tune_db.json")
 
 HQR_OPT_NO_FALLBACK = 1
-EXPORTS = ("hqr_workspace_size", "qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve",
+HQR_OPT_TSQR_PANEL = 2
+EXPORTS = ("hqr_workspace_size", "hqr_workspace_size_opts", "qr_factor", "qr_apply_qt", "qr_apply_q", "qr_form_q", "qr_backsolve",
            "qr_lsq_solve", "qr_lsq_solve_static", "qr_lsq_refine", "hqr_lse_workspace_size", "qr_lse_solve",
            "hqr_cholesky", "hqr_chol_update", "hqr_batched_workspace_size",
            "qr_lsq_solve_batched",
@@ -64,6 +65,8 @@ def load(path: str = LIB_PATH):
     i64, vp, ip = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
     lib.hqr_workspace_size.argtypes = [i64, i64, i64, ctypes.c_int]
     lib.hqr_workspace_size.restype = i64
+    lib.hqr_workspace_size_opts.argtypes = [i64, i64, i64, ctypes.c_void_p]
+    lib.hqr_workspace_size_opts.restype = i64
     lib.qr_factor.argtypes = [i64, i64, vp, i64, vp, vp, i64, ip, vp]
     lib.qr_apply_qt.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]
     lib.qr_apply_q.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp]
@@ -245,6 +248,14 @@ def workspace_size(m: int, n: int, nrhs: int = 0, precision: int = HQR_PREC_FP64
     return int(r)
 
 
+def workspace_size_opts(m: int, n: int, nrhs: int = 0, precision: int = HQR_PREC_FP64, tsqr: bool = False) -> int:
+    opts = hqr_opts(int(precision), 0.0, -1, HQR_OPT_TSQR_PANEL if tsqr else 0)
+    r = load().hqr_workspace_size_opts(m, n, nrhs, ctypes.byref(opts))
+    if r < 0:
+        raise HQRError("hqr_workspace_size_opts", int(r))
+    return int(r)
+
+
 def qr_factor(A, up=None, info=None, work=None, stream=None):
     """Factor A (m x n, column-major float64 device tensor) in place.
 
@@ -317,8 +328,9 @@ def qr_backsolve(R, B, info=None, stream=None):
 
 
 def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=HQR_PREC_FP64,
-                 tol=0.0, max_iter=-1, A_orig=None, work=None, stream=None, no_fallback=False):
-    """Least squares in place: A factored, B[0:n] <- x, returns (up, resnorm, info, iters)."""
+                 tol=0.0, max_iter=-1, A_orig=None, work=None, stream=None, no_fallback=False, tsqr=False):
+    """Least squares in place: A factored, B[0:n] <- x, returns (up, resnorm, info, iters).
+    tsqr: TSQR panels with Householder reconstruction (HQR_OPT_TSQR_PANEL)."""
     torch = _torch()
     lib = load()
     m, n = A.shape
@@ -332,7 +344,8 @@ def qr_lsq_solve(A, B, up=None, resnorm=None, info=None, iters=None, precision=H
         resnorm = torch.empty(max(nrhs, 1), dtype=torch.float64, device=dev)
     info = _int_dev(info, dev)
     iters = _int_dev(iters, dev)
-    opts = hqr_opts(int(precision), float(tol), int(max_iter), HQR_OPT_NO_FALLBACK if no_fallback else 0)
+    flags = (HQR_OPT_NO_FALLBACK if no_fallback else 0) | (HQR_OPT_TSQR_PANEL if tsqr else 0)
+    opts = hqr_opts(int(precision), float(tol), int(max_iter), flags)
     lda_o = _ld(A_orig, "A_orig") if A_orig is not None else max(1, m)
     lw = 0 if work is None else work.numel() * work.element_size()
     _check("qr_lsq_solve", lib.qr_lsq_solve(m, n, nrhs, _ptr(A), _ld(A, "A"), _ptr(up), _ptr(B), _ld(B, "B"),

@@ -49,6 +49,11 @@ def test_argument_validation_without_gpu(lib):
     assert lib.hqr_workspace_size(4, 3, -1, 0) == -3
     assert lib.hqr_workspace_size(4, 3, 1, 7) == -4
     assert lib.hqr_workspace_size(8192, 4096, 1, 0) > 0
+    from paper_2506_09463_amd import hqr
+    assert hqr.workspace_size_opts(8192, 4096, 1) == lib.hqr_workspace_size(8192, 4096, 1, 0)
+    # the TSQR tree's buffers: level 0's Q (m x 64) at least
+    assert hqr.workspace_size_opts(8192, 4096, 1, tsqr=True) >= lib.hqr_workspace_size(8192, 4096, 1, 0) + 8192 * 64 * 8
+    assert lib.hqr_workspace_size_opts(-1, 0, 0, None) == -1
     info = ctypes.c_int(0)
     assert lib.qr_factor(3, 4, None, 3, None, None, 0, ctypes.byref(info), None) == -2
     assert lib.qr_factor(4, 3, None, 2, None, None, 0, ctypes.byref(info), None) == -4

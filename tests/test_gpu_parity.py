@@ -248,7 +248,7 @@ def test_argument_errors(hqr):
 
 
 # -------------------------------------------------- panel algorithms
-@pytest.mark.parametrize("mode", ["cqr", "exact", "percol"])
+@pytest.mark.parametrize("mode", ["cqr", "exact", "percol", "tsqr"])
 @pytest.mark.parametrize("m,n,nrhs", [(700, 300, 2), (1100, 129, 1)])
 def test_panel_modes(hqr, oracle_mod, monkeypatch, mode, m, n, nrhs):
     """CholeskyQR2 + reconstruction (default), the exact one-workgroup panel
