@@ -215,6 +215,7 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "small", "batched", "mixed", "served", "slsqp"],
                     help="large (default, the headline line), or one of the other configurations")
     ap.add_argument("--count", type=int, default=2000, help="batched: number of instances")
+    ap.add_argument("--streams", type=int, default=2, help="served, slsqp: the executor's streams")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -573,7 +574,7 @@ def run_served(args):
 
     def run(rate, plain=False, reqs_in=None, keep=False):
         reqs = fresh(base if reqs_in is None else reqs_in)
-        ex = GpuExecutor(nstreams=1 if plain else 2, plain=plain)
+        ex = GpuExecutor(nstreams=1 if plain else args.streams, plain=plain)
         srv = Server(ex, budget_bytes=64 * GiB)
         start = time.perf_counter()
         if rate is None:
@@ -616,7 +617,7 @@ def run_served(args):
     if not args.no_cpu_baseline:
         cpu, err = served_cpu_baseline(done, base)
     cfg = {"workload": "served LSQ stream: %d instances x 3 solves, n log-uniform [16,2048], m = n + U{0..n/2}, "
-                       "1-4 RHS, FP64 or mixed per request, factor reuse, 64 GB budget, 2 streams" % ninst,
+                       "1-4 RHS, FP64 or mixed per request, factor reuse, 64 GB budget, %d streams" % (ninst, args.streams),
            "requests": len(base), "saturation": sat, "poisson_loads": loads,
            "plain_fp64_one_call_per_request": plain,
            "speedup_vs_plain_fp64": sat["throughput_per_s"] / plain["throughput_per_s"],
@@ -734,8 +735,8 @@ def run_slsqp(args):
     count = args.count if args.count != 2000 else 200
     probs = slsqp_driver.make_problems(count, seed=11, nmin=32, nmax=1024)
     warm = slsqp_driver.make_problems(8, seed=12, nmin=32, nmax=1024)
-    slsqp_driver.run_served(warm, Server(GpuExecutor(nstreams=2), budget_bytes=64 * GiB), max_outer=3)
-    srv = Server(GpuExecutor(nstreams=2), budget_bytes=64 * GiB)
+    slsqp_driver.run_served(warm, Server(GpuExecutor(nstreams=args.streams), budget_bytes=64 * GiB), max_outer=3)
+    srv = Server(GpuExecutor(nstreams=args.streams), budget_bytes=64 * GiB)
     stats, us = slsqp_driver.run_served(probs, srv, max_outer=15, tol=1e-11)
     lat = stats.latencies_ms
     print("[bench] slsqp driver: %d instances, %d outer iterations, %d requests in %.2f s, %d converged"

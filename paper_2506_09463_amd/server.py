@@ -15,9 +15,16 @@ Scheduling policy (host side; the GPU work is libhqr's):
     main/wait queue pattern of the paper's Alg. 5, applied to request
     dependencies);
   * continuous batching: whenever one of the executor's streams is idle,
-    every admitted request that is ready is launched on it as ONE batch, so
-    requests that arrived while others ran join the next launch and
-    launches on different streams overlap on the device;
+    admitted requests that are ready are launched on it, so requests that
+    arrived while others ran join the next launch and launches on different
+    streams overlap on the device.  An executor may sort requests into
+    launch classes (``launch_class(r) -> (key, group limit)``): the class of
+    the oldest ready request is launched next, as one group of at most its
+    limit in arrival order.  The GPU executor's classes are "batched" (all
+    small requests in one persistent launch) and "single" (one large request
+    per launch), so a small request never waits for a large one launched
+    beside it, and large ones complete one by one; without classes all
+    ready requests go into one batch;
   * factor cache: completed factorizations stay on the device (LRU) for
     later solve-only requests and are evicted least-recently-used when the
     budget needs the bytes;
@@ -229,9 +236,21 @@ class Server:
         self.queued = keep
 
     def _launch(self):
+        klass = getattr(self.ex, "launch_class", None)
         while self.pending and self.ex.idle_stream():
-            batch = self.pending[: self.max_batch]
-            self.pending = self.pending[self.max_batch:]
+            if klass is None:
+                batch = self.pending[: self.max_batch]
+                self.pending = self.pending[self.max_batch:]
+            else:
+                key, limit = klass(self.pending[0])
+                limit = min(limit, self.max_batch)
+                batch, rest = [], []
+                for r in self.pending:
+                    if len(batch) < limit and klass(r)[0] == key:
+                        batch.append(r)
+                    else:
+                        rest.append(r)
+                self.pending = rest
             entries = [self.cache[r.instance] for r in batch]
             for r in batch:
                 r.status = "running"
@@ -315,9 +334,15 @@ class GpuExecutor:
 
     ``plain=True`` is the reference executor: one plain FP64 library call
     per request (qr_lsq_solve, or qr_apply_qt + qr_backsolve on a cached
-    factor), whatever the size and precision flag, no batched launch."""
+    factor), whatever the size and precision flag, no batched launch.
 
-    def __init__(self, nstreams: int = 2, batch_n_max: int = 512, device="cuda", plain: bool = False):
+    Launch classes (see Server): requests for the batched launch form one
+    class, every other request is launched on its own (``single_group`` per
+    launch), so it completes on its own event; the plain executor keeps one
+    class."""
+
+    def __init__(self, nstreams: int = 2, batch_n_max: int = 512, device="cuda", plain: bool = False,
+                 single_group: int = 1):
         import torch
         import paper_2506_09463_amd as hqr
         self.torch = torch
@@ -328,6 +353,14 @@ class GpuExecutor:
         self.busy = [False] * nstreams
         self.batch_n_max = batch_n_max
         self.plain = plain
+        self.single_group = single_group
+
+    def launch_class(self, r):
+        if self.plain:
+            return "plain", 1 << 30
+        if r.n <= self.batch_n_max and not r.fallback:
+            return "batched", 1 << 30
+        return "single", self.single_group
 
     def idle_stream(self) -> bool:
         return not all(self.busy)

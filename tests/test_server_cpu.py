@@ -191,3 +191,44 @@ def test_unconverged_mixed_request_is_requeued_as_fp64(oracle_mod, monkeypatch):
     A0 = np.random.default_rng(0).standard_normal((8, 4))
     xo, *_ = oracle_mod.lsq_solve(A0, a.B)
     assert np.allclose(a.x, xo, rtol=1e-12, atol=1e-12)
+
+
+class ClassExecutor(FakeExecutor):
+    """Sorts requests into launch classes like the GPU executor: n <= 4 into
+    one batched launch, larger ones one per launch; large launches take 3 s,
+    batched ones 1 s."""
+
+    def launch_class(self, r):
+        return ("batched", 1 << 30) if r.n <= 4 else ("single", 1)
+
+    def launch(self, batch, entries):
+        h = super().launch(batch, entries)
+        if batch[0].n > 4:
+            h["t"] = self.clock() + 3.0
+        return h
+
+
+def test_launch_classes_keep_small_requests_off_large_launches(oracle_mod):
+    """The class of the oldest ready request goes first; small requests join
+    one batched launch and never ride on a large one, so they complete after
+    1 s while the large ones (one launch each) take 3 s."""
+    clk = Clock()
+    ex = ClassExecutor(clk, nstreams=3, dur=1.0, oracle=oracle_mod)
+    srv = Server(ex, budget_bytes=1 << 24, clock=clk)
+    reqs = [srv.submit(_req(0, 0, "factor_solve", m=16, n=8)),
+            srv.submit(_req(1, 1, "factor_solve")),
+            srv.submit(_req(2, 2, "factor_solve", m=16, n=8)),
+            srv.submit(_req(3, 3, "factor_solve"))]
+    srv.step()
+    assert ex.batches == [[0], [1, 3], [2]]
+    clk.t = 1.0
+    srv.step()
+    assert [r.status for r in reqs] == ["running", "done", "running", "done"]
+    clk.t = 3.0
+    srv.step()
+    assert all(r.status == "done" for r in reqs)
+    st = srv.stats()
+    assert st["p50_ms"] == pytest.approx(1000.0) and st["p99_ms"] == pytest.approx(3000.0)
+    A0 = np.random.default_rng(1).standard_normal((8, 4))
+    xo, *_ = oracle_mod.lsq_solve(A0, reqs[1].B)
+    assert np.allclose(reqs[1].x, xo, rtol=1e-12, atol=1e-12)
