@@ -54,29 +54,34 @@ HQR_DEV unsigned lo32(double v) { return (unsigned)__double2loint(v); }
 HQR_DEV unsigned hi32(double v) { return (unsigned)__double2hiint(v); }
 HQR_DEV double mk64(unsigned hi, unsigned lo) { return __hiloint2double((int)hi, (int)lo); }
 
-// S = 32 or 16: lanes with bit log2(S) clear receive a from lane + S, lanes
-// with it set receive b from lane - S (one swap instruction per 32-bit half).
+// S = 32 or 16: one step of the halving sum over the lanes that differ in
+// bit log2(S).  The swap exchanges a's half of the lanes with that bit set
+// and b's half with it clear (one instruction per 32-bit half), so afterwards
+// every lane holds, in the two registers, its own and its partner's copy of
+// the value it keeps: a in the lanes with the bit clear, b in the others.
+// Their sum is that value's partial total (own + partner, or partner + own:
+// the same double).
 template <int S>
-HQR_DEV double swap_partner(double a, double b, bool upper)
+HQR_DEV double swap_add(double a, double b)
 {
     if (S == 32) {
         const auto rl = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
         const auto rh = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
-        return upper ? mk64(rh[0], rl[0]) : mk64(rh[1], rl[1]);
+        return mk64(rh[0], rl[0]) + mk64(rh[1], rl[1]);
     } else {
         const auto rl = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
         const auto rh = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
-        return upper ? mk64(rh[0], rl[0]) : mk64(rh[1], rl[1]);
+        return mk64(rh[0], rl[0]) + mk64(rh[1], rl[1]);
     }
 }
 
-// DPP move of a double within 16-lane rows (CTRL: a DPP16 control code).
+// DPP move of a double within 16-lane rows (CTRL: a DPP16 control code
+// whose source lane is valid for every lane, so no old value is needed).
 template <int CTRL>
 HQR_DEV double dpp64(double v)
 {
-    const unsigned l = __builtin_amdgcn_update_dpp(0u, lo32(v), CTRL, 0xf, 0xf, false);
-    const unsigned h = __builtin_amdgcn_update_dpp(0u, hi32(v), CTRL, 0xf, 0xf, false);
-    return mk64(h, l);
+    const long r = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, v), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, r);
 }
 
 constexpr int DPP_ROW_ROR8 = 0x128;      // lane i <- i ^ 8 within the row
@@ -93,11 +98,11 @@ constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1, 0, 3, 2]
 HQR_DEV double wave_sum16(const double (&v)[WG_P], int lane)
 {
     double a8[8], a4[4], a2[2];
-    const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0, h2 = (lane & 4) != 0;
+    const bool h3 = (lane & 8) != 0, h2 = (lane & 4) != 0;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) a8[t] = (h5 ? v[8 + t] : v[t]) + swap_partner<32>(v[t], v[8 + t], h5);
+    for (int t = 0; t < 8; ++t) a8[t] = swap_add<32>(v[t], v[8 + t]);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a4[t] = (h4 ? a8[4 + t] : a8[t]) + swap_partner<16>(a8[t], a8[4 + t], h4);
+    for (int t = 0; t < 4; ++t) a4[t] = swap_add<16>(a8[t], a8[4 + t]);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const double keep = h3 ? a4[2 + t] : a4[t];
@@ -298,33 +303,74 @@ HQR_DEV void wg_panel_factor(const WgDesc &d, int c0, int pw, WgShared<NT, QM> &
     const int m = (int)d.m, nrows = m - c0;
     const size_t lda = (size_t)d.lda;
     double *const Ap = d.A + (size_t)c0 * lda + c0;   // A[c0][c0]
-    // stage the panel in LDS (columns beyond pw as zeros), then each thread
-    // takes its rows into registers
-#pragma unroll 1
-    for (int j = 0; j < WG_P; ++j) {
-        if (j < pw) {
-            const double *col = Ap + (size_t)j * lda;
-            for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = col[rr];
-        } else {
-            for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = 0.0;
-        }
-    }
-    if (tid < WG_P) {
-#pragma unroll
-        for (int j = 0; j < WG_P; ++j) sh.t[tid * WG_LD + j] = 0.0;
-    }
-    __syncthreads();
     double a[QM][WG_P];
+    if (pw == WG_P) {
+        // full panel: each thread loads its rows of the 16 columns straight
+        // into registers; a row's 16 loads (and those of its other rows) are
+        // all in flight before the first is used, instead of one round trip
+        // per column through LDS
 #pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        const int rr = tid + NT * q;
+        for (int q = 0; q < QM; ++q) {
+            const int rr = tid + NT * q;
+            if (rr < nrows) {
 #pragma unroll
-        for (int j = 0; j < WG_P; ++j) a[q][j] = (rr < nrows) ? sh.v[rr * WG_LD + j] : 0.0;
+                for (int j = 0; j < WG_P; ++j) a[q][j] = Ap[(size_t)j * lda + rr];
+            } else {
+#pragma unroll
+                for (int j = 0; j < WG_P; ++j) a[q][j] = 0.0;
+            }
+        }
+        if (tid < WG_P) {
+#pragma unroll
+            for (int j = 0; j < WG_P; ++j) sh.t[tid * WG_LD + j] = 0.0;
+        }
+        __syncthreads();
+    } else {
+        // ragged last panel: staged in LDS (columns beyond pw as zeros), then
+        // each thread takes its rows into registers
+#pragma unroll 1
+        for (int j = 0; j < WG_P; ++j) {
+            if (j < pw) {
+                const double *col = Ap + (size_t)j * lda;
+                for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = col[rr];
+            } else {
+                for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = 0.0;
+            }
+        }
+        if (tid < WG_P) {
+#pragma unroll
+            for (int j = 0; j < WG_P; ++j) sh.t[tid * WG_LD + j] = 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int rr = tid + NT * q;
+#pragma unroll
+            for (int j = 0; j < WG_P; ++j) a[q][j] = (rr < nrows) ? sh.v[rr * WG_LD + j] : 0.0;
+        }
     }
     // up of the reflector whose pivot row this thread owns (V's diagonal);
     // T row `tid` (tid < 16) lives in LDS, written and read by its thread only
     double myup = 0.0;
     wg_panel_steps<NT, QM>(d, c0, pw, m, a, myup, sh, std::make_integer_sequence<int, WG_P>{});
+    if (pw == WG_P) {
+        // the factored panel from registers to A; V (up on the diagonal, zeros
+        // above it) into LDS for the trailing update.  The diagonal of row
+        // rr < 16 belongs to thread rr (q = 0), whose myup it is.
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int rr = tid + NT * q;
+            if (rr < nrows) {
+#pragma unroll
+                for (int j = 0; j < WG_P; ++j) {
+                    Ap[(size_t)j * lda + rr] = a[q][j];
+                    sh.v[rr * WG_LD + j] = (rr < j) ? 0.0 : ((rr == j) ? myup : a[q][j]);
+                }
+            }
+        }
+        __syncthreads();
+        return;
+    }
     // back through LDS: the factored panel to A, then V (up on the diagonal,
     // zeros above it and beyond pw) stays in LDS for the trailing update
 #pragma unroll
