@@ -169,6 +169,29 @@ HQR_DEV double wg_block_reduce(double x, int op, WgShared<NT, QM> &sh)
     return r;
 }
 
+// ||(x0, x)|| for a column whose sum of squares under- or overflows: the
+// entries scaled by c = max |x_i| first (each thread passes its QM <= 4 rows
+// below the pivot, zeros elsewhere; every thread of the workgroup calls it).
+template <int NT, int QM>
+__device__ __noinline__ double wg_scaled_norm(double x0, double x1, double x2, double x3, double x4,
+                                              WgShared<NT, QM> &sh)
+{
+    const double xs[4] = {x1, x2, x3, x4};
+    double mx = 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) mx = fmax(mx, fabs(xs[q]));
+    const double c = fmax(fabs(x0), wg_block_reduce<NT, QM>(mx, 1, sh));
+    double ss = 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const double y = xs[q] / c;
+        ss = fma(y, y, ss);
+    }
+    const double t2 = wg_block_reduce<NT, QM>(ss, 0, sh);
+    const double x0c = x0 / c;
+    return c * sqrt(x0c * x0c + t2);
+}
+
 // ---------------------------------------------------------------- panel
 // One column step of the panel: k is a compile-time constant so every
 // register index is static (a runtime k would turn the register arrays into
@@ -189,15 +212,18 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
         double s[WG_P];
 #pragma unroll
         for (int j = 0; j < WG_P; ++j) s[j] = 0.0;
+        // no branches on the row (a divergent branch around the register
+        // arrays makes the compiler copy them at every join): rows outside
+        // the column below the pivot contribute x = 0
 #pragma unroll
         for (int q = 0; q < QM; ++q) {
             const int r = c0 + tid + NT * q;
             xk[q] = a[q][k];
-            if (r > pr && r < m) {
-                nz = nz || (xk[q] != 0.0);
+            const bool below = r > pr && r < m;
+            const double xm = below ? xk[q] : 0.0;
+            nz = nz || (xm != 0.0);
 #pragma unroll
-                for (int j = 0; j < WG_P; ++j) s[j] = fma(a[q][j], xk[q], s[j]);
-            }
+            for (int j = 0; j < WG_P; ++j) s[j] = fma(a[q][j], xm, s[j]);
         }
         if (tid == k) {
 #pragma unroll
@@ -224,26 +250,15 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
         if (tot >= 0x1p-920 && tot <= 0x1p920) {
             nu = sqrt(tot);
         } else {
-            // scaled norm: max |x| over the column from the pivot down
-            double mx = 0.0;
+            // rare: the squares under- or overflow (one copy of this code,
+            // outside the unrolled steps)
+            double xs[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
                 const int r = c0 + tid + NT * q;
-                if (r > pr && r < m) mx = fmax(mx, fabs(xk[q]));
+                xs[q] = (r > pr && r < m) ? xk[q] : 0.0;
             }
-            const double c = fmax(fabs(x0), wg_block_reduce<NT, QM>(mx, 1, sh));
-            double ss = 0.0;
-#pragma unroll
-            for (int q = 0; q < QM; ++q) {
-                const int r = c0 + tid + NT * q;
-                if (r > pr && r < m) {
-                    const double y = xk[q] / c;
-                    ss = fma(y, y, ss);
-                }
-            }
-            const double t2 = wg_block_reduce<NT, QM>(ss, 0, sh);
-            const double x0c = x0 / c;
-            nu = c * sqrt(x0c * x0c + t2);
+            nu = wg_scaled_norm<NT, QM>(x0, xs[0], xs[1], xs[2], xs[3], sh);
         }
         sk = (x0 >= 0.0) ? -nu : nu;
         upk = x0 - sk;
@@ -270,20 +285,23 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
     } else if (tid == k) {
         sh.t[tid * WG_LD + k] = -inv_b;
     }
-    // apply H_k to the panel's columns k+1 .. pw-1 (own rows)
+    // apply H_k to the panel's columns k+1 .. pw-1 (own rows), by selects:
+    // rows above the pivot and beyond m keep their values exactly
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         const int r = c0 + tid + NT * q;
-        if (r > pr && r < m) {
+        const bool below = r > pr && r < m, piv = r == pr;
+        const double vr = piv ? upk : xk[q];
 #pragma unroll
-            for (int j = k + 1; j < WG_P; ++j) a[q][j] = fma(wv[j], xk[q], a[q][j]);
-        } else if (r == pr) {
-#pragma unroll
-            for (int j = k + 1; j < WG_P; ++j) a[q][j] = fma(wv[j], upk, a[q][j]);
-            a[q][k] = sk;
+        for (int j = k + 1; j < WG_P; ++j) {
+            const double t = fma(wv[j], vr, a[q][j]);
+            a[q][j] = (below || piv) ? t : a[q][j];
         }
+        a[q][k] = piv ? sk : a[q][k];
     }
-    if (tid == 0) d.up[pr] = upk;
+    // up_k is stored once per panel (thread k holds it in myup): a global
+    // store here would make every later step reload the descriptor and wait
+    // for the store to complete
 }
 
 template <int NT, int QM, int... Ks>
@@ -353,6 +371,7 @@ HQR_DEV void wg_panel_factor(const WgDesc &d, int c0, int pw, WgShared<NT, QM> &
     // T row `tid` (tid < 16) lives in LDS, written and read by its thread only
     double myup = 0.0;
     wg_panel_steps<NT, QM>(d, c0, pw, m, a, myup, sh, std::make_integer_sequence<int, WG_P>{});
+    if (tid < pw) d.up[c0 + tid] = myup;
     if (pw == WG_P) {
         // the factored panel from registers to A; V (up on the diagonal, zeros
         // above it) into LDS for the trailing update.  The diagonal of row
