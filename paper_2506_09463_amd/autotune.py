@@ -145,8 +145,10 @@ def tune_batched(hqr, seed=12, count=512, reps=5, log=print):
             for b, b0 in zip(Bs, B0):
                 b.copy_(b0)
 
+        plan = hqr.BatchPlan(As, Bs, ups=ups, resnorms=res, info=info, work=work)
+
         def run():
-            hqr.qr_lsq_solve_batched(As, Bs, ups=ups, resnorms=res, info=info, work=work, stream=stream)
+            plan.run(stream)
 
         mmax = max(A.shape[0] for A, _ in probs)
         cands = [(nm, occ) for nm in names if nm.startswith("wg256x") and _variant_rows(nm)[1] >= mmax

@@ -441,54 +441,74 @@ def profile_end(max_classes: int = 64):
     return out
 
 
+class BatchPlan:
+    """The marshalled arguments of one batched launch: shapes, leading
+    dimensions and device pointers of a list of problems, kept so that a
+    caller reusing the same buffers (an SLSQP loop, a benchmark) marshals them
+    once and then only pays for the library call.  ``run`` enqueues
+    qr_lsq_solve_batched (or qr_lsq_batched_mixed when ``factored`` is given)
+    on ``stream``; the tensors must stay alive and keep their storage."""
+
+    def __init__(self, As, Bs, ups=None, resnorms=None, info=None, work=None, factored=None):
+        torch = _torch()
+        self.lib = load()
+        count = len(As)
+        if len(Bs) != count:
+            raise ValueError("As and Bs differ in length")
+        self.count = count
+        if count == 0:
+            self.ups, self.resnorms, self.info = [], [], torch.zeros(0, dtype=torch.int32)
+            return
+        dev = As[0].device
+        if ups is None:
+            ups = [torch.empty(max(A.shape[1], 1), dtype=torch.float64, device=dev) for A in As]
+        if resnorms is None:
+            resnorms = [torch.empty(max(Bm.shape[1], 1), dtype=torch.float64, device=dev) for Bm in Bs]
+        for i, (A, Bm) in enumerate(zip(As, Bs)):
+            if Bm.shape[0] != A.shape[0]:
+                raise ValueError("instance %d: B must have m rows" % i)
+        i64, vp = ctypes.c_int64 * count, ctypes.c_void_p * count
+        self.ms = i64(*[A.shape[0] for A in As])
+        self.ns = i64(*[A.shape[1] for A in As])
+        self.rs = i64(*[Bm.shape[1] for Bm in Bs])
+        self.ldas = i64(*[_ld(A, "A[%d]" % i) for i, A in enumerate(As)])
+        self.ldbs = i64(*[_ld(Bm, "B[%d]" % i) for i, Bm in enumerate(Bs)])
+        self.pa = vp(*[A.data_ptr() for A in As])
+        self.pb = vp(*[Bm.data_ptr() for Bm in Bs])
+        self.pu = vp(*[u.data_ptr() for u in ups])
+        self.pr = vp(*[r.data_ptr() for r in resnorms])
+        self.fl = None if factored is None else (ctypes.c_int * count)(*[1 if f else 0 for f in factored])
+        self.info = torch.zeros(count, dtype=torch.int32, device=dev) if info is None else info
+        self.work = work
+        self.lw = 0 if work is None else work.numel() * work.element_size()
+        self.ups, self.resnorms = ups, resnorms
+        self._keep = (As, Bs)
+
+    def run(self, stream=None):
+        if self.count == 0:
+            return self.ups, self.resnorms, self.info
+        cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
+        lib = self.lib
+        if self.fl is None:
+            _check("qr_lsq_solve_batched", lib.qr_lsq_solve_batched(
+                self.count, cast(self.ms), cast(self.ns), cast(self.rs), cast(self.pa), cast(self.ldas),
+                cast(self.pu), cast(self.pb), cast(self.ldbs), cast(self.pr), _ptr(self.info), _ptr(self.work),
+                self.lw, _stream(stream)))
+        else:
+            _check("qr_lsq_batched_mixed", lib.qr_lsq_batched_mixed(
+                self.count, cast(self.ms), cast(self.ns), cast(self.rs), cast(self.pa), cast(self.ldas),
+                cast(self.pu), cast(self.pb), cast(self.ldbs), cast(self.pr), cast(self.fl), _ptr(self.info),
+                _ptr(self.work), self.lw, _stream(stream)))
+        return self.ups, self.resnorms, self.info
+
+
 def qr_lsq_solve_batched(As, Bs, ups=None, resnorms=None, info=None, work=None, stream=None, factored=None):
     """Solve a list of least-squares problems in one persistent launch.
 
     As, Bs: lists of column-major float64 device tensors (A_i m_i x n_i,
     B_i m_i x nrhs_i), overwritten in place like qr_lsq_solve.  Returns
     (ups, resnorms, info) with info a device int32 tensor of len(As)."""
-    torch = _torch()
-    lib = load()
-    count = len(As)
-    if len(Bs) != count:
-        raise ValueError("As and Bs differ in length")
-    if count == 0:
-        return [], [], torch.zeros(0, dtype=torch.int32)
-    dev = As[0].device
-    ms = (ctypes.c_int64 * count)()
-    ns = (ctypes.c_int64 * count)()
-    rs = (ctypes.c_int64 * count)()
-    ldas = (ctypes.c_int64 * count)()
-    ldbs = (ctypes.c_int64 * count)()
-    pa = (ctypes.c_void_p * count)()
-    pb = (ctypes.c_void_p * count)()
-    pu = (ctypes.c_void_p * count)()
-    pr = (ctypes.c_void_p * count)()
-    if ups is None:
-        ups = [torch.empty(max(A.shape[1], 1), dtype=torch.float64, device=dev) for A in As]
-    if resnorms is None:
-        resnorms = [torch.empty(max(Bm.shape[1], 1), dtype=torch.float64, device=dev) for Bm in Bs]
-    for i, (A, Bm) in enumerate(zip(As, Bs)):
-        if Bm.shape[0] != A.shape[0]:
-            raise ValueError("instance %d: B must have m rows" % i)
-        ms[i], ns[i], rs[i] = A.shape[0], A.shape[1], Bm.shape[1]
-        ldas[i], ldbs[i] = _ld(A, "A[%d]" % i), _ld(Bm, "B[%d]" % i)
-        pa[i], pb[i] = A.data_ptr(), Bm.data_ptr()
-        pu[i], pr[i] = ups[i].data_ptr(), resnorms[i].data_ptr()
-    if info is None:
-        info = torch.zeros(count, dtype=torch.int32, device=dev)
-    lw = 0 if work is None else work.numel() * work.element_size()
-    cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
-    if factored is None:
-        _check("qr_lsq_solve_batched", lib.qr_lsq_solve_batched(
-            count, cast(ms), cast(ns), cast(rs), cast(pa), cast(ldas), cast(pu), cast(pb), cast(ldbs),
-            cast(pr), _ptr(info), _ptr(work), lw, _stream(stream)))
-    else:
-        fl = (ctypes.c_int * count)(*[1 if f else 0 for f in factored])
-        _check("qr_lsq_batched_mixed", lib.qr_lsq_batched_mixed(
-            count, cast(ms), cast(ns), cast(rs), cast(pa), cast(ldas), cast(pu), cast(pb), cast(ldbs),
-            cast(pr), cast(fl), _ptr(info), _ptr(work), lw, _stream(stream)))
-    return ups, resnorms, info
+    return BatchPlan(As, Bs, ups, resnorms, info, work, factored).run(stream)
 
 
 def batched_workspace_size(count: int) -> int:

@@ -157,3 +157,30 @@ def test_batched_full_workload_vs_oracle(hqr, oracle_mod):
         if i % 250 == 0:
             _say("checked %d instances (%.0f s)" % (i + 1, time.time() - t0))
     _say("worst |F - F_o| / tol %.2e, worst x error / bound %.2e" % (worst_f, worst_x))
+
+
+def test_batch_plan_reuse_is_bitwise(hqr):
+    """A BatchPlan marshals the pointers once; running it again on restored
+    inputs gives bitwise the results of a fresh qr_lsq_solve_batched call."""
+    import torch
+    probs = _mixed_problems(95, 60, 300, 4)
+    _say("BatchPlan reuse", len(probs))
+    ref, ref_info = _solve_batch(hqr, probs)
+    A0 = [to_dev(A) for A, _ in probs]
+    B0 = [to_dev(B) for _, B in probs]
+    As = [a.clone() for a in A0]
+    Bs = [b.clone() for b in B0]
+    plan = hqr.BatchPlan(As, Bs)
+    for rep in range(2):
+        for a, a0 in zip(As, A0):
+            a.copy_(a0)
+        for b, b0 in zip(Bs, B0):
+            b.copy_(b0)
+        ups, res, info = plan.run()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(info).astype(int), ref_info)
+        for i, (A, B) in enumerate(probs):
+            n = A.shape[1]
+            assert np.array_equal(to_host(As[i]), ref[i][0])
+            assert np.array_equal(to_host(ups[i])[:n], ref[i][1])
+            assert np.array_equal(to_host(Bs[i]), ref[i][2])
