@@ -36,26 +36,31 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch (read, write) of each kernel class on the default
 # workload, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs scaled by the
 # same counters on a 1 GiB device copy (x2.0 and x1.0).  Valid only for the
-# kernel sources they were taken on (SHA-256 over csrc/); otherwise the
-# roofline's traffic is null.  A class's figure averages over all its
+# kernel sources they were taken on (SHA-256 over the files that define the
+# blocked path's kernels and their arguments, C2_KERNEL_SOURCES); otherwise
+# the roofline's traffic is null.  A class's figure averages over all its
 # launches (update: the 64-column launch for panel p+2 and the bulk launch;
 # gram_reduce: the two Gram reductions and the X/W reduction).
 HBM_TRAFFIC = {
-    "csrc_sha256": "5a2feed2b69037fc64b6868801cb8ee49c29a7575a31a878b490a4c338392aa0",
-    "per_launch_bytes": {"update": [73643102, 55164431], "cqr_chol": [195224, 82176], "vtx": [130921591, 15503360],
-                         "wsolve": [15216532, 1001984], "trsv": [68735751, 34816], "cqr_gram1": [6731404, 6294032],
-                         "cqr_gram2": [3531743, 3194880], "gram_reduce": [3295444, 32779],
-                         "narrow_vtx": [6770795, 6324224], "cqr_finish": [2447283, 2097152]},
+    "csrc_sha256": "06ec85777ecb3d70ade89ed7cb0c3e0725662b8f0beccd79695f122553a0ebea",
+    "per_launch_bytes": {"update": [73644228, 55162566], "vtx": [130921716, 15503360],
+                         "wsolve": [15226401, 1001984], "trsv": [68727565, 34816],
+                         "cqr_gram1": [6731388, 6294032], "cqr_gram2": [3531683, 3194880],
+                         "cqr_chol": [197504, 82176], "cqr_finish": [2447283, 2097152],
+                         "narrow_vtx": [6770774, 6324224], "gram_reduce": [3307074, 32779]},
 }
 
 
+C2_KERNEL_SOURCES = ("hqr_args.hpp", "hqr_device.hpp", "hqr_blocked.hpp", "hqr_cqr.hpp", "k_blocked.hip",
+                     "k_cqr.hip")
+
+
 def csrc_sha256():
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2506_09463_amd", "csrc", "*"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
+    for nm in C2_KERNEL_SOURCES:
+        h.update(nm.encode())
+        with open(os.path.join(ROOT, "paper_2506_09463_amd", "csrc", nm), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
