@@ -89,35 +89,68 @@ constexpr int DPP_ROW_HALF_MIRROR = 0x141; // lane i <- 7 - i within 8 lanes
 constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2, 3, 0, 1]
 constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1, 0, 3, 2]
 
-// Sum of v[0..15] over the wave by recursive halving: lane L ends with the
-// total of index 8*b5 + 4*b4 + 2*b3 + b2 (b_i = bit i of L).  At each step a
+// Sum over the wave of N = 16, 8, 4 or 2 values v[0..N-1] by recursive
+// halving: lane L ends with the total of index wave_sum_index<N>(L), from
+// bits 5, 4, 3, 2 of L (the top log2(N) of them).  At each halving step a
 // lane keeps the half of its values selected by one bit of its id and adds
 // the other half of a partner lane across that bit; any pairing that crosses
 // the bit inside the lanes that share the higher bits adds up the same sums
-// (the bit-2 step pairs i with 7 - i, the others with i ^ 2^b).  No LDS.
-HQR_DEV double wave_sum16(const double (&v)[WG_P], int lane)
+// (the bit-2 step pairs i with 7 - i, the others with i ^ 2^b).  The lanes
+// then add across bits 1 and 0 and, for N < 16, across the bits above the
+// index, so every lane holding an index holds the same total.  No LDS.
+template <int N>
+HQR_DEV double wave_sum(const double (&v)[N], int lane)
 {
-    double a8[8], a4[4], a2[2];
+    static_assert(N == 16 || N == 8 || N == 4 || N == 2, "N");
+    double x8[8], x4[4], x2[2];
     const bool h3 = (lane & 8) != 0, h2 = (lane & 4) != 0;
+    if constexpr (N == 16) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) a8[t] = swap_add<32>(v[t], v[8 + t]);
+        for (int t = 0; t < 8; ++t) x8[t] = swap_add<32>(v[t], v[8 + t]);
+    } else if constexpr (N == 8) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a4[t] = swap_add<16>(a8[t], a8[4 + t]);
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const double keep = h3 ? a4[2 + t] : a4[t];
-        const double give = h3 ? a4[t] : a4[2 + t];
-        a2[t] = keep + dpp64<DPP_ROW_ROR8>(give);
+        for (int t = 0; t < 8; ++t) x8[t] = v[t];
     }
-    double a1 = (h2 ? a2[1] : a2[0]) + dpp64<DPP_ROW_HALF_MIRROR>(h2 ? a2[0] : a2[1]);
+    if constexpr (N >= 8) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x4[t] = swap_add<16>(x8[t], x8[4 + t]);
+    } else if constexpr (N == 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x4[t] = v[t];
+    }
+    if constexpr (N >= 4) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const double keep = h3 ? x4[2 + t] : x4[t];
+            const double give = h3 ? x4[t] : x4[2 + t];
+            x2[t] = keep + dpp64<DPP_ROW_ROR8>(give);
+        }
+    } else {
+        x2[0] = v[0];
+        x2[1] = v[1];
+    }
+    double a1 = (h2 ? x2[1] : x2[0]) + dpp64<DPP_ROW_HALF_MIRROR>(h2 ? x2[0] : x2[1]);
     a1 += dpp64<DPP_QUAD_XOR2>(a1);
     a1 += dpp64<DPP_QUAD_XOR1>(a1);
+    if constexpr (N <= 2) a1 += dpp64<DPP_ROW_ROR8>(a1);
+    if constexpr (N <= 4) a1 = swap_add<16>(a1, a1);
+    if constexpr (N <= 8) a1 = swap_add<32>(a1, a1);
     return a1;
 }
 
-HQR_DEV int wave_sum16_index(int lane)
+template <int N>
+HQR_DEV int wave_sum_index(int lane)
 {
-    return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+    const int i = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+    return i & (N - 1);
+}
+
+// lanes that write a wave_sum<N> total: one per index
+template <int N>
+HQR_DEV bool wave_sum_writer(int lane)
+{
+    constexpr int dup = (N == 16) ? 3 : (N == 8) ? 32 + 3 : (N == 4) ? 48 + 3 : 56 + 3;
+    return (lane & dup) == 0;
 }
 
 // The value lane 16r + i holds, in every lane of row r (DPP row_newbcast;
@@ -205,13 +238,18 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
     if (k >= pw) return;
     const int pr = c0 + k;
     const int buf = k & 1;
-    // partial dots of the column below the pivot with every panel column
+    // the step needs the dots with columns k .. 15 only (the norm and the
+    // weights; T comes from V^T V after the panel): they are reduced over
+    // the last N = 16, 8, 4 or 2 columns, starting at column j0
+    constexpr int j0 = (k < 8) ? 0 : (k < 12) ? 8 : (k < 14) ? 12 : 14;
+    constexpr int NRED = WG_P - j0;
+    // partial dots of the column below the pivot with the panel columns
     double xk[QM];
     bool nz = false;
     {
-        double s[WG_P];
+        double s[NRED];
 #pragma unroll
-        for (int j = 0; j < WG_P; ++j) s[j] = 0.0;
+        for (int j = 0; j < NRED; ++j) s[j] = 0.0;
         // no branches on the row (a divergent branch around the register
         // arrays makes the compiler copy them at every join): rows outside
         // the column below the pivot contribute x = 0
@@ -223,14 +261,14 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
             const double xm = below ? xk[q] : 0.0;
             nz = nz || (xm != 0.0);
 #pragma unroll
-            for (int j = 0; j < WG_P; ++j) s[j] = fma(a[q][j], xm, s[j]);
+            for (int j = k; j < WG_P; ++j) s[j - j0] = fma(a[q][j], xm, s[j - j0]);
         }
         if (tid == k) {
 #pragma unroll
-            for (int j = 0; j < WG_P; ++j) sh.prow[buf][j] = a[0][j];
+            for (int j = k; j < WG_P; ++j) sh.prow[buf][j] = a[0][j];
         }
-        const double part = wave_sum16(s, lane);
-        if ((lane & 3) == 0) sh.red[buf][w][wave_sum16_index(lane)] = part;
+        const double part = wave_sum<NRED>(s, lane);
+        if (wave_sum_writer<NRED>(lane)) sh.red[buf][w][j0 + wave_sum_index<NRED>(lane)] = part;
     }
     const bool wnz = __ballot(nz) != 0ull;
     if (lane == 0) sh.red[buf][w][WG_P] = wnz ? 1.0 : 0.0;
@@ -265,26 +303,18 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
     }
     const double inv_b = anynz ? 1.0 / (upk * sk) : 0.0;
     if (tid == k) myup = upk;
-    // w_j = (up A[pr][j] + sum_{r>pr} A[r][j] A[r][k]) / b for every panel
-    // column; for l < k, w_l = (v_l^T v_k) / b_k, which T's column needs
+    // w_j = (up A[pr][j] + sum_{r>pr} A[r][j] A[r][k]) / b for the later
+    // panel columns
     double wv[WG_P];
 #pragma unroll
-    for (int j = 0; j < WG_P; ++j) {
+    for (int j = k + 1; j < WG_P; ++j) {
         double t = sh.red[buf][0][j];
 #pragma unroll
         for (int i = 1; i < NWV; ++i) t += sh.red[buf][i][j];
         wv[j] = fma(upk, sh.prow[buf][j], t) * inv_b;
     }
-    // T column k: T[k][k] = tau_k = -1/b_k, T[i][k] = -tau_k sum_{l<k} T[i][l] v_l^T v_k
-    if (tid < k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int l = 0; l < WG_P; ++l)
-            if (l < k) acc = fma(sh.t[tid * WG_LD + l], wv[l], acc);
-        sh.t[tid * WG_LD + k] = acc;
-    } else if (tid == k) {
-        sh.t[tid * WG_LD + k] = -inv_b;
-    }
+    // T's diagonal: tau_k = -1/b_k (the rest of T follows the panel)
+    if (tid == k) sh.t[k * WG_LD + k] = -inv_b;
     // apply H_k to the panel's columns k+1 .. pw-1 (own rows), by selects:
     // rows above the pivot and beyond m keep their values exactly
 #pragma unroll
@@ -309,6 +339,67 @@ HQR_DEV void wg_panel_steps(const WgDesc &d, int c0, int pw, int m, double (&a)[
                             WgShared<NT, QM> &sh, std::integer_sequence<int, Ks...>)
 {
     (wg_panel_step<NT, QM, Ks>(d, c0, pw, m, a, myup, sh), ...);
+}
+
+// T of a factored panel: the Gram matrix G = V^T V of the panel's vectors
+// (in sh.v, rows 0 .. nrows-1; columns beyond pw zero) on MFMA, then T row i
+// by thread i from T[i][k] = -tau_k sum_{l=i}^{k-1} T[i][l] G[l][k], with
+// tau_k = T[k][k] as the column steps left it.  Starts after a barrier, ends
+// with one.
+template <int NT, int QM>
+HQR_DEV void wg_panel_t(int nrows, int pw, WgShared<NT, QM> &sh)
+{
+    constexpr int NWV = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double tau[WG_P];
+    if (tid < WG_P) {
+#pragma unroll
+        for (int k = 0; k < WG_P; ++k) tau[k] = sh.t[k * WG_LD + k];
+    }
+    f64x4 g = {0.0, 0.0, 0.0, 0.0};
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int nb16 = (nrows + 15) / 16;
+    for (int rb = w; rb < nb16; rb += NWV) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int rr = rb * 16 + 4 * kq + s;
+            const double vv = (rr < nrows) ? sh.v[rr * WG_LD + i16] : 0.0;
+            g = __builtin_amdgcn_mfma_f64_16x16x4f64(vv, vv, g, 0, 0, 0);
+        }
+    }
+    __syncthreads();   // the taus are in registers before G overwrites the T area
+    // G[i][j] at lane j + 16 (i % 4), reg i / 4; waves add into sh.t in turn
+    for (int wv = 0; wv < NWV; ++wv) {
+        if (w == wv) {
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                double *dst = &sh.t[(4 * r4 + kq) * WG_LD + i16];
+                *dst = (wv == 0) ? g[r4] : *dst + g[r4];
+            }
+        }
+        __syncthreads();
+    }
+    double trow[WG_P];
+#pragma unroll
+    for (int j = 0; j < WG_P; ++j) trow[j] = 0.0;
+    if (tid < WG_P) {
+#pragma unroll
+        for (int k = 0; k < WG_P; ++k) {
+            if (k < pw) {
+                double acc = 0.0;
+#pragma unroll
+                for (int l = 0; l < k; ++l) acc = fma(trow[l], sh.t[l * WG_LD + k], acc);
+                if (tid < k) trow[k] = -tau[k] * acc;
+                if (tid == k) trow[k] = tau[k];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < WG_P) {
+#pragma unroll
+        for (int j = 0; j < WG_P; ++j) sh.t[tid * WG_LD + j] = trow[j];
+    }
+    __syncthreads();
 }
 
 // Factor columns c0 .. c0+pw-1 (rows c0 .. m-1) in registers; write them
@@ -368,7 +459,7 @@ HQR_DEV void wg_panel_factor(const WgDesc &d, int c0, int pw, WgShared<NT, QM> &
         }
     }
     // up of the reflector whose pivot row this thread owns (V's diagonal);
-    // T row `tid` (tid < 16) lives in LDS, written and read by its thread only
+    // the steps leave tau_k on T's diagonal
     double myup = 0.0;
     wg_panel_steps<NT, QM>(d, c0, pw, m, a, myup, sh, std::make_integer_sequence<int, WG_P>{});
     if (tid < pw) d.up[c0 + tid] = myup;
@@ -388,6 +479,7 @@ HQR_DEV void wg_panel_factor(const WgDesc &d, int c0, int pw, WgShared<NT, QM> &
             }
         }
         __syncthreads();
+        wg_panel_t<NT, QM>(nrows, pw, sh);
         return;
     }
     // back through LDS: the factored panel to A, then V (up on the diagonal,
@@ -417,6 +509,7 @@ HQR_DEV void wg_panel_factor(const WgDesc &d, int c0, int pw, WgShared<NT, QM> &
     for (int j = pw; j < WG_P; ++j)
         for (int rr = tid; rr < nrows; rr += NT) sh.v[rr * WG_LD + j] = 0.0;
     __syncthreads();
+    wg_panel_t<NT, QM>(nrows, pw, sh);
 }
 
 // Stored factorization: V from A's tails and up, T from V^T V.  Ends with a
