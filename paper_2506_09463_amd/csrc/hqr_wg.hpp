@@ -225,6 +225,34 @@ __device__ __noinline__ double wg_scaled_norm(double x0, double x1, double x2, d
     return c * sqrt(x0c * x0c + t2);
 }
 
+// s = sqrt(d) and r = 1/sqrt(d) for 2^-920 <= d <= 2^920: the hardware
+// reciprocal square root refined by two coupled Newton steps for s and
+// 1/(2s) (Goldschmidt's iteration), then one residual correction of s.
+HQR_DEV void wg_sqrt_rsqrt(double d, double &s, double &r)
+{
+    const double y = __builtin_amdgcn_rsq(d);
+    double sv = d * y, h = 0.5 * y;
+    double e = fma(-sv, h, 0.5);
+    sv = fma(sv, e, sv);
+    h = fma(h, e, h);
+    e = fma(-sv, h, 0.5);
+    sv = fma(sv, e, sv);
+    h = fma(h, e, h);
+    s = fma(h, fma(-sv, sv, d), sv);
+    r = 2.0 * h;
+}
+
+// 1/u for a normal u whose reciprocal is normal: the hardware reciprocal
+// and two Newton steps.
+HQR_DEV double wg_recip(double u)
+{
+    double y = __builtin_amdgcn_rcp(u);
+    double e = fma(-u, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-u, y, 1.0);
+    return fma(y, e, y);
+}
+
 // ---------------------------------------------------------------- panel
 // One column step of the panel: k is a compile-time constant so every
 // register index is static (a runtime k would turn the register arrays into
@@ -273,20 +301,35 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
     const bool wnz = __ballot(nz) != 0ull;
     if (lane == 0) sh.red[buf][w][WG_P] = wnz ? 1.0 : 0.0;
     __syncthreads();
-    // every thread forms the same scalars from the reduction
+    // every thread forms the same scalars from the reduction.  Lane 16r + j
+    // sums the waves' partial dots of column j (the same total in each of the
+    // four 16-lane rows) and holds A[pr][j]; the values a thread needs of
+    // other columns come by DPP row broadcasts instead of LDS reads of their
+    // own (columns below j0 hold stale sums that no lane takes)
+    const int jl = lane & 15;
     bool anynz = false;
-    double sxx = sh.red[buf][0][k];
+    double dsum = sh.red[buf][0][jl];
 #pragma unroll
-    for (int i = 1; i < NWV; ++i) sxx += sh.red[buf][i][k];
+    for (int i = 1; i < NWV; ++i) dsum += sh.red[buf][i][jl];
+    const double prow_l = sh.prow[buf][jl];
 #pragma unroll
     for (int i = 0; i < NWV; ++i) anynz = anynz || (sh.red[buf][i][WG_P] != 0.0);
-    const double x0 = sh.prow[buf][k];
-    double upk = 0.0, sk = x0;
+    const double sxx = row_bcast16_c<k>(dsum);
+    const double x0 = row_bcast16_c<k>(prow_l);
+    double upk = 0.0, sk = x0, inv_b = 0.0;
     if (anynz) {
         const double tot = x0 * x0 + sxx;
         double nu;
         if (tot >= 0x1p-920 && tot <= 0x1p920) {
-            nu = sqrt(tot);
+            // nu and 1/nu together, then 1/b = 1/(up s) = (1/up)(1/s): no
+            // division and no correctly rounded square root on the step's
+            // dependency chain (|up| >= nu >= 2^-460, so nothing over- or
+            // underflows)
+            double rnu;
+            wg_sqrt_rsqrt(tot, nu, rnu);
+            sk = (x0 >= 0.0) ? -nu : nu;
+            upk = x0 - sk;
+            inv_b = wg_recip(upk) * ((x0 >= 0.0) ? -rnu : rnu);
         } else {
             // rare: the squares under- or overflow (one copy of this code,
             // outside the unrolled steps)
@@ -297,22 +340,18 @@ HQR_DEV void wg_panel_step(const WgDesc &d, int c0, int pw, int m, double (&a)[Q
                 xs[q] = (r > pr && r < m) ? xk[q] : 0.0;
             }
             nu = wg_scaled_norm<NT, QM>(x0, xs[0], xs[1], xs[2], xs[3], sh);
+            sk = (x0 >= 0.0) ? -nu : nu;
+            upk = x0 - sk;
+            inv_b = 1.0 / (upk * sk);
         }
-        sk = (x0 >= 0.0) ? -nu : nu;
-        upk = x0 - sk;
     }
-    const double inv_b = anynz ? 1.0 / (upk * sk) : 0.0;
     if (tid == k) myup = upk;
     // w_j = (up A[pr][j] + sum_{r>pr} A[r][j] A[r][k]) / b for the later
     // panel columns
+    const double wl = fma(upk, prow_l, dsum) * inv_b;   // w of column jl
     double wv[WG_P];
 #pragma unroll
-    for (int j = k + 1; j < WG_P; ++j) {
-        double t = sh.red[buf][0][j];
-#pragma unroll
-        for (int i = 1; i < NWV; ++i) t += sh.red[buf][i][j];
-        wv[j] = fma(upk, sh.prow[buf][j], t) * inv_b;
-    }
+    for (int j = k + 1; j < WG_P; ++j) wv[j] = row_bcast16(wl, j);
     // T's diagonal: tau_k = -1/b_k (the rest of T follows the panel)
     if (tid == k) sh.t[k * WG_LD + k] = -inv_b;
     // apply H_k to the panel's columns k+1 .. pw-1 (own rows), by selects:
