@@ -28,9 +28,6 @@
 
 namespace hqr {
 
-
-
-
 // Rows a variant holds (NT threads x QM rows) bound m; n * nrhs must fit the
 // V area for the back-substitution.
 template <int NT, int QM>
@@ -418,19 +415,21 @@ HQR_DEV void wg_panel_t(int nrows, int pw, WgShared<NT, QM> &sh)
         }
         __syncthreads();
     }
+    // right-looking: once T[i][l] is final it is added into the sums of all
+    // later columns (the same terms in the same order as summing each column
+    // over l = i .. k-1 in turn, with the sums no longer one long chain)
     double trow[WG_P];
 #pragma unroll
     for (int j = 0; j < WG_P; ++j) trow[j] = 0.0;
     if (tid < WG_P) {
+        double acc[WG_P];
 #pragma unroll
-        for (int k = 0; k < WG_P; ++k) {
-            if (k < pw) {
-                double acc = 0.0;
+        for (int k = 0; k < WG_P; ++k) acc[k] = 0.0;
 #pragma unroll
-                for (int l = 0; l < k; ++l) acc = fma(trow[l], sh.t[l * WG_LD + k], acc);
-                if (tid < k) trow[k] = -tau[k] * acc;
-                if (tid == k) trow[k] = tau[k];
-            }
+        for (int l = 0; l < WG_P; ++l) {
+            trow[l] = (l >= pw || tid > l) ? 0.0 : ((tid == l) ? tau[l] : -tau[l] * acc[l]);
+#pragma unroll
+            for (int k = l + 1; k < WG_P; ++k) acc[k] = fma(trow[l], sh.t[l * WG_LD + k], acc[k]);
         }
     }
     __syncthreads();
@@ -746,9 +745,13 @@ __device__ __noinline__ void wg_resnorm(const WgDesc &d)
 }
 
 // R X = B[0:n]: info = smallest k+1 with R[k][k] == 0 (B untouched), else X
-// in B[0:n].  X staged column-major in the V area.
+// in B[0:n].  X staged column-major in the V area.  Block rows of 16 from the
+// bottom: wave 0 solves the diagonal block (lane 16 cg + i: row i, right-hand
+// side cg of each group of four; x_l broadcast by DPP, with 1/R_ll formed
+// before the sequential steps), then every thread updates its rows above
+// (all of a row's reads issued together, no branch per entry).
 template <int NT, int QM>
-__device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
+HQR_DEV void wg_backsolve(const WgDesc &d, int *info, WgShared<NT, QM> &sh)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t n = d.n, nrhs = d.nrhs;
@@ -778,6 +781,10 @@ __device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<N
             double rrow[WG_P];
 #pragma unroll
             for (int l = 0; l < WG_P; ++l) rrow[l] = (i < bw && l < bw) ? d.A[(size_t)(b0 + l) * d.lda + b0 + i] : 1.0;
+            double dii = 1.0;
+#pragma unroll
+            for (int l = 0; l < WG_P; ++l) dii = (l == i) ? rrow[l] : dii;
+            const double rinv = 1.0 / dii;   // lane i's 1/R_ii (nonzero: checked above)
             for (int64_t cs = 0; cs < nrhs; cs += 4) {
                 const int64_t c = cs + cg;
                 const bool ok = (i < bw) && (c < nrhs);
@@ -785,10 +792,9 @@ __device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<N
 #pragma unroll
                 for (int l = WG_P - 1; l >= 0; --l) {
                     if (l < bw) {
-                        const double cand = xi / rrow[l];
+                        const double cand = xi * rinv;
                         const double xl = row_bcast16(cand, l);     // lane l of this 16-lane row
-                        if (i == l) xi = xl;
-                        else if (i < l) xi = fma(-rrow[l], xl, xi);
+                        xi = (i == l) ? xl : ((i < l) ? fma(-rrow[l], xl, xi) : xi);
                     }
                 }
                 if (ok) xs[c * n + b0 + i] = xi;
@@ -803,9 +809,12 @@ __device__ __noinline__ void wg_backsolve(const WgDesc &d, int *info, WgShared<N
                 double acc = xs[c * n + i];
                 // only the block's bw solved rows: past them the staging area
                 // holds other columns' values or stale LDS, and 0 * NaN = NaN
+                // (row b0 is read there instead and its value replaced by 0)
+                double xv[WG_P];
 #pragma unroll
-                for (int l = 0; l < WG_P; ++l)
-                    if (l < bw) acc = fma(-rv[l], xs[c * n + b0 + l], acc);
+                for (int l = 0; l < WG_P; ++l) xv[l] = xs[c * n + b0 + ((l < bw) ? l : 0)];
+#pragma unroll
+                for (int l = 0; l < WG_P; ++l) acc = fma(-rv[l], (l < bw) ? xv[l] : 0.0, acc);
                 xs[c * n + i] = acc;
             }
         }
