@@ -316,50 +316,6 @@ __global__ void __launch_bounds__(256, 2) vtx_kernel(VtxArgs p)
 }
 
 
-__global__ void __launch_bounds__(256) tfactor_kernel(TArgs p)
-{
-    __shared__ double G[NB][NB + 1];
-    __shared__ double Ts[NB][NB + 1];
-    __shared__ double tau[NB];
-    __shared__ double tmp[NB];
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx / NB, j = idx - i * NB;
-        double s = 0.0;
-        if (i < p.bw && j < p.bw) {
-#pragma unroll 8
-            for (int q = 0; q < p.nsplit; ++q) s += p.wpart[(size_t)q * NB * p.nxpad + (size_t)i * p.nxpad + j];
-        }
-        G[i][j] = s;
-        Ts[i][j] = 0.0;
-    }
-    if (tid < NB) {
-        double t = 0.0;
-        if (tid < p.bw) {
-            const double u = p.up[p.c0 + tid];
-            const double rkk = HQR_AT(p.A, (int64_t)p.c0 + tid, p.c0 + tid, p.lda);
-            t = (u == 0.0) ? 0.0 : -1.0 / (u * rkk);
-        }
-        tau[tid] = t;
-    }
-    __syncthreads();
-    for (int j = 0; j < p.bw; ++j) {
-        // tmp[i] = sum_{l=i}^{j-1} T[i][l] G[l][j], i < j
-        if (tid < j) {
-            double s = 0.0;
-            for (int l = tid; l < j; ++l) s += Ts[tid][l] * G[l][j];
-            tmp[tid] = s;
-        }
-        __syncthreads();
-        if (tid < j) Ts[tid][j] = -tau[j] * tmp[tid];
-        if (tid == j) Ts[j][j] = tau[j];
-        __syncthreads();
-    }
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-        const int i = idx / NB, j = idx - i * NB;
-        p.T[idx] = Ts[i][j];
-    }
-}
 
 
 

@@ -1334,4 +1334,68 @@ __global__ void __launch_bounds__(256) xw_reduce_kernel(XwArgs p)
     if (tid < 64) p.Wt[e] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
 }
 
+// T of a stored panel (compact WY, T upper, Q_panel^T = I + V T^T V^T with
+// T[k][k] = tau_k = -1/b_k) from G = V^T V, the splits' partial sums of the
+// V^T X pass.  T^{-1} = diag(1/tau) + the strict upper triangle of G, so T
+// is the inverse of that upper triangular matrix: its four 16 x 16 diagonal
+// blocks by the column recurrence T[i][k] = -tau_k sum_{l=i}^{k-1} T[i][l]
+// G[l][k] (one wave each, lane i < 16 keeping row i and adding T[i][l]
+// G[l][k] into every later column's sum once T[i][l] is final), then the
+// blocks above them by distance from the diagonal on MFMA
+// (inv_upper_levels).  Zero taus (identity reflectors, columns past bw) give
+// zero rows and columns.  One workgroup of 256 threads.
+__global__ void __launch_bounds__(256) tfactor_kernel(TArgs p)
+{
+    __shared__ double G[NB][LD65];
+    __shared__ double Ts[NB][LD65];
+    __shared__ double tau[NB];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // G = the splits' partial V^T V summed in split order; a thread's 16
+    // elements are loaded together for each split
+    constexpr int EPT = NB * NB / 256;
+    double gs[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) gs[e] = 0.0;
+#pragma unroll 4
+    for (int q = 0; q < p.nsplit; ++q) {
+        const double *src = p.wpart + (size_t)q * NB * p.nxpad;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int idx = tid + 256 * e, i = idx / NB, j = idx - i * NB;
+            gs[e] += (i < p.bw && j < p.bw) ? src[(size_t)i * p.nxpad + j] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + 256 * e;
+        G[idx / NB][idx % NB] = gs[e];
+    }
+    if (tid < NB) {
+        double t = 0.0;
+        if (tid < p.bw) {
+            const double u = p.up[p.c0 + tid];
+            const double rkk = HQR_AT(p.A, (int64_t)p.c0 + tid, p.c0 + tid, p.lda);
+            t = (u == 0.0) ? 0.0 : -1.0 / (u * rkk);
+        }
+        tau[tid] = t;
+    }
+    __syncthreads();
+    if (lane < 16) {
+        const int b0 = 16 * w, i = lane;
+        double acc[16], trow[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+#pragma unroll
+        for (int l = 0; l < 16; ++l) {
+            trow[l] = (i > l) ? 0.0 : ((i == l) ? tau[b0 + l] : -tau[b0 + l] * acc[l]);
+#pragma unroll
+            for (int k = l + 1; k < 16; ++k) acc[k] = fma(trow[l], G[b0 + l][b0 + k], acc[k]);
+        }
+#pragma unroll
+        for (int l = 0; l < 16; ++l) Ts[b0 + i][b0 + l] = trow[l];
+    }
+    inv_upper_levels(Ts, G, lane, w);
+    for (int idx = tid; idx < NB * NB; idx += 256) p.T[idx] = Ts[idx / NB][idx % NB];
+}
+
 } // namespace hqr

@@ -1,5 +1,5 @@
 // k_blocked.hip -- launch functions of the blocked-path kernels
-// (hqr_blocked.hpp): panel columns, V^T X, T, W', the trailing update, the
+// (hqr_blocked.hpp): panel columns, V^T X, W', the trailing update, the
 // triangular solve, residual norms and the refinement kernels.
 #include "hqr_blocked.hpp"
 
@@ -22,12 +22,6 @@ hipError_t k_vtx(bool f32, bool with_v, dim3 grid, hipStream_t s, const VtxArgs 
         if (f32) HQR_LAUNCH(K_VTX, (vtx_kernel<true, false>), grid, dim3(256), 0, s, a);
         else HQR_LAUNCH(K_VTX, (vtx_kernel<false, false>), grid, dim3(256), 0, s, a);
     }
-    return hipGetLastError();
-}
-
-hipError_t k_tfactor(hipStream_t s, const TArgs &a)
-{
-    HQR_LAUNCH(K_TFACTOR, tfactor_kernel, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

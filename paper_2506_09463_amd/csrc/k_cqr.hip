@@ -1,5 +1,6 @@
 // k_cqr.hip -- launch functions of the CholeskyQR2 + reconstruction panel
-// kernels and the look-ahead chain (hqr_cqr.hpp).
+// kernels, the look-ahead chain and the T factor of stored panels
+// (hqr_cqr.hpp).
 #include "hqr_cqr.hpp"
 
 namespace hqr {
@@ -37,6 +38,12 @@ hipError_t k_cqr_finish(dim3 grid, hipStream_t s, const FinArgs &a)
 hipError_t k_narrow_vtx(dim3 grid, hipStream_t s, const NarrowArgs &a)
 {
     HQR_LAUNCH(K_NVTX, narrow_vtx_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t k_tfactor(hipStream_t s, const TArgs &a)
+{
+    HQR_LAUNCH(K_TFACTOR, tfactor_kernel, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
