@@ -42,12 +42,12 @@ PEAK_HBM_GBS = 8000.0
 # launches (update: the 64-column launch for panel p+2 and the bulk launch;
 # gram_reduce: the two Gram reductions and the X/W reduction).
 HBM_TRAFFIC = {
-    "csrc_sha256": "06ec85777ecb3d70ade89ed7cb0c3e0725662b8f0beccd79695f122553a0ebea",
-    "per_launch_bytes": {"update": [73644228, 55162566], "vtx": [130921716, 15503360],
-                         "wsolve": [15226401, 1001984], "trsv": [68727565, 34816],
-                         "cqr_gram1": [6731388, 6294032], "cqr_gram2": [3531683, 3194880],
-                         "cqr_chol": [197504, 82176], "cqr_finish": [2447283, 2097152],
-                         "narrow_vtx": [6770774, 6324224], "gram_reduce": [3307074, 32779]},
+    "csrc_sha256": "c725ee6826a87fec846cd33d0304854e56f93cf74db376c7094df2fb6128155b",
+    "per_launch_bytes": {"update": [73636358, 55158860], "vtx": [130921881, 15503360],
+                         "wsolve": [15226383, 1001984], "trsv": [68737982, 34816],
+                         "cqr_gram1": [6731188, 6294032], "cqr_gram2": [3524509, 3194880],
+                         "cqr_chol": [198140, 82176], "cqr_finish": [2447280, 2097152],
+                         "narrow_vtx": [6770737, 6324224], "gram_reduce": [3307070, 32779]},
 }
 
 
