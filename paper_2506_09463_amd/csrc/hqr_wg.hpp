@@ -6,11 +6,11 @@
 //   * panel: the panel's rows are spread over the threads (thread t owns
 //     rows c0 + t + NT*q) and kept in registers.  For column k one block
 //     reduction gives, from each thread's own rows below the pivot,
-//     s_j = sum_r A[r][j] A[r][k] for all 16 panel columns j: j = k is the
-//     tail's squared norm, j > k the dots the reflector's application needs,
-//     j < k the dots v_j^T v_k of the compact-WY T factor.  Every thread then
-//     forms the same s = -sgn(x0)||x||, up = x0 - s, b = up s and updates its
-//     own rows, so one barrier per column suffices;
+//     s_j = sum_r A[r][j] A[r][k] for the panel columns j >= k: j = k is the
+//     tail's squared norm, j > k the dots the reflector's application needs.
+//     Every thread then forms the same s = -sgn(x0)||x||, up = x0 - s,
+//     b = up s and updates its own rows, so one barrier per column suffices;
+//     the compact-WY T of the panel follows from V^T V once it is factored;
 //   * trailing update (and Q^T B, B's columns riding as trailing columns):
 //     Q_panel^T C = C - V T^T (V^T C) on FP64 MFMA, V and T staged in LDS,
 //     every wave owning whole 16-column tiles (no cross-wave reduction).
