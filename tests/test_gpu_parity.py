@@ -369,6 +369,44 @@ def test_apply_q_matches_oracle(hqr, oracle_mod, m, n, nrhs):
     assert np.abs(to_host(dB) - B).max() <= 100 * m * U * max(1.0, np.abs(B).max())
 
 
+@pytest.mark.parametrize("m,n,nrhs,zero_first", [(2600, 1100, 3, False), (1500, 700, 2, True)])
+def test_stored_factor_t_blocks(hqr, oracle_mod, m, n, nrhs, zero_first):
+    """Q^T B and Q B with a stored blocked factor, where every panel's T is
+    rebuilt from V^T V as the inverse of diag(1/tau) + the strict upper
+    triangle of V^T V (16 x 16 diagonal blocks, then the blocks above them):
+    18 and 11 panels with a ragged last one; with zero_first column 0's tail
+    is exactly zero, so its reflector is the identity (up_0 == 0, tau_0 == 0).
+    Against the oracle's application of the same stored reflectors."""
+    import torch
+    rng = np.random.default_rng(300 + m)
+    A = rng.standard_normal((m, n))
+    if zero_first:
+        A[1:, 0] = 0.0
+    A = np.asfortranarray(A)
+    B = np.asfortranarray(rng.standard_normal((m, nrhs)))
+    _say("stored-factor T blocks", (m, n, nrhs, zero_first))
+    dA = to_dev(A)
+    up, info = hqr.qr_factor(dA)
+    torch.cuda.synchronize()
+    F, upn = to_host(dA), to_host(up)[:n]
+    if zero_first:
+        assert upn[0] == 0.0
+    dB = to_dev(B)
+    hqr.qr_apply_qt(dA, up, dB)
+    torch.cuda.synchronize()
+    QtB = to_host(dB).copy()
+    QtBo = oracle_mod.apply_qt(F, upn, B)
+    assert np.abs(QtB - QtBo).max() <= 50 * m * U * max(1.0, np.abs(B).max())
+    hqr.qr_apply_q(dA, up, dB)
+    torch.cuda.synchronize()
+    assert np.abs(to_host(dB) - B).max() <= 100 * m * U * max(1.0, np.abs(B).max())
+    dB = to_dev(B)
+    hqr.qr_apply_q(dA, up, dB)
+    torch.cuda.synchronize()
+    QBo = oracle_mod.apply_q(F, upn, B)
+    assert np.abs(to_host(dB) - QBo).max() <= 50 * m * U * max(1.0, np.abs(B).max())
+
+
 @pytest.mark.parametrize("m,n,k", [(7, 7, 7), (128, 64, 64), (128, 64, 128), (200, 150, 90), (1000, 333, 333),
                                    (900, 500, 900), (513, 200, 1)])
 def test_form_q_matches_oracle(hqr, oracle_mod, m, n, k):
