@@ -119,9 +119,10 @@ constexpr int UPD_TILE = 128;
 
 // Blocked back-substitution R X = B[0:n].  Row blocks of 64; workgroup b
 // owns row block nblk-1-b, so every block it waits for belongs to a
-// workgroup dispatched before it.  A block is published by writing its x
-// values to B and then raising flags[block] (release); consumers acquire it.
-// The wait is bounded: on expiry the kernel records HQR_INFO_TIMEOUT.
+// workgroup dispatched before it.  A block is published by storing its x
+// values into xpub, whose slots hold the TRSV_EMPTY pattern until then: each
+// value is its own flag, so a consumer's poll is the read of the data.  The
+// wait is bounded: on expiry the kernel records HQR_INFO_TIMEOUT.
 struct TrsvArgs {
     const double *A;
     int64_t lda;
@@ -129,14 +130,19 @@ struct TrsvArgs {
     int64_t ldb;
     int64_t n;
     int nrhs;
-    int *flags;      // [nblk], zero on entry
+    double *xpub;    // [nrhs][n], every slot TRSV_EMPTY on entry
     int *info;       // read: nonzero -> nothing to do; written on timeout
-    int epoch;       // value a published flag holds
     long spin_limit;
     const int *active; // optional: nothing to do when *active == 0
 };
 
 constexpr int TRSV_MAXRHS = 8;
+// A signalling NaN with a nonzero payload, the same 32-bit word twice (so the
+// integer fill writes it).  Arithmetic returns only quiet NaNs, and a value
+// that matched the pattern would be published as the default quiet NaN, so a
+// slot that differs from it holds its block's final value.
+constexpr unsigned long long TRSV_EMPTY = 0x7FF47FF47FF47FF4ull;
+constexpr int TRSV_EMPTY_WORD = 0x7FF47FF4;
 
 // Refinement of least-squares solutions with the semi-normal equations,
 // every right-hand side at once (column c: x = X[0:n, c], original b =

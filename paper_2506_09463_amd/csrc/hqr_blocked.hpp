@@ -621,9 +621,12 @@ __global__ void __launch_bounds__(256) diag_check_kernel(const double *A, int64_
 // other blocks is loaded before the first wait: the diagonal block (with the
 // reciprocals of its diagonal), the block's right-hand sides, and each
 // off-diagonal block of R one iteration ahead, in registers.  The remaining
-// critical path per block is: observe the predecessor's flag, read its x,
-// one 64 x 64 block product, a 64-step substitution with multiplies by the
-// precomputed reciprocals, publish.  NR: right-hand sides handled per pass
+// critical path per block is: poll the predecessor's x values until none
+// holds TRSV_EMPTY (one read of memory shared by all XCDs, no separate flag
+// and no cache invalidation), one 64 x 64 block product, a 64-step
+// substitution with multiplies by the precomputed reciprocals, and the
+// stores that publish the result (no release fence: no other data rides on
+// them).  NR: right-hand sides handled per pass
 // (1, or TRSV_MAXRHS for 2..8).
 template <bool TRANS, int NR>
 __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
@@ -676,25 +679,26 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
     for (int jj = 0; jj < npred; ++jj) {
         const int jb = TRANS ? jj : nblk - 1 - jj;
         if (jj + 1 < npred) fetch(jj + 1, rn);
-        if (tid == 0) {
-            long s = 0;
-            while (__hip_atomic_load(&p.flags[jb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != p.epoch) {
-                if (++s > p.spin_limit) {
-                    bad = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __syncthreads();
-        if (bad) break;
         const int64_t c0 = (int64_t)jb * 64;
         const int nc = (int)min<int64_t>(64, p.n - c0);
         for (int idx = tid; idx < 64 * NR; idx += 256) {
             const int r = idx / NR, c = idx - r * NR;
-            xs[r][c] = (r < nc && c < nrhs) ? __hip_atomic_load(&p.B[(size_t)(c0 + r) + (size_t)c * p.ldb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+            unsigned long long u = 0;   // the bits of +0.0
+            if (r < nc && c < nrhs) {
+                unsigned long long *slot = (unsigned long long *)(p.xpub + (size_t)c * p.n + (size_t)(c0 + r));
+                long spins = 0;
+                while ((u = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == TRSV_EMPTY) {
+                    if (++spins > p.spin_limit) {
+                        bad = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            xs[r][c] = __longlong_as_double((long long)u);
         }
         __syncthreads();
+        if (bad) break;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int l = g + 4 * q;
@@ -744,16 +748,16 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
                     }
                 }
             }
-            accs[lane][c] = t;
+            if (lane < nr) {
+                // publish first (the successors wait on it), then the result
+                unsigned long long u = (unsigned long long)__double_as_longlong(t);
+                if (u == TRSV_EMPTY) u = 0x7FF8000000000000ull;
+                __hip_atomic_store((unsigned long long *)(p.xpub + (size_t)c * p.n + (size_t)(r0 + lane)), u,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                p.B[(size_t)(r0 + lane) + (size_t)c * p.ldb] = t;
+            }
         }
     }
-    __syncthreads();
-    for (int idx = tid; idx < nr * nrhs; idx += 256) {
-        const int c = idx / nr, r = idx - c * nr;
-        __hip_atomic_store(&p.B[(size_t)(r0 + r) + (size_t)c * p.ldb], accs[r][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&p.flags[ib], p.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // resnorm[c] = ||B[n:m, c]||, one workgroup per column.

@@ -230,7 +230,7 @@ static bool tsqr_geometry(int64_t mp, int bw, TsqrGeom &g)
 struct Work {
     double *xbuf, *pbuf, *wpart, *T, *wp;
     double *wpart2, *T2, *wp2;            // second set for the look-ahead stream
-    int *flags;
+    double *xpub;                            // back-substitution: published x, [TRSV_MAXRHS][n]
     int *iscratch;
     double *gpart, *r1, *r1inv, *winv, *q1top;
     double *G, *xn;                          // reduced Gram; W = T^T V^T C of the look-ahead (transposed)
@@ -265,7 +265,7 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
     char *wpart2 = take(sizeof(double) * (size_t)p.nsplit_max * NB * p.nxpad);
     char *T2 = take(sizeof(double) * NB * NB);
     char *wp2 = take(sizeof(double) * NB * (size_t)p.nxpad);
-    char *fl = take(sizeof(int) * (size_t)std::max(p.nblk, 1));
+    char *fl = take(sizeof(double) * TRSV_MAXRHS * (size_t)std::max<int64_t>(p.n, 1));
     char *is = take(sizeof(int) * 64);
     char *gp = take(sizeof(double) * (size_t)p.ngroups * NB * NB);
     char *r1 = take(sizeof(double) * NB * NB);
@@ -336,7 +336,7 @@ static size_t work_bytes(const Plan &p, Work *w, char *base)
         w->wpart2 = (double *)wpart2;
         w->T2 = (double *)T2;
         w->wp2 = (double *)wp2;
-        w->flags = (int *)fl;
+        w->xpub = (double *)fl;
         w->iscratch = (int *)is;
     }
     return off;
@@ -888,7 +888,6 @@ static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int
 {
     HQR_CK(k_diag_check(s, A, lda, pl.n, info));
     for (int c = 0; c < nrhs; c += TRSV_MAXRHS) {
-        HQR_CK(k_fill_int(s, w.flags, 0, (int64_t)pl.nblk));
         TrsvArgs t;
         t.A = A;
         t.lda = lda;
@@ -896,9 +895,9 @@ static int backsolve_blocked(const Plan &pl, const Work &w, const double *A, int
         t.ldb = ldb;
         t.n = pl.n;
         t.nrhs = std::min(TRSV_MAXRHS, nrhs - c);
-        t.flags = w.flags;
+        HQR_CK(k_fill_int(s, (int *)w.xpub, TRSV_EMPTY_WORD, 2 * pl.n * (int64_t)t.nrhs));
+        t.xpub = w.xpub;
         t.info = info;
-        t.epoch = 1;
         t.spin_limit = 20000000L;
         t.active = active;
         HQR_CK(k_trsv(trans, t.nrhs, dim3(pl.nblk), s, t));

@@ -70,7 +70,10 @@ hipError_t k_resnorm(dim3 grid, hipStream_t s, const double *B, int64_t ldb, int
 
 hipError_t k_fill_int(hipStream_t s, int *p, int v, int64_t count)
 {
-    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(1), dim3(256), 0, s, p, v, count);
+    // one workgroup for the small fills, up to 64 for the back-substitution's
+    // published-value buffer (up to 8 x n doubles)
+    const int grid = (int)std::min<int64_t>(64, std::max<int64_t>(1, (count + 4095) / 4096));
+    HQR_LAUNCH(K_FILL, fill_int_kernel, dim3(grid), dim3(256), 0, s, p, v, count);
     return hipGetLastError();
 }
 
