@@ -42,12 +42,12 @@ PEAK_HBM_GBS = 8000.0
 # launches (update: the 64-column launch for panel p+2 and the bulk launch;
 # gram_reduce: the two Gram reductions and the X/W reduction).
 HBM_TRAFFIC = {
-    "csrc_sha256": "c725ee6826a87fec846cd33d0304854e56f93cf74db376c7094df2fb6128155b",
-    "per_launch_bytes": {"update": [73636358, 55158860], "vtx": [130921881, 15503360],
-                         "wsolve": [15226383, 1001984], "trsv": [68737982, 34816],
-                         "cqr_gram1": [6731188, 6294032], "cqr_gram2": [3524509, 3194880],
-                         "cqr_chol": [198140, 82176], "cqr_finish": [2447280, 2097152],
-                         "narrow_vtx": [6770737, 6324224], "gram_reduce": [3307070, 32779]},
+    "csrc_sha256": "d9ee8ee0f65138e6178716b064b881f63ba18d9e9abdeeb0cee546470f19f577",
+    "per_launch_bytes": {"update": [73634536, 55160430], "vtx": [130922570, 15503360],
+                         "wsolve": [15226388, 1001984], "trsv": [68966220, 65536],
+                         "cqr_gram1": [6731191, 6294032], "cqr_gram2": [3524510, 3194880],
+                         "cqr_chol": [198140, 82176], "cqr_finish": [2447281, 2097152],
+                         "narrow_vtx": [6770739, 6324224], "gram_reduce": [3307071, 32779]},
 }
 
 
@@ -58,7 +58,7 @@ C2_KERNEL_SOURCES = ("hqr_args.hpp", "hqr_device.hpp", "hqr_blocked.hpp", "hqr_c
 # two counters and scaling; valid for the one-workgroup kernel's sources, the
 # tuning database (which picks the variant) and the batch recipe hashed here.
 BATCHED_TRAFFIC = {
-    "sha256": "a4de1b8f6241e26ddb0b9706658bae20383246d2d79d2dcfded115d17288c63f",
+    "sha256": "28e71dc2dff17136784fa7f16f4cd614d23f174b3782add429ad80007ba199ad",
     "bytes": [41010364032, 22412739968],
 }
 BATCHED_SOURCES = ("csrc/hqr_args.hpp", "csrc/hqr_device.hpp", "csrc/hqr_wg.hpp", "csrc/k_wg.hip", "tune_db.json",
