@@ -626,8 +626,8 @@ __global__ void __launch_bounds__(256) diag_check_kernel(const double *A, int64_
 // and no cache invalidation), one 64 x 64 block product, a 64-step
 // substitution with multiplies by the precomputed reciprocals, and the
 // stores that publish the result (no release fence: no other data rides on
-// them).  NR: right-hand sides handled per pass
-// (1, or TRSV_MAXRHS for 2..8).
+// them).  NR: right-hand sides handled per pass (1, or TRSV_MAXRHS for
+// 2..8); the four waves take the right-hand sides' substitutions in turn.
 template <bool TRANS, int NR>
 __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
 {
@@ -716,35 +716,44 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
 #pragma unroll
     for (int c = 0; c < NR; ++c) part[g][lane][c] = acc[c];
     __syncthreads();
-    if (g == 0) {
+    if (g < nrhs && g < NR) {
         // the substitution runs fully unrolled on registers: lane l holds its
         // row (column when TRANS) of the diagonal block and 1/R_ll, so a step
         // is two lane reads, a multiply and an FMA (no LDS access on the
-        // dependency chain)
+        // dependency chain).  Wave g solves right-hand sides g, g + 4.
         double rowv[64];
 #pragma unroll
         for (int i = 0; i < 64; ++i) rowv[i] = TRANS ? Rd[i][lane] : Rd[lane][i];
         const double rl = (lane < nr) ? rinv[lane] : 0.0;
-        for (int c = 0; c < nrhs && c < NR; ++c) {
+        for (int c = g; c < nrhs && c < NR; c += 4) {
+            // fresh copies per right-hand side, so that the 64 steps' lane
+            // masks and lane reads are not hoisted out of this loop into
+            // hundreds of SGPRs (which spill to VGPR lanes and are read back
+            // at every step)
+            double rlc = rl;
+            pin_f64(rlc);
+            int lc = lane, nrc = nr;
+            asm volatile("" : "+v"(lc));
+            asm volatile("" : "+s"(nrc));
             double t = 0.0;
             if (lane < nr)
                 t = accs[lane][c] - (((part[0][lane][c] + part[1][lane][c]) + part[2][lane][c]) + part[3][lane][c]);
             if (TRANS) {
 #pragma unroll
                 for (int i = 0; i < 64; ++i) {
-                    if (i < nr) {
-                        const double xi = readlane_f64(t, i) * readlane_f64(rl, i);
-                        if (lane > i && lane < nr) t = fma(-rowv[i], xi, t);
-                        if (lane == i) t = xi;
+                    if (i < nrc) {
+                        const double xi = readlane_f64(t, i) * readlane_f64(rlc, i);
+                        if (lc > i && lc < nrc) t = fma(-rowv[i], xi, t);
+                        if (lc == i) t = xi;
                     }
                 }
             } else {
 #pragma unroll
                 for (int i = 63; i >= 0; --i) {
-                    if (i < nr) {
-                        const double xi = readlane_f64(t, i) * readlane_f64(rl, i);
-                        if (lane < i) t = fma(-rowv[i], xi, t);
-                        if (lane == i) t = xi;
+                    if (i < nrc) {
+                        const double xi = readlane_f64(t, i) * readlane_f64(rlc, i);
+                        if (lc < i) t = fma(-rowv[i], xi, t);
+                        if (lc == i) t = xi;
                     }
                 }
             }

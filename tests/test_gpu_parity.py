@@ -129,6 +129,66 @@ def test_factor_apply_backsolve_split(hqr, oracle_mod, m, n, nrhs, seed):
         assert np.linalg.norm(X[:, c] - Xo[:, c]) / np.linalg.norm(Xo[:, c]) <= 2 * lsq_forward_bound(A, Xo[:, c], r)
 
 
+def _dominant_upper(rng, n):
+    """Upper triangle with |R_ii| = n + U(0,1) against N(0,1) entries above:
+    strictly diagonally dominant by rows, so kappa(R) stays near 1 at any n."""
+    R = np.triu(rng.standard_normal((n, n)))
+    np.fill_diagonal(R, (n + rng.random(n)) * np.where(rng.random(n) < 0.5, -1.0, 1.0))
+    return np.asfortranarray(R)
+
+
+@pytest.mark.parametrize("n,nrhs,seed", [(1, 1, 61), (64, 3, 62), (65, 8, 63), (1000, 11, 64), (4133, 1, 65),
+                                         (4133, 9, 66)])
+def test_backsolve_blocks_and_chunks(hqr, oracle_mod, n, nrhs, seed):
+    """qr_backsolve (the multi-workgroup TRSV: 64-row blocks that wait on the
+    values their predecessors publish; more than 8 right-hand sides take two
+    launches over the same published-value buffer) against the oracle's
+    substitution: max |x - x_o| <= 50 n u max |x_o| per column (kappa ~ 1)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    R = _dominant_upper(rng, n)
+    B = np.asfortranarray(rng.standard_normal((n + 5, nrhs)))
+    _say("qr_backsolve", (n, nrhs, seed))
+    dR, dB = to_dev(R), to_dev(B)
+    _, info = hqr.qr_backsolve(dR, dB)
+    torch.cuda.synchronize()
+    X = to_host(dB)
+    Xo, info_o = oracle_mod.backsolve(R, B)
+    assert int(info.item()) == 0 and info_o == 0
+    for c in range(nrhs):
+        assert np.abs(X[:n, c] - Xo[:, c]).max() <= 50 * n * U * np.abs(Xo[:, c]).max()
+    assert np.array_equal(X[n:], B[n:])   # rows below n untouched
+
+
+def test_backsolve_nonfinite_rhs(hqr, oracle_mod):
+    """NaN, +Inf and the signalling-NaN pattern the TRSV's published-value
+    slots hold before they are written, each in one right-hand side: the wait
+    ends (info 0, no timeout), the non-finite rows are those of the oracle's
+    substitution, and the finite rows agree with it."""
+    import torch
+    rng = np.random.default_rng(67)
+    n = 1000
+    R = _dominant_upper(rng, n)
+    B = np.asfortranarray(rng.standard_normal((n, 4)))
+    B[700, 0] = np.nan
+    B[999, 1] = np.inf
+    B[300, 2] = np.array([0x7FF47FF47FF47FF4], dtype=np.uint64).view(np.float64)[0]
+    _say("qr_backsolve nonfinite", (n, 4))
+    dR, dB = to_dev(R), to_dev(B)
+    _, info = hqr.qr_backsolve(dR, dB)
+    torch.cuda.synchronize()
+    X = to_host(dB)
+    Xo, _ = oracle_mod.backsolve(R, B)
+    assert int(info.item()) == 0
+    fin = np.isfinite(Xo)
+    assert np.array_equal(np.isfinite(X), fin)
+    assert not fin[:701, 0].any() and fin[701:, 0].all()
+    assert not fin[:, 1].any()
+    assert not fin[:301, 2].any() and fin[301:, 2].all()
+    assert fin[:, 3].all()
+    assert np.abs(X[fin] - Xo[fin]).max() <= 50 * n * U * np.abs(Xo[fin]).max()
+
+
 @pytest.mark.parametrize("m,n", [(128, 64), (700, 300)])
 def test_deterministic(hqr, m, n):
     """Same input, same launch configuration: bitwise identical results."""
