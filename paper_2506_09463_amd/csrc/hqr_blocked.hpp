@@ -808,27 +808,90 @@ __global__ void __launch_bounds__(256) resnorm_kernel(const double *B, int64_t l
 }
 
 // ------------------------------------------------------------ refinement
-// r = b - A0 x for column blockIdx.y (FP64), one thread per row; x staged in
-// LDS in chunks.  Skipped for frozen columns unless `all`.
+// r = b - A0 x (FP64) for RESID_ROWS rows (blockIdx.x) and up to RESID_NR
+// right-hand sides (blockIdx.y), so A0 is streamed once per RESID_NR columns
+// of x.  Lane l of wave w takes row l % 32 and lane group k = 2w + l / 32,
+// which owns columns [64k, 64k + 64) of each 512-column chunk of x (staged in
+// LDS): a load instruction reads two 256-byte column segments, and every lane
+// keeps 16 loads in flight with two partial sums per right-hand side.  The
+// eight groups' sums are combined in a fixed order (deterministic).  Columns
+// that are frozen are skipped unless `all`.
+constexpr int RESID_ROWS = 32, RESID_NR = 4, RESID_CHUNK = 512, RESID_UNROLL = 16;
 __global__ void __launch_bounds__(256) resid_kernel(RefineArgs a, int all)
 {
-    __shared__ double xs[1024];
-    const int c = blockIdx.y;
-    if (!all && (*((volatile int *)a.active) == 0 || a.stat[4 * c + 3])) return;
-    const double *x = a.X + (size_t)c * a.ldx;
-    const double *b = a.borig + (size_t)c * a.m;
-    double *r = a.rvec + (size_t)c * a.m;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double s = 0.0;
-    for (int64_t j0 = 0; j0 < a.n; j0 += 1024) {
-        const int64_t nj = min<int64_t>(1024, a.n - j0);
+    __shared__ double xs[RESID_CHUNK][RESID_NR];
+    __shared__ double red[8][RESID_ROWS][RESID_NR];
+    const int tid = threadIdx.x, lane = tid & 63, row = lane & 31, grp = 2 * (tid >> 6) + (lane >> 5);
+    if (!all && *((volatile int *)a.active) == 0) return;
+    const int c0 = (int)blockIdx.y * RESID_NR;
+    int act = 0;   // bit c: right-hand side c0 + c is computed
+#pragma unroll
+    for (int c = 0; c < RESID_NR; ++c)
+        if (c0 + c < a.nrhs && (all || a.stat[4 * (c0 + c) + 3] == 0)) act |= 1 << c;
+    if (act == 0) return;
+    const int64_t i = (int64_t)blockIdx.x * RESID_ROWS + row;
+    const bool rok = i < a.m;
+    const double *arow = a.A0 + (rok ? i : 0);   // rows past m read row 0; discarded
+    double s0[RESID_NR], s1[RESID_NR];
+#pragma unroll
+    for (int c = 0; c < RESID_NR; ++c) s0[c] = s1[c] = 0.0;
+    for (int64_t j0 = 0; j0 < a.n; j0 += RESID_CHUNK) {
+        const int nj = (int)min<int64_t>(RESID_CHUNK, a.n - j0);
         __syncthreads();
-        for (int64_t j = threadIdx.x; j < nj; j += 256) xs[j] = x[j0 + j];
+        {
+            // all loads first (unconditional, at a clamped address: X[0] when
+            // not needed), then the selects: no wait between the loads
+            constexpr int PER = RESID_CHUNK * RESID_NR / 256;
+            double v[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int idx = tid + 256 * q, j = idx / RESID_NR, c = idx - j * RESID_NR;
+                const bool ok = j < nj && ((act >> c) & 1);
+                v[q] = a.X[ok ? (size_t)(c0 + c) * a.ldx + (size_t)(j0 + j) : 0];
+            }
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int idx = tid + 256 * q, j = idx / RESID_NR, c = idx - j * RESID_NR;
+                const bool ok = j < nj && ((act >> c) & 1);
+                xs[j][c] = ok ? v[q] : 0.0;
+            }
+        }
         __syncthreads();
-        if (i < a.m)
-            for (int64_t j = 0; j < nj; ++j) s += HQR_AT(a.A0, i, j0 + j, a.lda0) * xs[j];
+        const int jb = 64 * grp;
+        const int cnt = max(0, min(64, nj - jb));   // uniform over the 32-lane group
+        const double *ap = arow + (size_t)(j0 + jb) * a.lda0;
+        int jj = 0;
+        for (; jj + RESID_UNROLL <= cnt; jj += RESID_UNROLL) {
+            double av[RESID_UNROLL];
+#pragma unroll
+            for (int u = 0; u < RESID_UNROLL; ++u) av[u] = ap[(size_t)(jj + u) * a.lda0];
+#pragma unroll
+            for (int u = 0; u < RESID_UNROLL; u += 2) {
+#pragma unroll
+                for (int c = 0; c < RESID_NR; ++c) {
+                    s0[c] = fma(av[u], xs[jb + jj + u][c], s0[c]);
+                    s1[c] = fma(av[u + 1], xs[jb + jj + u + 1][c], s1[c]);
+                }
+            }
+        }
+        for (; jj < cnt; ++jj) {
+            const double av = ap[(size_t)jj * a.lda0];
+#pragma unroll
+            for (int c = 0; c < RESID_NR; ++c) s0[c] = fma(av, xs[jb + jj][c], s0[c]);
+        }
     }
-    if (i < a.m) r[i] = b[i] - s;
+#pragma unroll
+    for (int c = 0; c < RESID_NR; ++c) red[grp][row][c] = s0[c] + s1[c];
+    __syncthreads();
+    if (tid < RESID_ROWS * RESID_NR) {
+        const int r = tid % RESID_ROWS, c = tid / RESID_ROWS;
+        const int64_t ir = (int64_t)blockIdx.x * RESID_ROWS + r;
+        if (ir < a.m && ((act >> c) & 1)) {
+            const double t = ((red[0][r][c] + red[1][r][c]) + (red[2][r][c] + red[3][r][c])) +
+                             ((red[4][r][c] + red[5][r][c]) + (red[6][r][c] + red[7][r][c]));
+            a.rvec[(size_t)(c0 + c) * a.m + ir] = a.borig[(size_t)(c0 + c) * a.m + ir] - t;
+        }
+    }
 }
 
 // g = A0^T r for column blockIdx.y (FP64): one wave per column of A0, lanes

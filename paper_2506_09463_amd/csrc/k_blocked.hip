@@ -98,7 +98,7 @@ hipError_t k_refine_init(hipStream_t s, const RefineArgs &a)
 
 hipError_t k_resid(bool all, hipStream_t s, const RefineArgs &a)
 {
-    const dim3 g((unsigned)((a.m + 255) / 256), (unsigned)a.nrhs);
+    const dim3 g((unsigned)((a.m + RESID_ROWS - 1) / RESID_ROWS), (unsigned)((a.nrhs + RESID_NR - 1) / RESID_NR));
     HQR_LAUNCH(K_REFINE, resid_kernel, g, dim3(256), 0, s, a, all ? 1 : 0);
     return hipGetLastError();
 }
