@@ -42,12 +42,12 @@ PEAK_HBM_GBS = 8000.0
 # launches (update: the 64-column launch for panel p+2 and the bulk launch;
 # gram_reduce: the two Gram reductions and the X/W reduction).
 HBM_TRAFFIC = {
-    "csrc_sha256": "84f5173a00a60deb7a3e6db5434f685bfc5e3cd45ccbac5b12938fca061670b3",
-    "per_launch_bytes": {"update": [73644890, 55163120], "vtx": [130923322, 15503360],
-                         "wsolve": [15226395, 1001984], "trsv": [68956138, 65536],
-                         "cqr_gram1": [6731193, 6294032], "cqr_gram2": [3524558, 3194880],
-                         "cqr_chol": [198159, 82176], "cqr_finish": [2447282, 2097152],
-                         "narrow_vtx": [6770775, 6324224], "gram_reduce": [3307045, 32779]},
+    "csrc_sha256": "3392d76b22262ca54f5994ef7e7e30c2f44f0e31207ed2ef22d547283fa77b92",
+    "per_launch_bytes": {"update": [73626170, 55162797], "vtx": [130921612, 15503360],
+                         "wsolve": [15226388, 1001984], "trsv": [68946381, 65536],
+                         "cqr_gram1": [6731191, 6294032], "cqr_gram2": [3524552, 3194880],
+                         "cqr_chol": [198159, 82176], "cqr_finish": [2447281, 2097152],
+                         "narrow_vtx": [6770772, 6324224], "gram_reduce": [3307043, 32779]},
 }
 
 
