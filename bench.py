@@ -42,12 +42,12 @@ PEAK_HBM_GBS = 8000.0
 # launches (update: the 64-column launch for panel p+2 and the bulk launch;
 # gram_reduce: the two Gram reductions and the X/W reduction).
 HBM_TRAFFIC = {
-    "csrc_sha256": "3392d76b22262ca54f5994ef7e7e30c2f44f0e31207ed2ef22d547283fa77b92",
-    "per_launch_bytes": {"update": [73626170, 55162797], "vtx": [130921612, 15503360],
-                         "wsolve": [15226388, 1001984], "trsv": [68946381, 65536],
-                         "cqr_gram1": [6731191, 6294032], "cqr_gram2": [3524552, 3194880],
-                         "cqr_chol": [198159, 82176], "cqr_finish": [2447281, 2097152],
-                         "narrow_vtx": [6770772, 6324224], "gram_reduce": [3307043, 32779]},
+    "csrc_sha256": "f54c4f5036ab3d3bfd8fc23efb83dd58192a88f2b74df80f766175199e9fccc4",
+    "per_launch_bytes": {"update": [73637700, 55161771], "vtx": [130921559, 15503360],
+                         "wsolve": [15226391, 1001984], "trsv": [68917337, 65536],
+                         "cqr_gram1": [6731192, 6294032], "cqr_gram2": [3524511, 3194880],
+                         "cqr_chol": [198140, 82176], "cqr_finish": [2447281, 2097152],
+                         "narrow_vtx": [6770741, 6324224], "gram_reduce": [3307072, 32779]},
 }
 
 

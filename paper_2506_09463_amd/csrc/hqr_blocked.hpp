@@ -744,7 +744,6 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
                     if (i < nrc) {
                         const double xi = readlane_f64(t, i) * readlane_f64(rlc, i);
                         if (lc > i && lc < nrc) t = fma(-rowv[i], xi, t);
-                        if (lc == i) t = xi;
                     }
                 }
             } else {
@@ -753,10 +752,13 @@ __global__ void __launch_bounds__(256) trsv_kernel(TrsvArgs p)
                     if (i < nrc) {
                         const double xi = readlane_f64(t, i) * readlane_f64(rlc, i);
                         if (lc < i) t = fma(-rowv[i], xi, t);
-                        if (lc == i) t = xi;
                     }
                 }
             }
+            // lane l's value is final once step l has read it, so x_l is the
+            // same product t_l / R_ll (as t_l * rinv) that step l used; taking
+            // it here keeps a select off each step's dependency chain
+            t *= rl;
             if (lane < nr) {
                 // publish first (the successors wait on it), then the result
                 unsigned long long u = (unsigned long long)__double_as_longlong(t);
