@@ -55,6 +55,28 @@ def test_mixed_multiple_rhs(hqr, oracle_mod):
         assert np.linalg.norm(X[:, c] - xref) / np.linalg.norm(xref) <= 1e-10
 
 
+def test_mixed_six_rhs_two_residual_chunks(hqr, oracle_mod):
+    """Six right-hand sides: the refinement's residual kernel takes them in
+    two chunks of up to four, one workgroup row per chunk.  The columns
+    differ in scale (1e-3 .. 1e3) and noise (0 .. 1e-6), so they need
+    different numbers of steps; each must reach 1e-10 of the
+    extended-precision reference, with its residual norm."""
+    m, n = 700, 300
+    A, b, _ = workloads.conditioned(m, n, 1e5, seed=25)
+    rng = np.random.default_rng(26)
+    cols = [b]
+    for scale, noise in ((1e-3, 0.0), (1.0, 1e-12), (1e3, 1e-9), (10.0, 1e-7), (0.1, 1e-6)):
+        cols.append(scale * (A @ rng.standard_normal(n)) + noise * rng.standard_normal(m))
+    B = np.asfortranarray(np.stack(cols, axis=1))
+    print("[case] mixed six rhs", (m, n), flush=True)
+    X, res, info, iters = _mixed(hqr, A, B)
+    assert info == 0 and 1 <= iters <= 10
+    for c in range(B.shape[1]):
+        xref, _ = oracle_mod.lsq_reference(A, B[:, c])
+        assert np.linalg.norm(X[:, c] - xref) / np.linalg.norm(xref) <= 1e-10
+        assert abs(res[c] - np.linalg.norm(B[:, c] - A @ X[:, c])) <= 1e-12 * max(1.0, np.linalg.norm(B[:, c]))
+
+
 @pytest.mark.parametrize("m,n", [(300, 100), (128, 64)])
 def test_mixed_fallback_when_refinement_cannot_converge(hqr, oracle_mod, m, n):
     """With no refinement steps allowed the run cannot converge: the inputs
